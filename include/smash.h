@@ -1,0 +1,172 @@
+/*
+ * smash.h -- C ABI of libsmash, a row-wise (Gustavson) sparse matrix-matrix
+ * multiply C = A * B for AMD Instinct MI355X (gfx950).
+ *
+ * The operation is the row-wise product of the SMASH thesis (arXiv
+ * 2105.14156), Background chapter, eq. "row_wise":
+ *     C[i,:] = sum_k A[i,k] * B[k,:],
+ * i.e. c_ij = sum_k a_ik * b_kj (eq. "inner_product"), with every output
+ * row's partial products merged in an on-chip hash table by atomic
+ * compare-and-swap on keys and atomic add on values (SMASH Kernels chapter,
+ * section "Hashing Phase"; algorithms "SMASH HASHING" even/odd sections).
+ * Output sizing follows the Window Distribution Phase: per-row product
+ * counts from the row pointers, then an exact symbolic count.
+ *
+ * Conventions shared by every entry point
+ * ----------------------------------------
+ * Matrices are CSR with int32 row pointers and int32 column indices, values
+ * FP32 or FP64 (smash_dtype).  All matrix arrays live in device memory and
+ * are owned by the caller; the library never frees caller memory.
+ * Preconditions on A and B: row_ptr[0] = 0, row_ptr nondecreasing,
+ * row_ptr[rows] = nnz, 0 <= col_idx < cols, columns strictly ascending in each
+ * row.  With SMASH_OPT_VALIDATE set (the default) these are checked on the
+ * device and a violation returns SMASH_ERR_INVALID_CSR.
+ * C is returned canonical: int64 row pointer, columns ascending and unique
+ * in each row, and every structural product kept, even where the products
+ * cancel to 0.0.
+ * All work is ordered on the caller's HIP stream.  A context is not
+ * thread-safe: use one context per host thread.
+ * Every function returns a status; nothing aborts or throws across the ABI.
+ * After an error the output buffers hold unspecified values, but nothing
+ * outside them is written.  smash_last_error() returns the message of the
+ * last failing call on the context.
+ */
+#ifndef SMASH_H
+#define SMASH_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SMASH_OK = 0,
+    SMASH_ERR_INVALID_ARG = 1,     /* null pointer, bad shape, bad option */
+    SMASH_ERR_INVALID_CSR = 2,     /* validation found a precondition violated */
+    SMASH_ERR_INDEX_OVERFLOW = 3,  /* a count does not fit the requested index type */
+    SMASH_ERR_CAPACITY = 4,        /* a caller buffer or the C_row_ptr given is too small */
+    SMASH_ERR_OUT_OF_MEMORY = 5,   /* device or pinned host allocation failed */
+    SMASH_ERR_HIP = 6,             /* a HIP runtime call failed */
+    SMASH_ERR_NO_PLAN = 7          /* numeric phase without a matching symbolic phase */
+} smash_status;
+
+typedef enum { SMASH_F32 = 0, SMASH_F64 = 1 } smash_dtype;
+
+/* Opaque per-device context: scratch memory cache, the plan of the last
+ * symbolic call, options and per-kernel timing. */
+typedef struct smash_ctx_s *smash_ctx;
+
+/* A CSR matrix in device memory (see the conventions above).  val may be
+ * NULL for the symbolic phase. */
+typedef struct {
+    int64_t rows, cols, nnz;
+    const int32_t *row_ptr;   /* rows + 1 entries */
+    const int32_t *col_idx;   /* nnz entries */
+    const void *val;          /* nnz entries of the call's dtype */
+} smash_csr;
+
+/* Options (smash_set_option / smash_get_option). */
+typedef enum {
+    /* 1 = check the CSR preconditions of A and B on the device (default 1). */
+    SMASH_OPT_VALIDATE = 0,
+    /* Rows whose output bound min(products, cols) exceeds this many
+     * entries leave the LDS hash path for the heavy-row path.  Range
+     * 32..4096, default 4096. */
+    SMASH_OPT_LDS_ROW_MAX = 1,
+    /* Heavy-row path: 0 = column-windowed LDS accumulation (default),
+     * 1 = global-memory hash table (the fallback of the paper's third
+     * version, "Fragmenting Memory": hash table moved to DRAM). */
+    SMASH_OPT_HEAVY_MODE = 2,
+    /* Column width of one numeric window of the windowed heavy path, in
+     * units of 8192 columns: 1, 2 or 4 (FP64 allows 1 or 2).  Default: 4
+     * for FP32, 2 for FP64 (value 0). */
+    SMASH_OPT_WINDOW_UNITS = 3,
+    /* 1 = record HIP events around every kernel launch and accumulate the
+     * elapsed time per kernel (smash_kernel_time).  Default 0. */
+    SMASH_OPT_TIMING = 4
+} smash_option;
+
+/* Counters of the last symbolic/numeric call (smash_get_stats). */
+typedef struct {
+    int64_t rows;            /* A.rows */
+    int64_t products;        /* sum over rows of the products (multiply-adds) */
+    int64_t nnz_c;           /* nnz(C) */
+    int64_t rows_empty;      /* rows with no product */
+    int64_t rows_lds;        /* rows merged in an LDS hash table */
+    int64_t rows_heavy;      /* rows on the heavy-row path */
+    int64_t heavy_windows;   /* non-empty column windows of heavy rows (windowed mode) */
+    int64_t global_slots;    /* global hash table slots used (global mode) */
+} smash_stats;
+
+/* Allocation callback of smash_spgemm: return device memory of at least
+ * `bytes` bytes (256-byte aligned) or NULL.  The caller owns it. */
+typedef void *(*smash_alloc_fn)(size_t bytes, void *user);
+
+/* Create a context on HIP device `device`.  *out is NULL on failure. */
+smash_status smash_create(smash_ctx *out, int device);
+
+/* Destroy a context and free its scratch memory.  NULL is ignored.  Work
+ * queued on streams by this context must have completed. */
+void smash_destroy(smash_ctx ctx);
+
+/* Message of the last failing call on ctx ("" if none).  Owned by ctx. */
+const char *smash_last_error(smash_ctx ctx);
+
+/* Static name of a status code. */
+const char *smash_status_string(smash_status s);
+
+smash_status smash_set_option(smash_ctx ctx, smash_option opt, int64_t value);
+smash_status smash_get_option(smash_ctx ctx, smash_option opt, int64_t *value);
+
+/* Symbolic phase: the exact nnz of every row of C = A * B.
+ * Writes C_row_ptr[0..A.rows] (device, int64, exclusive prefix of the row
+ * counts) and *C_nnz (host).  A.val and B.val are not read.  The plan built
+ * here (row bins, heavy-row column counts) is kept in ctx for the next
+ * smash_spgemm_numeric call with the same A, B and C_row_ptr.
+ * Synchronizes the stream once (to read nnz(C) back).
+ * Errors: INVALID_ARG (null pointer, A.cols != B.rows, negative sizes),
+ * INVALID_CSR, OUT_OF_MEMORY, HIP. */
+smash_status smash_spgemm_symbolic(smash_ctx ctx, const smash_csr *A, const smash_csr *B,
+                                   int64_t *C_row_ptr, int64_t *C_nnz, hipStream_t stream);
+
+/* Numeric phase: the columns and values of C = A * B, written at
+ * C_col_idx[C_row_ptr[i] .. C_row_ptr[i+1]) and the same range of C_val
+ * (device; nnz(C) entries each; C_val of dtype).  Requires the plan of a
+ * preceding smash_spgemm_symbolic call on ctx with the same A and B
+ * descriptors and C_row_ptr pointer (else SMASH_ERR_NO_PLAN); the plan stays
+ * valid, so numeric may be repeated after A.val or B.val change.
+ * Synchronizes the stream once (to read the device error flags).
+ * Errors: INVALID_ARG, NO_PLAN, CAPACITY (C_row_ptr inconsistent with the
+ * product), OUT_OF_MEMORY, HIP. */
+smash_status smash_spgemm_numeric(smash_ctx ctx, smash_dtype dtype, const smash_csr *A, const smash_csr *B,
+                                  const int64_t *C_row_ptr, int32_t *C_col_idx, void *C_val,
+                                  hipStream_t stream);
+
+/* Both phases: symbolic, then C_col_idx and C_val allocated through
+ * alloc(nnz * 4, user) and alloc(nnz * value_bytes, user), then numeric.
+ * C_row_ptr (device, A.rows + 1 int64) is the caller's.  On success
+ * *C_col_idx, *C_val (never NULL, also when nnz(C) = 0) and *C_nnz are set.
+ * Errors: those of the two phases, OUT_OF_MEMORY if alloc returns NULL. */
+smash_status smash_spgemm(smash_ctx ctx, smash_dtype dtype, const smash_csr *A, const smash_csr *B,
+                          smash_alloc_fn alloc, void *user, int64_t *C_row_ptr,
+                          int32_t **C_col_idx, void **C_val, int64_t *C_nnz, hipStream_t stream);
+
+/* Counters of the last symbolic (and numeric) call on ctx. */
+smash_status smash_get_stats(smash_ctx ctx, smash_stats *out);
+
+/* Per-kernel timing (SMASH_OPT_TIMING = 1).  For kernel index `index`
+ * (0 .. smash_kernel_count()-1) returns its static name, the number of
+ * launches and the summed elapsed milliseconds since the last reset.
+ * Returns INVALID_ARG for an index out of range. */
+int smash_kernel_count(void);
+smash_status smash_kernel_time(smash_ctx ctx, int index, const char **name, int64_t *launches, double *ms);
+smash_status smash_kernel_time_reset(smash_ctx ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SMASH_H */

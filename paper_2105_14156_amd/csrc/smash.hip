@@ -1,0 +1,703 @@
+// smash.hip -- host side of libsmash: contexts, planning, launches and the C
+// ABI declared in include/smash.h.
+//
+// Call structure (SMASH Kernels chapter: window distribution, hashing and
+// write-back phases, each closed by a barrier; here every phase is a set of
+// kernels ordered on the caller's stream):
+//   symbolic: validate -> analyze (products per row, bins) -> bin offsets ->
+//             scatter rows by bin -> [read bin counts back] -> per-bin LDS
+//             hash kernels + heavy-row kernel -> row-pointer scan -> numeric
+//             bins -> [read nnz(C) back]
+//   numeric:  per-bin LDS hash kernels (hash, compact, sort, write) +
+//             heavy-row kernels -> [read error flags back]
+#include "smash.h"
+#include "smash_kernels.hpp"
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace smash;
+
+namespace {
+
+enum KernelId {
+    K_VALIDATE, K_ANALYZE, K_BIN_OFFSETS, K_SCATTER, K_SYM_LDS, K_SYM_HEAVY, K_SYM_GLOBAL, K_FILL,
+    K_SCAN_REDUCE, K_SCAN_TOP, K_SCAN_APPLY, K_NUM_BINS, K_CHUNK_PREFIX, K_BSPLIT, K_NUM_LDS,
+    K_NUM_HEAVY, K_NUM_GLOBAL, K_COUNT
+};
+
+const char *const kKernelNames[K_COUNT] = {
+    "validate", "analyze", "bin_offsets", "scatter", "sym_lds", "sym_heavy", "sym_global", "fill",
+    "scan_reduce", "scan_top", "scan_apply", "num_bins", "chunk_prefix", "bsplit", "num_lds",
+    "num_heavy_dense", "num_global"};
+
+// Grow-only device buffer.
+struct Arena {
+    void *ptr = nullptr;
+    size_t cap = 0;
+};
+
+struct Carve {
+    char *base;
+    size_t off = 0;
+    template <typename T>
+    T *take(size_t count)
+    {
+        off = (off + 255) & ~size_t(255);
+        T *p = (T *)(base + off);
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+struct Plan {
+    bool valid = false;
+    smash_csr A{}, B{};
+    const int64_t *crp = nullptr;
+    int64_t m = 0, n = 0;
+    int heavy_mode = 0, lds_row_max = 0;
+    DevHdr hdr{};
+    int nchunks = 0;
+    long long *ub = nullptr;
+    int *cap = nullptr, *nnzc = nullptr, *sym_perm = nullptr, *num_perm = nullptr;
+    unsigned char *sym_bin = nullptr, *num_bin = nullptr;
+    long long *bsum = nullptr, *goff_sym = nullptr, *goff_num = nullptr;
+    int *wcnt = nullptr, *woff = nullptr;
+};
+
+struct Pending {
+    int kid;
+    hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct smash_ctx_s {
+    int device = 0;
+    std::string err;
+    int64_t opt[5] = {1, 4096, 0, 0, 0};
+    DevHdr *h_hdr = nullptr;   // pinned host mirror
+    DevHdr *d_hdr = nullptr;
+    Arena plan_mem, heavy_mem, tmp_mem, gkeys, gvals;
+    Plan plan;
+    smash_stats stats{};
+    std::vector<hipEvent_t> event_pool;
+    std::vector<Pending> pending;
+    int64_t launches[K_COUNT] = {};
+    double ms[K_COUNT] = {};
+};
+
+namespace {
+
+smash_status fail(smash_ctx c, smash_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    c->err = std::string(smash_status_string(s)) + ": " + buf;
+    return s;
+}
+
+#define HIP_TRY(c, call)                                                                         \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess)                                                                    \
+            return fail((c), SMASH_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_));      \
+    } while (0)
+
+// Makes the context's device current for the scope of one call.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+smash_status ensure(smash_ctx c, Arena &a, size_t bytes, hipStream_t s)
+{
+    bytes = std::max<size_t>(bytes, 256);
+    if (a.cap >= bytes) return SMASH_OK;
+    if (a.ptr) {
+        HIP_TRY(c, hipStreamSynchronize(s));
+        HIP_TRY(c, hipFree(a.ptr));
+        a.ptr = nullptr;
+        a.cap = 0;
+    }
+    size_t want = std::max(bytes, a.cap + a.cap / 2);
+    if (hipMalloc(&a.ptr, want) != hipSuccess) {
+        (void)hipGetLastError();
+        if (hipMalloc(&a.ptr, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            a.ptr = nullptr;
+            return fail(c, SMASH_ERR_OUT_OF_MEMORY, "device allocation of %zu bytes failed", bytes);
+        }
+        want = bytes;
+    }
+    a.cap = want;
+    return SMASH_OK;
+}
+
+hipEvent_t take_event(smash_ctx c)
+{
+    if (!c->event_pool.empty()) {
+        hipEvent_t e = c->event_pool.back();
+        c->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Launches `fn` (a lambda issuing one kernel) and, with timing on, brackets
+// it with events on the same stream.
+template <typename F>
+smash_status launch(smash_ctx c, int kid, hipStream_t s, F fn)
+{
+    hipEvent_t a = nullptr, b = nullptr;
+    if (c->opt[SMASH_OPT_TIMING]) {
+        a = take_event(c);
+        b = take_event(c);
+        if (a && b) HIP_TRY(c, hipEventRecord(a, s));
+    }
+    fn();
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(c, SMASH_ERR_HIP, "launch of %s failed: %s", kKernelNames[kid], hipGetErrorString(e));
+    if (a && b) {
+        HIP_TRY(c, hipEventRecord(b, s));
+        c->pending.push_back({kid, a, b});
+    }
+    return SMASH_OK;
+}
+
+// Folds completed timing events into the per-kernel totals (after a sync).
+void collect_times(smash_ctx c)
+{
+    for (auto &p : c->pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            c->ms[p.kid] += ms;
+            c->launches[p.kid] += 1;
+        }
+        c->event_pool.push_back(p.a);
+        c->event_pool.push_back(p.b);
+    }
+    c->pending.clear();
+}
+
+#define TRY(...)                           \
+    do {                                   \
+        smash_status s_ = (__VA_ARGS__);   \
+        if (s_ != SMASH_OK) return s_;     \
+    } while (0)
+
+smash_status check_csr(smash_ctx c, const smash_csr *M, const char *name, bool need_val)
+{
+    if (!M) return fail(c, SMASH_ERR_INVALID_ARG, "%s is NULL", name);
+    if (M->rows < 0 || M->cols < 0 || M->nnz < 0)
+        return fail(c, SMASH_ERR_INVALID_ARG, "%s has a negative size", name);
+    if (M->rows >= INT32_MAX || M->cols >= INT32_MAX || M->nnz >= INT32_MAX)
+        return fail(c, SMASH_ERR_INDEX_OVERFLOW, "%s exceeds int32 indexing", name);
+    if (!M->row_ptr) return fail(c, SMASH_ERR_INVALID_ARG, "%s.row_ptr is NULL", name);
+    if (M->nnz > 0 && !M->col_idx) return fail(c, SMASH_ERR_INVALID_ARG, "%s.col_idx is NULL", name);
+    if (need_val && M->nnz > 0 && !M->val) return fail(c, SMASH_ERR_INVALID_ARG, "%s.val is NULL", name);
+    return SMASH_OK;
+}
+
+bool same_csr(const smash_csr &x, const smash_csr &y)
+{
+    return x.rows == y.rows && x.cols == y.cols && x.nnz == y.nnz && x.row_ptr == y.row_ptr && x.col_idx == y.col_idx;
+}
+
+unsigned blocks_for(long long items, int per_block)
+{
+    return (unsigned)((items + per_block - 1) / per_block);
+}
+
+// ------------------------------------------------------------- LDS bins
+
+template <int LOGT>
+struct BinShape {
+    static constexpr int WPR = LOGT <= 10 ? 1 : (1 << (LOGT - 9)) / 1;   // 2048->4, 4096->8, 8192->16
+    static constexpr int RPW = LOGT <= 10 ? 4 : 1;
+    static constexpr int THREADS = kWave * WPR * RPW;
+};
+
+template <int LOGT>
+smash_status launch_sym_bin(smash_ctx c, hipStream_t s, const Plan &p, int cnt, const int *rows)
+{
+    using S = BinShape<LOGT>;
+    return launch(c, K_SYM_LDS, s, [&] {
+        k_sym_lds<LOGT, S::WPR, S::RPW><<<blocks_for(cnt, S::RPW), S::THREADS, 0, s>>>(
+            p.A.row_ptr, p.A.col_idx, p.B.row_ptr, p.B.col_idx, rows, cnt, p.nnzc, &c->d_hdr->error);
+    });
+}
+
+template <typename V, int LOGT>
+smash_status launch_num_bin(smash_ctx c, hipStream_t s, const Plan &p, int cnt, const int *rows, const V *Aval,
+                            const V *Bval, const int64_t *crp, int32_t *ccol, V *cval)
+{
+    using S = BinShape<LOGT>;
+    return launch(c, K_NUM_LDS, s, [&] {
+        k_num_lds<V, LOGT, S::WPR, S::RPW><<<blocks_for(cnt, S::RPW), S::THREADS, 0, s>>>(
+            p.A.row_ptr, p.A.col_idx, Aval, p.B.row_ptr, p.B.col_idx, Bval, rows, cnt, (const long long *)crp, ccol,
+            cval, &c->d_hdr->error);
+    });
+}
+
+smash_status run_sym_bins(smash_ctx c, hipStream_t s, const Plan &p)
+{
+    const BinHdr &b = p.hdr.sym;
+    const int *perm = p.sym_perm;
+#define SYM_BIN(LT)                                                                               \
+    if (b.count[LT - kMinLogT]) TRY(launch_sym_bin<LT>(c, s, p, b.count[LT - kMinLogT], perm + b.offset[LT - kMinLogT]));
+    SYM_BIN(6) SYM_BIN(7) SYM_BIN(8) SYM_BIN(9) SYM_BIN(10) SYM_BIN(11) SYM_BIN(12) SYM_BIN(13)
+#undef SYM_BIN
+    return SMASH_OK;
+}
+
+template <typename V>
+smash_status run_num_bins(smash_ctx c, hipStream_t s, const Plan &p, const V *Aval, const V *Bval,
+                          const int64_t *crp, int32_t *ccol, V *cval)
+{
+    const BinHdr &b = p.hdr.num;
+    const int *perm = p.num_perm;
+#define NUM_BIN(LT)                                                                                   \
+    if (b.count[LT - kMinLogT])                                                                       \
+        TRY(launch_num_bin<V, LT>(c, s, p, b.count[LT - kMinLogT], perm + b.offset[LT - kMinLogT], Aval, Bval, crp, \
+                                  ccol, cval));
+    NUM_BIN(6) NUM_BIN(7) NUM_BIN(8) NUM_BIN(9) NUM_BIN(10) NUM_BIN(11) NUM_BIN(12) NUM_BIN(13)
+#undef NUM_BIN
+    return SMASH_OK;
+}
+
+size_t sym_heavy_lds(int64_t ncols)
+{
+    const int wbits = ncols < kSymWindowBits ? (int)((ncols + 31) & ~31LL) : kSymWindowBits;
+    return (size_t)wbits / 32 * 4 + 2 * (kHeavyThreads / kWave) * kWave * sizeof(int);
+}
+
+template <typename V, int UNITS>
+size_t num_heavy_lds()
+{
+    constexpr int W = UNITS * kChunkCols;
+    return (size_t)W * sizeof(V) + W / 32 * 4 + 2 * (kHeavyThreads / kWave) * kWave * sizeof(int) +
+           (kHeavyThreads / kWave) * kWave * sizeof(V);
+}
+
+template <typename V, int UNITS>
+smash_status launch_num_heavy(smash_ctx c, hipStream_t s, const Plan &p, int H, const V *Aval, const V *Bval,
+                              const int *bsplit, int nwin, const int64_t *crp, int32_t *ccol, V *cval)
+{
+    const size_t lds = num_heavy_lds<V, UNITS>();
+    (void)hipFuncSetAttribute((const void *)k_num_heavy_dense<V, UNITS>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+    const int *rows = p.sym_perm + p.hdr.sym.offset[kBinHeavy];
+    return launch(c, K_NUM_HEAVY, s, [&] {
+        k_num_heavy_dense<V, UNITS><<<(unsigned)((long long)H * nwin), kHeavyThreads, lds, s>>>(
+            p.A.row_ptr, p.A.col_idx, Aval, p.B.col_idx, Bval, bsplit, rows, nwin, p.nchunks, p.wcnt, p.woff,
+            (const long long *)crp, ccol, cval, &c->d_hdr->error, &c->d_hdr->heavy_windows);
+    });
+}
+
+template <typename V>
+smash_status numeric_impl(smash_ctx c, hipStream_t s, const Plan &p, const V *Aval, const V *Bval,
+                          const int64_t *crp, int32_t *ccol, V *cval)
+{
+    TRY(run_num_bins<V>(c, s, p, Aval, Bval, crp, ccol, cval));
+    const int H = p.hdr.sym.count[kBinHeavy];
+    if (H == 0) return SMASH_OK;
+    if (p.heavy_mode == 0) {
+        int units = (int)c->opt[SMASH_OPT_WINDOW_UNITS];
+        if (units == 0) units = sizeof(V) == 4 ? 4 : 2;
+        if (sizeof(V) == 8 && units > 2) units = 2;
+        const int W = units * kChunkCols;
+        const int nwin = (int)((p.n + W - 1) / W);
+        const long long kdim = p.B.rows;
+        TRY(ensure(c, c->tmp_mem, (size_t)(kdim * (nwin + 1)) * sizeof(int), s));
+        int *bsplit = (int *)c->tmp_mem.ptr;
+        TRY(launch(c, K_BSPLIT, s, [&] {
+            k_bsplit<<<blocks_for(kdim * (nwin + 1), 256), 256, 0, s>>>((int)kdim, W, nwin, p.B.row_ptr, p.B.col_idx,
+                                                                       bsplit);
+        }));
+        switch (units) {
+        case 1: return launch_num_heavy<V, 1>(c, s, p, H, Aval, Bval, bsplit, nwin, crp, ccol, cval);
+        case 2: return launch_num_heavy<V, 2>(c, s, p, H, Aval, Bval, bsplit, nwin, crp, ccol, cval);
+        default:
+            if constexpr (sizeof(V) == 4) return launch_num_heavy<V, 4>(c, s, p, H, Aval, Bval, bsplit, nwin, crp, ccol, cval);
+            return fail(c, SMASH_ERR_INVALID_ARG, "window units %d not supported for this dtype", units);
+        }
+    }
+    // global-memory hash tables
+    const unsigned long long slots = p.hdr.gneed[1];
+    TRY(ensure(c, c->gkeys, slots * sizeof(int), s));
+    TRY(ensure(c, c->gvals, slots * sizeof(V), s));
+    const size_t lds = (size_t)kGlobalRankBits / 8;
+    (void)hipFuncSetAttribute((const void *)k_num_global<V>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const int *rows = p.num_perm + p.hdr.num.offset[kBinHeavy];
+    return launch(c, K_NUM_GLOBAL, s, [&] {
+        k_num_global<V><<<H, kHeavyThreads, lds, s>>>(p.A.row_ptr, p.A.col_idx, Aval, p.B.row_ptr, p.B.col_idx, Bval,
+                                                      rows, (int)p.n, p.goff_num, (int *)c->gkeys.ptr,
+                                                      (V *)c->gvals.ptr, (const long long *)crp, ccol, cval,
+                                                      &c->d_hdr->error);
+    });
+}
+
+smash_status read_hdr(smash_ctx c, hipStream_t s)
+{
+    HIP_TRY(c, hipMemcpyAsync(c->h_hdr, c->d_hdr, sizeof(DevHdr), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    collect_times(c);
+    return SMASH_OK;
+}
+
+smash_status device_errors(smash_ctx c, int e)
+{
+    if (e & (kErrCsrA | kErrCsrB))
+        return fail(c, SMASH_ERR_INVALID_CSR, "%s violates the CSR preconditions (row_ptr[0] = 0, nondecreasing, "
+                    "row_ptr[rows] = nnz, columns in range and strictly ascending)",
+                    (e & kErrCsrA) ? "A" : "B");
+    if (e & (kErrProbe | kErrCount))
+        return fail(c, SMASH_ERR_CAPACITY, "C_row_ptr does not match the product (device flags 0x%x)", e);
+    return SMASH_OK;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+
+extern "C" {
+
+const char *smash_status_string(smash_status s)
+{
+    switch (s) {
+    case SMASH_OK: return "SMASH_OK";
+    case SMASH_ERR_INVALID_ARG: return "SMASH_ERR_INVALID_ARG";
+    case SMASH_ERR_INVALID_CSR: return "SMASH_ERR_INVALID_CSR";
+    case SMASH_ERR_INDEX_OVERFLOW: return "SMASH_ERR_INDEX_OVERFLOW";
+    case SMASH_ERR_CAPACITY: return "SMASH_ERR_CAPACITY";
+    case SMASH_ERR_OUT_OF_MEMORY: return "SMASH_ERR_OUT_OF_MEMORY";
+    case SMASH_ERR_HIP: return "SMASH_ERR_HIP";
+    case SMASH_ERR_NO_PLAN: return "SMASH_ERR_NO_PLAN";
+    }
+    return "SMASH_ERR_UNKNOWN";
+}
+
+smash_status smash_create(smash_ctx *out, int device)
+{
+    if (!out) return SMASH_ERR_INVALID_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return SMASH_ERR_INVALID_ARG;
+    smash_ctx c = new (std::nothrow) smash_ctx_s();
+    if (!c) return SMASH_ERR_OUT_OF_MEMORY;
+    c->device = device;
+    DeviceGuard g(device);
+    if (!g.ok || hipHostMalloc((void **)&c->h_hdr, sizeof(DevHdr), hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return SMASH_ERR_HIP;
+    }
+    if (hipMalloc((void **)&c->d_hdr, sizeof(DevHdr)) != hipSuccess) {
+        (void)hipHostFree(c->h_hdr);
+        delete c;
+        return SMASH_ERR_OUT_OF_MEMORY;
+    }
+    memset(c->h_hdr, 0, sizeof(DevHdr));
+    *out = c;
+    return SMASH_OK;
+}
+
+void smash_destroy(smash_ctx c)
+{
+    if (!c) return;
+    DeviceGuard g(c->device);
+    for (Arena *a : {&c->plan_mem, &c->heavy_mem, &c->tmp_mem, &c->gkeys, &c->gvals})
+        if (a->ptr) (void)hipFree(a->ptr);
+    if (c->d_hdr) (void)hipFree(c->d_hdr);
+    if (c->h_hdr) (void)hipHostFree(c->h_hdr);
+    for (auto &p : c->pending) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    for (auto e : c->event_pool) (void)hipEventDestroy(e);
+    delete c;
+}
+
+const char *smash_last_error(smash_ctx c) { return c ? c->err.c_str() : "null context"; }
+
+smash_status smash_set_option(smash_ctx c, smash_option opt, int64_t v)
+{
+    if (!c) return SMASH_ERR_INVALID_ARG;
+    switch (opt) {
+    case SMASH_OPT_VALIDATE:
+    case SMASH_OPT_TIMING:
+        if (v != 0 && v != 1) return fail(c, SMASH_ERR_INVALID_ARG, "option %d takes 0 or 1", (int)opt);
+        break;
+    case SMASH_OPT_LDS_ROW_MAX:
+        if (v < 32 || v > 4096) return fail(c, SMASH_ERR_INVALID_ARG, "LDS row max must be in [32, 4096]");
+        break;
+    case SMASH_OPT_HEAVY_MODE:
+        if (v != 0 && v != 1) return fail(c, SMASH_ERR_INVALID_ARG, "heavy mode is 0 (windowed) or 1 (global hash)");
+        break;
+    case SMASH_OPT_WINDOW_UNITS:
+        if (v != 0 && v != 1 && v != 2 && v != 4) return fail(c, SMASH_ERR_INVALID_ARG, "window units are 0, 1, 2 or 4");
+        break;
+    default: return fail(c, SMASH_ERR_INVALID_ARG, "unknown option %d", (int)opt);
+    }
+    c->opt[opt] = v;
+    c->plan.valid = false;
+    return SMASH_OK;
+}
+
+smash_status smash_get_option(smash_ctx c, smash_option opt, int64_t *v)
+{
+    if (!c || !v || (int)opt < 0 || (int)opt > SMASH_OPT_TIMING) return SMASH_ERR_INVALID_ARG;
+    *v = c->opt[opt];
+    return SMASH_OK;
+}
+
+smash_status smash_spgemm_symbolic(smash_ctx c, const smash_csr *A, const smash_csr *B, int64_t *C_row_ptr,
+                                   int64_t *C_nnz, hipStream_t s)
+{
+    if (!c) return SMASH_ERR_INVALID_ARG;
+    c->err.clear();
+    c->plan.valid = false;
+    TRY(check_csr(c, A, "A", false));
+    TRY(check_csr(c, B, "B", false));
+    if (A->cols != B->rows) return fail(c, SMASH_ERR_INVALID_ARG, "A.cols (%lld) != B.rows (%lld)", (long long)A->cols, (long long)B->rows);
+    if (!C_row_ptr || !C_nnz) return fail(c, SMASH_ERR_INVALID_ARG, "C_row_ptr and C_nnz must not be NULL");
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(c, SMASH_ERR_HIP, "hipSetDevice(%d) failed", c->device);
+
+    Plan &p = c->plan;
+    p = Plan();
+    p.A = *A;
+    p.B = *B;
+    p.crp = C_row_ptr;
+    p.m = A->rows;
+    p.n = B->cols;
+    p.heavy_mode = (int)c->opt[SMASH_OPT_HEAVY_MODE];
+    p.lds_row_max = (int)c->opt[SMASH_OPT_LDS_ROW_MAX];
+    p.nchunks = (int)((p.n + kChunkCols - 1) / kChunkCols);
+    const int64_t m = p.m;
+    c->stats = smash_stats();
+    c->stats.rows = m;
+
+    HIP_TRY(c, hipMemsetAsync(c->d_hdr, 0, sizeof(DevHdr), s));
+    if (c->opt[SMASH_OPT_VALIDATE]) {
+        TRY(launch(c, K_VALIDATE, s, [&] {
+            k_validate<<<blocks_for(A->rows + 1, 256), 256, 0, s>>>((int)A->rows, (int)A->cols, A->nnz, A->row_ptr,
+                                                                    A->col_idx, kErrCsrA, &c->d_hdr->error);
+        }));
+        TRY(launch(c, K_VALIDATE, s, [&] {
+            k_validate<<<blocks_for(B->rows + 1, 256), 256, 0, s>>>((int)B->rows, (int)B->cols, B->nnz, B->row_ptr,
+                                                                    B->col_idx, kErrCsrB, &c->d_hdr->error);
+        }));
+        TRY(read_hdr(c, s));
+        TRY(device_errors(c, c->h_hdr->error));
+    }
+    if (m == 0) {
+        HIP_TRY(c, hipMemsetAsync(C_row_ptr, 0, sizeof(int64_t), s));
+        HIP_TRY(c, hipStreamSynchronize(s));
+        *C_nnz = 0;
+        p.hdr = DevHdr();
+        p.valid = true;
+        return SMASH_OK;
+    }
+
+    // per-row plan arrays
+    const int nb = (int)blocks_for(m, kScanItems);
+    const bool global = p.heavy_mode == 1;
+    {
+        size_t need = 0;
+        need += 256 + m * sizeof(long long);          // ub
+        need += 256 + m * sizeof(int) * 4;            // cap, nnzc, sym_perm, num_perm
+        need += 512 + m * 2;                          // bins
+        need += 256 + (nb + 1) * sizeof(long long);   // bsum
+        if (global) need += 512 + 2 * m * sizeof(long long);
+        need += 4096;
+        TRY(ensure(c, c->plan_mem, need, s));
+        Carve cv{(char *)c->plan_mem.ptr};
+        p.ub = cv.take<long long>(m);
+        p.cap = cv.take<int>(m);
+        p.nnzc = cv.take<int>(m);
+        p.sym_perm = cv.take<int>(m);
+        p.num_perm = cv.take<int>(m);
+        p.sym_bin = cv.take<unsigned char>(m);
+        p.num_bin = cv.take<unsigned char>(m);
+        p.bsum = cv.take<long long>(nb + 1);
+        if (global) {
+            p.goff_sym = cv.take<long long>(m);
+            p.goff_num = cv.take<long long>(m);
+        }
+    }
+
+    TRY(launch(c, K_ANALYZE, s, [&] {
+        k_analyze<<<blocks_for(m, 4), 256, 0, s>>>((int)m, (int)p.n, p.lds_row_max, A->row_ptr, A->col_idx, B->row_ptr,
+                                                   p.ub, p.cap, p.nnzc, p.sym_bin, c->d_hdr);
+    }));
+    TRY(launch(c, K_BIN_OFFSETS, s, [&] { k_bin_offsets<<<1, 1, 0, s>>>(&c->d_hdr->sym); }));
+    TRY(launch(c, K_SCATTER, s, [&] {
+        k_scatter<<<blocks_for(m, 256), 256, 0, s>>>((int)m, p.sym_bin, &c->d_hdr->sym, p.sym_perm,
+                                                     global ? p.cap : nullptr, &c->d_hdr->gcursor[0], p.goff_sym);
+    }));
+    TRY(read_hdr(c, s));
+    p.hdr = *c->h_hdr;
+
+    // symbolic per bin
+    TRY(run_sym_bins(c, s, p));
+    const int H = p.hdr.sym.count[kBinHeavy];
+    const int *heavy_rows = p.sym_perm + p.hdr.sym.offset[kBinHeavy];
+    if (H > 0) {
+        if (!global) {
+            const size_t cells = (size_t)H * p.nchunks;
+            TRY(ensure(c, c->heavy_mem, 2 * cells * sizeof(int) + 512, s));
+            Carve cv{(char *)c->heavy_mem.ptr};
+            p.wcnt = cv.take<int>(cells);
+            p.woff = cv.take<int>(cells);
+            const size_t lds = sym_heavy_lds(p.n);
+            (void)hipFuncSetAttribute((const void *)k_sym_heavy, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            TRY(launch(c, K_SYM_HEAVY, s, [&] {
+                k_sym_heavy<<<H, kHeavyThreads, lds, s>>>(A->row_ptr, A->col_idx, B->row_ptr, B->col_idx, heavy_rows,
+                                                          (int)p.n, p.nchunks, p.wcnt, p.nnzc, &c->d_hdr->error);
+            }));
+        } else {
+            const unsigned long long slots = p.hdr.gneed[0];
+            TRY(ensure(c, c->gkeys, slots * sizeof(int), s));
+            TRY(launch(c, K_FILL, s, [&] {
+                k_fill_i32<<<2048, 256, 0, s>>>((long long)slots, (int *)c->gkeys.ptr, kEmpty);
+            }));
+            TRY(launch(c, K_SYM_GLOBAL, s, [&] {
+                k_sym_global<<<H, kHeavyThreads, 0, s>>>(A->row_ptr, A->col_idx, B->row_ptr, B->col_idx, heavy_rows,
+                                                         p.cap, p.goff_sym, (int *)c->gkeys.ptr, p.nnzc,
+                                                         &c->d_hdr->error);
+            }));
+        }
+    }
+
+    // C_row_ptr = exclusive scan of the row counts
+    TRY(launch(c, K_SCAN_REDUCE, s, [&] { k_scan_reduce<<<nb, kScanThreads, 0, s>>>((int)m, p.nnzc, p.bsum); }));
+    TRY(launch(c, K_SCAN_TOP, s, [&] { k_scan_top<<<1, kScanThreads, 0, s>>>(nb, p.bsum, &c->d_hdr->nnz_c); }));
+    TRY(launch(c, K_SCAN_APPLY, s, [&] {
+        k_scan_apply<<<nb, kScanThreads, 0, s>>>((int)m, p.nnzc, p.bsum, &c->d_hdr->nnz_c, (long long *)C_row_ptr);
+    }));
+    // numeric bins of the plan
+    TRY(launch(c, K_NUM_BINS, s, [&] {
+        k_num_bins<<<blocks_for(m, 256), 256, 0, s>>>((int)m, p.nnzc, p.sym_bin, p.num_bin, c->d_hdr);
+    }));
+    TRY(launch(c, K_BIN_OFFSETS, s, [&] { k_bin_offsets<<<1, 1, 0, s>>>(&c->d_hdr->num); }));
+    TRY(launch(c, K_SCATTER, s, [&] {
+        k_scatter<<<blocks_for(m, 256), 256, 0, s>>>((int)m, p.num_bin, &c->d_hdr->num, p.num_perm,
+                                                     global ? p.nnzc : nullptr, &c->d_hdr->gcursor[1], p.goff_num);
+    }));
+    if (H > 0 && !global) {
+        TRY(launch(c, K_CHUNK_PREFIX, s, [&] {
+            k_chunk_prefix<<<blocks_for(H, 256), 256, 0, s>>>(H, p.nchunks, p.wcnt, p.woff);
+        }));
+    }
+    TRY(read_hdr(c, s));
+    p.hdr = *c->h_hdr;
+    TRY(device_errors(c, p.hdr.error));
+    *C_nnz = p.hdr.nnz_c;
+    c->stats.products = (int64_t)p.hdr.products;
+    c->stats.nnz_c = p.hdr.nnz_c;
+    c->stats.rows_empty = p.hdr.sym.count[kBinEmpty];
+    c->stats.rows_heavy = H;
+    c->stats.rows_lds = m - H - p.hdr.sym.count[kBinEmpty];
+    c->stats.global_slots = global ? (int64_t)(p.hdr.gneed[0] + p.hdr.gneed[1]) : 0;
+    p.valid = true;
+    return SMASH_OK;
+}
+
+smash_status smash_spgemm_numeric(smash_ctx c, smash_dtype dtype, const smash_csr *A, const smash_csr *B,
+                                  const int64_t *C_row_ptr, int32_t *C_col_idx, void *C_val, hipStream_t s)
+{
+    if (!c) return SMASH_ERR_INVALID_ARG;
+    c->err.clear();
+    if (dtype != SMASH_F32 && dtype != SMASH_F64) return fail(c, SMASH_ERR_INVALID_ARG, "unknown dtype %d", (int)dtype);
+    TRY(check_csr(c, A, "A", true));
+    TRY(check_csr(c, B, "B", true));
+    const Plan &p = c->plan;
+    if (!p.valid || !same_csr(p.A, *A) || !same_csr(p.B, *B) || p.crp != C_row_ptr)
+        return fail(c, SMASH_ERR_NO_PLAN, "no symbolic plan on this context for these A, B and C_row_ptr");
+    if (p.hdr.nnz_c > 0 && (!C_col_idx || !C_val))
+        return fail(c, SMASH_ERR_INVALID_ARG, "C_col_idx and C_val must not be NULL");
+    if (p.m == 0 || p.hdr.nnz_c == 0) return SMASH_OK;
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(c, SMASH_ERR_HIP, "hipSetDevice(%d) failed", c->device);
+    HIP_TRY(c, hipMemsetAsync(&c->d_hdr->error, 0, 2 * sizeof(int), s));
+    smash_status st;
+    if (dtype == SMASH_F32)
+        st = numeric_impl<float>(c, s, p, (const float *)A->val, (const float *)B->val, C_row_ptr, C_col_idx,
+                                 (float *)C_val);
+    else
+        st = numeric_impl<double>(c, s, p, (const double *)A->val, (const double *)B->val, C_row_ptr, C_col_idx,
+                                  (double *)C_val);
+    if (st != SMASH_OK) return st;
+    TRY(read_hdr(c, s));
+    c->stats.heavy_windows = c->h_hdr->heavy_windows;
+    return device_errors(c, c->h_hdr->error);
+}
+
+smash_status smash_spgemm(smash_ctx c, smash_dtype dtype, const smash_csr *A, const smash_csr *B,
+                          smash_alloc_fn alloc, void *user, int64_t *C_row_ptr, int32_t **C_col_idx, void **C_val,
+                          int64_t *C_nnz, hipStream_t s)
+{
+    if (!c) return SMASH_ERR_INVALID_ARG;
+    if (!alloc || !C_col_idx || !C_val || !C_nnz) return fail(c, SMASH_ERR_INVALID_ARG, "null output argument");
+    if (dtype != SMASH_F32 && dtype != SMASH_F64) return fail(c, SMASH_ERR_INVALID_ARG, "unknown dtype %d", (int)dtype);
+    int64_t nnz = 0;
+    TRY(smash_spgemm_symbolic(c, A, B, C_row_ptr, &nnz, s));
+    const size_t vb = dtype == SMASH_F32 ? 4 : 8;
+    void *col = alloc(std::max<size_t>((size_t)nnz * 4, 256), user);
+    void *val = alloc(std::max<size_t>((size_t)nnz * vb, 256), user);
+    if (!col || !val) return fail(c, SMASH_ERR_OUT_OF_MEMORY, "allocation callback returned NULL");
+    *C_col_idx = (int32_t *)col;
+    *C_val = val;
+    *C_nnz = nnz;
+    return smash_spgemm_numeric(c, dtype, A, B, C_row_ptr, (int32_t *)col, val, s);
+}
+
+smash_status smash_get_stats(smash_ctx c, smash_stats *out)
+{
+    if (!c || !out) return SMASH_ERR_INVALID_ARG;
+    *out = c->stats;
+    return SMASH_OK;
+}
+
+int smash_kernel_count(void) { return K_COUNT; }
+
+smash_status smash_kernel_time(smash_ctx c, int index, const char **name, int64_t *launches, double *ms)
+{
+    if (!c || index < 0 || index >= K_COUNT) return SMASH_ERR_INVALID_ARG;
+    if (name) *name = kKernelNames[index];
+    if (launches) *launches = c->launches[index];
+    if (ms) *ms = c->ms[index];
+    return SMASH_OK;
+}
+
+smash_status smash_kernel_time_reset(smash_ctx c)
+{
+    if (!c) return SMASH_ERR_INVALID_ARG;
+    for (int k = 0; k < K_COUNT; ++k) {
+        c->launches[k] = 0;
+        c->ms[k] = 0.0;
+    }
+    return SMASH_OK;
+}
+
+}  // extern "C"

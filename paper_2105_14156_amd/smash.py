@@ -1,0 +1,216 @@
+"""ctypes binding of libsmash (include/smash.h): argument marshalling only.
+
+Every step of the multiply runs in the HIP library; this module turns torch
+device tensors into the C ABI's pointers and sizes.  Importing it fails
+loudly when ``libsmash.so`` has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsmash.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950) first")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+OK = 0
+STATUS = {0: "SMASH_OK", 1: "SMASH_ERR_INVALID_ARG", 2: "SMASH_ERR_INVALID_CSR", 3: "SMASH_ERR_INDEX_OVERFLOW",
+          4: "SMASH_ERR_CAPACITY", 5: "SMASH_ERR_OUT_OF_MEMORY", 6: "SMASH_ERR_HIP", 7: "SMASH_ERR_NO_PLAN"}
+F32, F64 = 0, 1
+OPT_VALIDATE, OPT_LDS_ROW_MAX, OPT_HEAVY_MODE, OPT_WINDOW_UNITS, OPT_TIMING = range(5)
+
+
+class CsrDesc(ctypes.Structure):
+    _fields_ = [("rows", ctypes.c_int64), ("cols", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("rows", "products", "nnz_c", "rows_empty", "rows_lds",
+                                               "rows_heavy", "heavy_windows", "global_slots")]
+
+    def as_dict(self):
+        return {n: int(getattr(self, n)) for n, _ in self._fields_}
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+
+_c = ctypes.c_void_p
+_lib.smash_create.argtypes = [ctypes.POINTER(_c), ctypes.c_int]
+_lib.smash_destroy.argtypes = [_c]
+_lib.smash_destroy.restype = None
+_lib.smash_last_error.argtypes = [_c]
+_lib.smash_last_error.restype = ctypes.c_char_p
+_lib.smash_status_string.argtypes = [ctypes.c_int]
+_lib.smash_status_string.restype = ctypes.c_char_p
+_lib.smash_set_option.argtypes = [_c, ctypes.c_int, ctypes.c_int64]
+_lib.smash_get_option.argtypes = [_c, ctypes.c_int, ctypes.POINTER(ctypes.c_int64)]
+_lib.smash_spgemm_symbolic.argtypes = [_c, ctypes.POINTER(CsrDesc), ctypes.POINTER(CsrDesc), _c,
+                                       ctypes.POINTER(ctypes.c_int64), _c]
+_lib.smash_spgemm_numeric.argtypes = [_c, ctypes.c_int, ctypes.POINTER(CsrDesc), ctypes.POINTER(CsrDesc), _c, _c, _c, _c]
+_lib.smash_spgemm.argtypes = [_c, ctypes.c_int, ctypes.POINTER(CsrDesc), ctypes.POINTER(CsrDesc), ALLOC_FN, _c, _c,
+                              ctypes.POINTER(_c), ctypes.POINTER(_c), ctypes.POINTER(ctypes.c_int64), _c]
+_lib.smash_get_stats.argtypes = [_c, ctypes.POINTER(Stats)]
+_lib.smash_kernel_count.argtypes = []
+_lib.smash_kernel_time.argtypes = [_c, ctypes.c_int, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_int64),
+                                   ctypes.POINTER(ctypes.c_double)]
+_lib.smash_kernel_time_reset.argtypes = [_c]
+for _f in ("smash_create", "smash_set_option", "smash_get_option", "smash_spgemm_symbolic", "smash_spgemm_numeric",
+           "smash_spgemm", "smash_get_stats", "smash_kernel_count", "smash_kernel_time", "smash_kernel_time_reset"):
+    getattr(_lib, _f).restype = ctypes.c_int
+
+
+class SmashError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+@dataclasses.dataclass
+class DeviceCSR:
+    """CSR in device memory (torch tensors: int32 row_ptr/col_idx)."""
+    rows: int
+    cols: int
+    row_ptr: "object"
+    col_idx: "object"
+    val: "object"
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col_idx.numel())
+
+    def desc(self) -> CsrDesc:
+        return CsrDesc(self.rows, self.cols, self.nnz, self.row_ptr.data_ptr(),
+                       self.col_idx.data_ptr() if self.nnz else 0,
+                       self.val.data_ptr() if (self.val is not None and self.nnz) else 0)
+
+
+def to_device(M, device="cuda", dtype=None) -> DeviceCSR:
+    """Copies a host CSR (synthetic.CSR) to the device."""
+    import torch
+    val = M.val if dtype is None else M.val.astype(dtype)
+    return DeviceCSR(M.rows, M.cols,
+                     torch.from_numpy(np.ascontiguousarray(M.row_ptr, np.int32)).to(device),
+                     torch.from_numpy(np.ascontiguousarray(M.col_idx, np.int32)).to(device),
+                     torch.from_numpy(np.ascontiguousarray(val)).to(device))
+
+
+def _stream_ptr(stream) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _dtype_code(t) -> int:
+    import torch
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype == torch.float64:
+        return F64
+    raise TypeError(f"unsupported value dtype {t.dtype}")
+
+
+class Context:
+    """One libsmash context on one HIP device."""
+
+    def __init__(self, device: int = 0):
+        h = _c()
+        st = _lib.smash_create(ctypes.byref(h), int(device))
+        if st != OK:
+            raise SmashError(st, f"smash_create(device={device}) failed")
+        self._h = h
+        self.device = int(device)
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.smash_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int):
+        if st != OK:
+            raise SmashError(st, _lib.smash_last_error(self._h).decode())
+
+    def set_option(self, opt: int, value: int):
+        self._check(_lib.smash_set_option(self._h, int(opt), int(value)))
+
+    def get_option(self, opt: int) -> int:
+        v = ctypes.c_int64()
+        self._check(_lib.smash_get_option(self._h, int(opt), ctypes.byref(v)))
+        return int(v.value)
+
+    def symbolic(self, A: DeviceCSR, B: DeviceCSR, C_row_ptr, stream=None) -> int:
+        nnz = ctypes.c_int64()
+        da, db = A.desc(), B.desc()
+        self._check(_lib.smash_spgemm_symbolic(self._h, ctypes.byref(da), ctypes.byref(db), C_row_ptr.data_ptr(),
+                                               ctypes.byref(nnz), _stream_ptr(stream)))
+        return int(nnz.value)
+
+    def numeric(self, A: DeviceCSR, B: DeviceCSR, C_row_ptr, C_col, C_val, stream=None):
+        da, db = A.desc(), B.desc()
+        self._check(_lib.smash_spgemm_numeric(self._h, _dtype_code(A.val), ctypes.byref(da), ctypes.byref(db),
+                                              C_row_ptr.data_ptr(), C_col.data_ptr() if C_col.numel() else 0,
+                                              C_val.data_ptr() if C_val.numel() else 0, _stream_ptr(stream)))
+
+    def spgemm(self, A: DeviceCSR, B: DeviceCSR, stream=None, C_row_ptr=None) -> DeviceCSR:
+        """C = A * B through smash_spgemm; C's arrays come from torch."""
+        import torch
+        dev = A.row_ptr.device
+        if C_row_ptr is None:
+            C_row_ptr = torch.empty(A.rows + 1, dtype=torch.int64, device=dev)
+        held = []
+
+        def _alloc(nbytes, _user):
+            t = torch.empty(int(nbytes), dtype=torch.uint8, device=dev)
+            held.append(t)
+            return t.data_ptr()
+
+        cb = ALLOC_FN(_alloc)
+        col_p, val_p, nnz = _c(), _c(), ctypes.c_int64()
+        da, db = A.desc(), B.desc()
+        self._check(_lib.smash_spgemm(self._h, _dtype_code(A.val), ctypes.byref(da), ctypes.byref(db), cb, None,
+                                      C_row_ptr.data_ptr(), ctypes.byref(col_p), ctypes.byref(val_p),
+                                      ctypes.byref(nnz), _stream_ptr(stream)))
+        n = int(nnz.value)
+        col = held[0].view(torch.int32)[:n]
+        val = held[1].view(A.val.dtype)[:n]
+        return DeviceCSR(A.rows, B.cols, C_row_ptr, col, val)
+
+    def stats(self) -> dict:
+        s = Stats()
+        self._check(_lib.smash_get_stats(self._h, ctypes.byref(s)))
+        return s.as_dict()
+
+    def kernel_times(self) -> dict:
+        """{kernel name: (launches, total ms)} with OPT_TIMING on."""
+        out = {}
+        for i in range(_lib.smash_kernel_count()):
+            name, n, ms = ctypes.c_char_p(), ctypes.c_int64(), ctypes.c_double()
+            self._check(_lib.smash_kernel_time(self._h, i, ctypes.byref(name), ctypes.byref(n), ctypes.byref(ms)))
+            out[name.value.decode()] = (int(n.value), float(ms.value))
+        return out
+
+    def reset_kernel_times(self):
+        self._check(_lib.smash_kernel_time_reset(self._h))
+
+
+def status_string(code: int) -> str:
+    return _lib.smash_status_string(int(code)).decode()
+
+
+def exported_symbols():
+    """Names of the C entry points this binding expects."""
+    return [n for n in dir(_lib) if n.startswith("smash_")]

@@ -1,0 +1,194 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle.
+
+Structure bit-exact, values within 1e-5 (FP32) / 1e-12 (FP64) of the sum of
+|a_ik b_kj| per entry, single-term entries bitwise (see tests/_parity.py).
+Workloads: RMAT scale 10 (edge factor 8) and scale 16 (edge factor 16) C = A.A,
+both heavy-row strategies, forced heavy rows, rectangular and structured
+edge cases.
+"""
+import numpy as np
+import pytest
+
+import synthetic as syn
+from tests._parity import check_rows
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def sm(torch_mod):
+    from paper_2105_14156_amd import smash
+    return smash
+
+
+@pytest.fixture()
+def ctx(sm):
+    c = sm.Context(0)
+    yield c
+    c.close()
+
+
+def run(sm, ctx, A, B, dtype, split=False):
+    dA = sm.to_device(A, dtype=dtype)
+    dB = dA if B is A else sm.to_device(B, dtype=dtype)
+    if split:
+        import torch
+        rp = torch.empty(A.rows + 1, dtype=torch.int64, device="cuda")
+        nnz = ctx.symbolic(dA, dB, rp)
+        col = torch.empty(nnz, dtype=torch.int32, device="cuda")
+        val = torch.empty(nnz, dtype=dA.val.dtype, device="cuda")
+        ctx.numeric(dA, dB, rp, col, val)
+        return rp.cpu().numpy(), col.cpu().numpy(), val.cpu().numpy()
+    C = ctx.spgemm(dA, dB)
+    return C.row_ptr.cpu().numpy(), C.col_idx.cpu().numpy(), C.val.cpu().numpy()
+
+
+def full_check(sm, ctx, A, B, dtype, oracle_mod, split=False, where=""):
+    A = A.astype(dtype)
+    B = A if B is None else B.astype(dtype)
+    rp, col, val = run(sm, ctx, A, B, dtype, split)
+    ref = oracle_mod.spgemm(A, B)
+    return check_rows(rp, col, val, ref, dtype, where)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("split", [False, True])
+def test_rmat_s10(sm, ctx, oracle_mod, dtype, split):
+    w = syn.workload_small()
+    full_check(sm, ctx, w.A, None, dtype, oracle_mod, split, "s10")
+    st = ctx.stats()
+    ub = oracle_mod.products_per_row(w.A, w.A)
+    assert st["products"] == int(ub.sum())
+
+
+@pytest.fixture(scope="module")
+def s16():
+    return syn.workload_s16().A
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_rmat_s16(sm, ctx, oracle_mod, s16, dtype):
+    full_check(sm, ctx, s16, None, dtype, oracle_mod, False, "s16")
+    st = ctx.stats()
+    assert st["rows_heavy"] > 0 and st["rows_lds"] > 0
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_rmat_s16_global_hash(sm, ctx, oracle_mod, s16, dtype):
+    ctx.set_option(sm.OPT_HEAVY_MODE, 1)
+    full_check(sm, ctx, s16, None, dtype, oracle_mod, False, "s16 global")
+    assert ctx.stats()["global_slots"] > 0
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("units", [1, 2, 4])
+def test_forced_heavy_rows(sm, ctx, oracle_mod, mode, units):
+    # every row with more than 32 outputs takes the heavy-row path
+    A = syn.rmat(13, 8, 0x77, np.float32)
+    ctx.set_option(sm.OPT_LDS_ROW_MAX, 32)
+    ctx.set_option(sm.OPT_HEAVY_MODE, mode)
+    ctx.set_option(sm.OPT_WINDOW_UNITS, units)
+    for dtype in (np.float32, np.float64):
+        if dtype == np.float64 and units == 4:
+            continue
+        full_check(sm, ctx, A, None, dtype, oracle_mod, False, f"forced heavy mode={mode} units={units}")
+        assert ctx.stats()["rows_heavy"] > 100
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_rectangular(sm, ctx, oracle_mod, dtype):
+    A = syn.rmat(14, 8, 0x5EED0501, dtype)
+    B = syn.uniform_k_per_row(A.cols, 4096, 16, 0xB, dtype)
+    full_check(sm, ctx, A, B, dtype, oracle_mod, False, "rect")
+    # and with more columns than one heavy-row window
+    B = syn.uniform_k_per_row(A.cols, 100_000, 16, 0xC, dtype)
+    ctx.set_option(sm.OPT_LDS_ROW_MAX, 64)
+    full_check(sm, ctx, A, B, dtype, oracle_mod, False, "rect wide")
+
+
+def test_structured_cases(sm, ctx, oracle_mod):
+    n = 3000
+    cases = {
+        "identity_left": (syn.identity(n), syn.rmat(11, 4, 3, np.float64)),
+        "permutation": (syn.permutation(2048, 4), syn.rmat(11, 4, 5, np.float64)),
+        "diagonal_right": (syn.rmat(11, 4, 6, np.float64), syn.diagonal(2048, 7)),
+        "adversarial_stride": (syn.rmat(11, 4, 8, np.float64), syn.strided_columns(2048, 1 << 20, 64, 1024, 9)),
+        "dense_rows": (syn.dense_rows(64, 64, [0, 5, 63], 10, np.float64), syn.dense_rows(64, 20000, range(64), 11, np.float64)),
+        "n_equals_1": (syn.random_sparse(500, 40, 0.3, 12), syn.random_sparse(40, 1, 0.5, 13)),
+        "empty_A": (syn.empty(100, 50), syn.random_sparse(50, 60, 0.2, 14)),
+        "empty_B": (syn.random_sparse(100, 50, 0.2, 15), syn.empty(50, 60)),
+        "no_rows": (syn.empty(0, 50), syn.random_sparse(50, 60, 0.2, 16)),
+    }
+    for name, (A, B) in cases.items():
+        if name == "identity_left":
+            A = syn.identity(B.rows)
+        for dtype in (np.float32, np.float64):
+            full_check(sm, ctx, A.astype(dtype), B.astype(dtype), dtype, oracle_mod, False, name)
+
+
+def test_cancellation_keeps_structural_zero(sm, ctx, oracle_mod):
+    A = syn.CSR(2, 2, np.array([0, 2, 3], np.int32), np.array([0, 1, 1], np.int32), np.array([1.0, 1.0, 2.0]))
+    B = syn.CSR(2, 3, np.array([0, 2, 4], np.int32), np.array([0, 2, 0, 2], np.int32), np.array([1.0, 3.0, -1.0, 5.0]))
+    rp, col, val = run(sm, ctx, A, B, np.float64)
+    assert rp.tolist() == [0, 2, 4] and col.tolist() == [0, 2, 0, 2]
+    assert val.tolist() == [0.0, 8.0, -2.0, 10.0]
+
+
+def test_repeat_numeric_and_determinism(sm, ctx, oracle_mod, torch_mod):
+    torch = torch_mod
+    A = syn.rmat(14, 8, 0x99, np.float32)
+    dA = sm.to_device(A)
+    rp = torch.empty(A.rows + 1, dtype=torch.int64, device="cuda")
+    nnz = ctx.symbolic(dA, dA, rp)
+    col = torch.empty(nnz, dtype=torch.int32, device="cuda")
+    val = torch.empty(nnz, dtype=torch.float32, device="cuda")
+    ctx.numeric(dA, dA, rp, col, val)
+    col0 = col.clone()
+    for _ in range(3):
+        col.fill_(-7)
+        ctx.numeric(dA, dA, rp, col, val)
+        assert torch.equal(col, col0)
+    # new values, same structure: the plan is reused
+    A2 = syn.CSR(A.rows, A.cols, A.row_ptr, A.col_idx, (A.val * -0.5).astype(np.float32))
+    dA.val.copy_(torch.from_numpy(A2.val))
+    ctx.numeric(dA, dA, rp, col, val)
+    check_rows(rp.cpu().numpy(), col.cpu().numpy(), val.cpu().numpy(), oracle_mod.spgemm(A2, A2), np.float32, "revalued")
+
+
+def test_errors(sm, ctx, torch_mod):
+    torch = torch_mod
+    A = syn.rmat(10, 4, 1, np.float32)
+    dA = sm.to_device(A)
+    rp = torch.empty(A.rows + 1, dtype=torch.int64, device="cuda")
+    col = torch.empty(10, dtype=torch.int32, device="cuda")
+    val = torch.empty(10, dtype=torch.float32, device="cuda")
+    with pytest.raises(sm.SmashError) as e:
+        ctx.numeric(dA, dA, rp, col, val)           # no symbolic plan
+    assert e.value.status == 7
+    B = syn.rmat(9, 4, 1, np.float32)
+    with pytest.raises(sm.SmashError) as e:
+        ctx.symbolic(dA, sm.to_device(B), rp)       # A.cols != B.rows
+    assert e.value.status == 1
+    # invalid CSR: unsorted columns, column out of range, bad row_ptr
+    bad = [
+        syn.CSR(2, 4, np.array([0, 2, 3], np.int32), np.array([2, 1, 0], np.int32), np.ones(3, np.float32)),
+        syn.CSR(2, 4, np.array([0, 2, 3], np.int32), np.array([0, 4, 0], np.int32), np.ones(3, np.float32)),
+        syn.CSR(2, 4, np.array([0, 3, 2], np.int32), np.array([0, 1, 2], np.int32), np.ones(3, np.float32)),
+    ]
+    good = syn.random_sparse(4, 4, 0.5, 3, np.float32)
+    for M in bad:
+        dM = sm.to_device(M)
+        rp2 = torch.empty(3, dtype=torch.int64, device="cuda")
+        with pytest.raises(sm.SmashError) as e:
+            ctx.symbolic(dM, sm.to_device(good), rp2)
+        assert e.value.status == 2
+    with pytest.raises(sm.SmashError):
+        ctx.set_option(sm.OPT_LDS_ROW_MAX, 5)
