@@ -1,0 +1,181 @@
+"""Benchmark of the row-wise hash SpGEMM C = A * B on one MI355X.
+
+A step is one whole product through the C ABI (symbolic phase, nnz(C)
+readback, output allocation from torch's caching allocator, numeric phase)
+on inputs already resident in HBM.  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--workload s19|s16|s10|rect] [--dtype f32|f64]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import synthetic  # noqa: E402
+from paper_2105_14156_amd import metrics  # noqa: E402
+
+METRIC = "SpGEMM GFLOP/s (2·products/s) + HBM GB/s; learned/batched vs plain at exact C"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "s19": ("rmat_s19_ef16_AxA", synthetic.workload_s19, "RMAT scale 19, edge factor 16, a/b/c/d=.57/.19/.19/.05, C=A*A"),
+    "s16": ("rmat_s16_ef16_AxA", synthetic.workload_s16, "RMAT scale 16, edge factor 16, C=A*A"),
+    "s10": ("rmat_s10_ef8_AxA", synthetic.workload_small, "RMAT scale 10, edge factor 8, C=A*A"),
+    "rect": ("rmat_s21_ef8_x_uniform4096k16", synthetic.workload_rect, "RMAT scale 21 ef 8 times 2^21x4096 (16/row)"),
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="s19", choices=sorted(WORKLOADS))
+    ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--heavy-mode", type=int, default=0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle time for the CPU baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(A, B, target_s):
+    """The oracle timed on a seeded row sample of the same product (all host
+    threads up to 16), scaled to GFLOP/s of 2 x products."""
+    import oracle
+    ub = oracle.products_per_row(A, B)
+    threads = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()))
+    # calibrate on a small sample, then size the timed sample to about target_s
+    total = int(ub.sum())
+    rng_rows = np.argsort(synthetic.uniform01(0xBA5E, 0, A.rows), kind="stable")
+    pref = np.cumsum(ub[rng_rows])
+    probe_n = int(np.searchsorted(pref, min(total, 5e7))) + 1
+    t0 = time.perf_counter()
+    oracle.spgemm(A, B, rows=np.sort(rng_rows[:probe_n]), threads=threads, with_stats=False)
+    t_probe = time.perf_counter() - t0
+    rate = max(float(pref[probe_n - 1]) / max(t_probe, 1e-6), 1.0)
+    want = min(total, int(rate * target_s))
+    n_rows = int(np.searchsorted(pref, want)) + 1
+    sel = np.sort(rng_rows[:n_rows])
+    prods = int(ub[sel].sum())
+    t0 = time.perf_counter()
+    oracle.spgemm(A, B, rows=sel, threads=threads, with_stats=False)
+    t = time.perf_counter() - t0
+    return {"value": round(2.0 * prods / t / 1e9, 4), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n_rows} seeded random rows of {A.rows} ({prods} of {total} products, "
+                      f"{prods / total:.1%}), {t:.1f} s wall"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
+              f"(the multi-GPU row sharding is described in DESIGN.md, not built)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2105_14156_amd import smash
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    name, make, desc = WORKLOADS[args.workload]
+    npdt = np.float32 if args.dtype == "f32" else np.float64
+    vbytes = 4 if args.dtype == "f32" else 8
+    t0 = time.perf_counter()
+    w = make(npdt)
+    A, B = w.A, w.B
+    log(f"workload {name}: A {A.rows}x{A.cols} nnz {A.nnz}, B {B.rows}x{B.cols} nnz {B.nnz} "
+        f"(generated in {time.perf_counter() - t0:.1f} s)")
+    dA = smash.to_device(A)
+    dB = dA if B is A else smash.to_device(B)
+    ctx = smash.Context(0)
+    ctx.set_option(smash.OPT_HEAVY_MODE, args.heavy_mode)
+    stream = torch.cuda.current_stream()
+
+    C = None
+    for i in range(args.warmup):
+        C = None
+        C = ctx.spgemm(dA, dB, stream)
+        log(f"warmup {i + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+    st = ctx.stats()
+    products, nnz_c = st["products"], st["nnz_c"]
+
+    ctx.set_option(smash.OPT_TIMING, 1)
+    ctx.reset_kernel_times()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        C = None
+        C = ctx.spgemm(dA, dB, stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    log(f"timed {args.steps} steps in {elapsed:.3f} s")
+    kt = ctx.kernel_times()
+    ctx.set_option(smash.OPT_TIMING, 0)
+    st = ctx.stats()
+
+    ms_step = elapsed / args.steps * 1e3
+    gflops = metrics.gflops(products, elapsed / args.steps)
+    alg = metrics.algorithmic_bytes(A.rows, B.rows, A.nnz, B.nnz, nnz_c, vbytes)
+    path_gbs = alg / (elapsed / args.steps) / 1e9
+
+    # dominant kernel; its algorithmic bytes per launch are its share of C's
+    # entries times the path's compulsory bytes (read A and B, write C once)
+    dom = max(kt.items(), key=lambda kv: kv[1][1])
+    dname, (dlaunch, dms) = dom
+    nnz_heavy, nnz_dense = st["nnz_heavy"], st["nnz_dense"]
+    entries = {"num_rows": nnz_c - nnz_heavy, "sym_rows": nnz_c - nnz_heavy, "num_seg": nnz_heavy - nnz_dense,
+               "num_dense": nnz_dense, "sym_heavy": nnz_heavy, "num_global": nnz_heavy, "sym_global": nnz_heavy}
+    share = entries.get(dname, nnz_c) / max(1, nnz_c)
+    launches_per_step = dlaunch / args.steps
+    per_launch_bytes = alg * share / max(1e-9, launches_per_step)
+    avg_ms = dms / max(1, dlaunch)
+    achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+
+    out = {
+        "metric": METRIC,
+        "value": round(gflops, 3),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {"workload": name, "description": desc, "path": "plain two-phase (symbolic + numeric)",
+                   "heavy_mode": "lds_segments" if args.heavy_mode == 0 else "global_hash",
+                   "rows": A.rows, "cols": B.cols, "nnz_a": A.nnz, "nnz_b": B.nnz, "nnz_c": nnz_c,
+                   "products": products},
+        "hbm_gbs_algorithmic": round(path_gbs, 2),
+        "path_roofline_frac": round(path_gbs / HBM_PEAK_GBS, 4),
+        "roofline": {"bound": "hbm", "kernel": dname, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "launches_per_step": launches_per_step, "avg_launch_ms": round(avg_ms, 4),
+                     "alg_bytes_per_launch": int(per_launch_bytes), "c_entry_share": round(share, 4)},
+        "kernel_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in kt.items() if v[0]},
+        "stats": st,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(A, B, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -68,37 +68,39 @@ typedef struct {
     const void *val;          /* nnz entries of the call's dtype */
 } smash_csr;
 
-/* Options (smash_set_option / smash_get_option). */
+/* Options (smash_set_option / smash_get_option).  Setting an option drops
+ * the plan of the last symbolic call. */
 typedef enum {
     /* 1 = check the CSR preconditions of A and B on the device (default 1). */
     SMASH_OPT_VALIDATE = 0,
     /* Rows whose output bound min(products, cols) exceeds this many
-     * entries leave the LDS hash path for the heavy-row path.  Range
-     * 32..4096, default 4096. */
+     * entries leave the LDS row tables for the heavy-row path.  Range
+     * 32..1024, default 1024. */
     SMASH_OPT_LDS_ROW_MAX = 1,
-    /* Heavy-row path: 0 = column-windowed LDS accumulation (default),
-     * 1 = global-memory hash table (the fallback of the paper's third
-     * version, "Fragmenting Memory": hash table moved to DRAM). */
+    /* Heavy-row path: 0 = column segments merged in LDS, hashed or, for
+     * chunks denser than a quarter, accumulated by column (default);
+     * 1 = one hash table per row in global memory (the paper's third
+     * version, "Fragmenting Memory", moves the table to DRAM). */
     SMASH_OPT_HEAVY_MODE = 2,
-    /* Column width of one numeric window of the windowed heavy path, in
-     * units of 8192 columns: 1, 2 or 4 (FP64 allows 1 or 2).  Default: 4
-     * for FP32, 2 for FP64 (value 0). */
-    SMASH_OPT_WINDOW_UNITS = 3,
     /* 1 = record HIP events around every kernel launch and accumulate the
      * elapsed time per kernel (smash_kernel_time).  Default 0. */
-    SMASH_OPT_TIMING = 4
+    SMASH_OPT_TIMING = 3,
+    SMASH_OPT_COUNT = 4
 } smash_option;
 
 /* Counters of the last symbolic/numeric call (smash_get_stats). */
 typedef struct {
-    int64_t rows;            /* A.rows */
-    int64_t products;        /* sum over rows of the products (multiply-adds) */
-    int64_t nnz_c;           /* nnz(C) */
-    int64_t rows_empty;      /* rows with no product */
-    int64_t rows_lds;        /* rows merged in an LDS hash table */
-    int64_t rows_heavy;      /* rows on the heavy-row path */
-    int64_t heavy_windows;   /* non-empty column windows of heavy rows (windowed mode) */
-    int64_t global_slots;    /* global hash table slots used (global mode) */
+    int64_t rows;               /* A.rows */
+    int64_t products;           /* sum over rows of the products (multiply-adds) */
+    int64_t nnz_c;              /* nnz(C) */
+    int64_t rows_empty;         /* rows with no product */
+    int64_t rows_lds;           /* rows merged in an LDS row table */
+    int64_t rows_heavy;         /* rows on the heavy-row path */
+    int64_t heavy_segments;     /* hashed column segments of heavy rows */
+    int64_t heavy_dense_chunks; /* column chunks of heavy rows accumulated by column */
+    int64_t global_slots;       /* global hash table slots (global mode) */
+    int64_t nnz_heavy;          /* entries of C in heavy rows */
+    int64_t nnz_dense;          /* entries of C in dense chunks of heavy rows */
 } smash_stats;
 
 /* Allocation callback of smash_spgemm: return device memory of at least

@@ -25,15 +25,15 @@ using namespace smash;
 namespace {
 
 enum KernelId {
-    K_VALIDATE, K_ANALYZE, K_BIN_OFFSETS, K_SCATTER, K_SYM_LDS, K_SYM_HEAVY, K_SYM_GLOBAL, K_FILL,
-    K_SCAN_REDUCE, K_SCAN_TOP, K_SCAN_APPLY, K_NUM_BINS, K_CHUNK_PREFIX, K_BSPLIT, K_NUM_LDS,
-    K_NUM_HEAVY, K_NUM_GLOBAL, K_COUNT
+    K_VALIDATE, K_ANALYZE, K_BIN_COUNT, K_BIN_SCAN, K_SCATTER, K_SYM_ROWS, K_BSPLIT, K_SYM_HEAVY,
+    K_SYM_GLOBAL, K_FILL, K_SCAN_REDUCE, K_SCAN_TOP, K_SCAN_APPLY, K_NUM_BINS, K_CHUNK_PREFIX,
+    K_SEG_PLAN, K_SEG_SCAN, K_NUM_ROWS, K_NUM_SEG, K_NUM_DENSE, K_NUM_GLOBAL, K_COUNT
 };
 
 const char *const kKernelNames[K_COUNT] = {
-    "validate", "analyze", "bin_offsets", "scatter", "sym_lds", "sym_heavy", "sym_global", "fill",
-    "scan_reduce", "scan_top", "scan_apply", "num_bins", "chunk_prefix", "bsplit", "num_lds",
-    "num_heavy_dense", "num_global"};
+    "validate", "analyze", "bin_count", "bin_scan", "scatter", "sym_rows", "bsplit", "sym_heavy",
+    "sym_global", "fill", "scan_reduce", "scan_top", "scan_apply", "num_bins", "chunk_prefix",
+    "seg_plan", "seg_scan", "num_rows", "num_seg", "num_dense", "num_global"};
 
 // Grow-only device buffer.
 struct Arena {
@@ -54,6 +54,13 @@ struct Carve {
     }
 };
 
+size_t carve_size(std::initializer_list<size_t> parts)
+{
+    size_t s = 0;
+    for (size_t p : parts) s += ((p + 255) & ~size_t(255)) + 256;
+    return s;
+}
+
 struct Plan {
     bool valid = false;
     smash_csr A{}, B{};
@@ -61,12 +68,16 @@ struct Plan {
     int64_t m = 0, n = 0;
     int heavy_mode = 0, lds_row_max = 0;
     DevHdr hdr{};
-    int nchunks = 0;
+    int nchunks = 0, nblk = 0;
     long long *ub = nullptr;
     int *cap = nullptr, *nnzc = nullptr, *sym_perm = nullptr, *num_perm = nullptr;
     unsigned char *sym_bin = nullptr, *num_bin = nullptr;
-    long long *bsum = nullptr, *goff_sym = nullptr, *goff_num = nullptr;
-    int *wcnt = nullptr, *woff = nullptr;
+    int *bcount = nullptr;
+    unsigned long long *bprod = nullptr;
+    long long *bw = nullptr;
+    long long *bsum = nullptr, *gsz = nullptr, *goff_sym = nullptr, *goff_num = nullptr;
+    int *bsplit = nullptr, *wcnt = nullptr, *woff = nullptr, *seg_bcount = nullptr;
+    Seg *segs = nullptr;
 };
 
 struct Pending {
@@ -79,10 +90,10 @@ struct Pending {
 struct smash_ctx_s {
     int device = 0;
     std::string err;
-    int64_t opt[5] = {1, 4096, 0, 0, 0};
+    int64_t opt[5] = {1, 1024, 0, 0, 0};
     DevHdr *h_hdr = nullptr;   // pinned host mirror
     DevHdr *d_hdr = nullptr;
-    Arena plan_mem, heavy_mem, tmp_mem, gkeys, gvals;
+    Arena plan_mem, heavy_mem, gkeys, gvals;
     Plan plan;
     smash_stats stats{};
     std::vector<hipEvent_t> event_pool;
@@ -111,6 +122,12 @@ smash_status fail(smash_ctx c, smash_status s, const char *fmt, ...)
             return fail((c), SMASH_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_));      \
     } while (0)
 
+#define TRY(...)                           \
+    do {                                   \
+        smash_status s_ = (__VA_ARGS__);   \
+        if (s_ != SMASH_OK) return s_;     \
+    } while (0)
+
 // Makes the context's device current for the scope of one call.
 struct DeviceGuard {
     int prev = -1;
@@ -135,9 +152,9 @@ smash_status ensure(smash_ctx c, Arena &a, size_t bytes, hipStream_t s)
         HIP_TRY(c, hipStreamSynchronize(s));
         HIP_TRY(c, hipFree(a.ptr));
         a.ptr = nullptr;
-        a.cap = 0;
     }
     size_t want = std::max(bytes, a.cap + a.cap / 2);
+    a.cap = 0;
     if (hipMalloc(&a.ptr, want) != hipSuccess) {
         (void)hipGetLastError();
         if (hipMalloc(&a.ptr, bytes) != hipSuccess) {
@@ -199,12 +216,6 @@ void collect_times(smash_ctx c)
     c->pending.clear();
 }
 
-#define TRY(...)                           \
-    do {                                   \
-        smash_status s_ = (__VA_ARGS__);   \
-        if (s_ != SMASH_OK) return s_;     \
-    } while (0)
-
 smash_status check_csr(smash_ctx c, const smash_csr *M, const char *name, bool need_val)
 {
     if (!M) return fail(c, SMASH_ERR_INVALID_ARG, "%s is NULL", name);
@@ -232,7 +243,7 @@ unsigned blocks_for(long long items, int per_block)
 
 template <int LOGT>
 struct BinShape {
-    static constexpr int WPR = LOGT <= 10 ? 1 : (1 << (LOGT - 9)) / 1;   // 2048->4, 4096->8, 8192->16
+    static constexpr int WPR = LOGT <= 10 ? 1 : (1 << (LOGT - 9));   // 2048 slots -> 4 waves
     static constexpr int RPW = LOGT <= 10 ? 4 : 1;
     static constexpr int THREADS = kWave * WPR * RPW;
 };
@@ -241,8 +252,8 @@ template <int LOGT>
 smash_status launch_sym_bin(smash_ctx c, hipStream_t s, const Plan &p, int cnt, const int *rows)
 {
     using S = BinShape<LOGT>;
-    return launch(c, K_SYM_LDS, s, [&] {
-        k_sym_lds<LOGT, S::WPR, S::RPW><<<blocks_for(cnt, S::RPW), S::THREADS, 0, s>>>(
+    return launch(c, K_SYM_ROWS, s, [&] {
+        k_sym_rows<LOGT, S::WPR, S::RPW><<<blocks_for(cnt, S::RPW), S::THREADS, 0, s>>>(
             p.A.row_ptr, p.A.col_idx, p.B.row_ptr, p.B.col_idx, rows, cnt, p.nnzc, &c->d_hdr->error);
     });
 }
@@ -252,8 +263,8 @@ smash_status launch_num_bin(smash_ctx c, hipStream_t s, const Plan &p, int cnt, 
                             const V *Bval, const int64_t *crp, int32_t *ccol, V *cval)
 {
     using S = BinShape<LOGT>;
-    return launch(c, K_NUM_LDS, s, [&] {
-        k_num_lds<V, LOGT, S::WPR, S::RPW><<<blocks_for(cnt, S::RPW), S::THREADS, 0, s>>>(
+    return launch(c, K_NUM_ROWS, s, [&] {
+        k_num_rows<V, LOGT, S::WPR, S::RPW><<<blocks_for(cnt, S::RPW), S::THREADS, 0, s>>>(
             p.A.row_ptr, p.A.col_idx, Aval, p.B.row_ptr, p.B.col_idx, Bval, rows, cnt, (const long long *)crp, ccol,
             cval, &c->d_hdr->error);
     });
@@ -265,7 +276,7 @@ smash_status run_sym_bins(smash_ctx c, hipStream_t s, const Plan &p)
     const int *perm = p.sym_perm;
 #define SYM_BIN(LT)                                                                               \
     if (b.count[LT - kMinLogT]) TRY(launch_sym_bin<LT>(c, s, p, b.count[LT - kMinLogT], perm + b.offset[LT - kMinLogT]));
-    SYM_BIN(6) SYM_BIN(7) SYM_BIN(8) SYM_BIN(9) SYM_BIN(10) SYM_BIN(11) SYM_BIN(12) SYM_BIN(13)
+    SYM_BIN(6) SYM_BIN(7) SYM_BIN(8) SYM_BIN(9) SYM_BIN(10) SYM_BIN(11)
 #undef SYM_BIN
     return SMASH_OK;
 }
@@ -280,37 +291,55 @@ smash_status run_num_bins(smash_ctx c, hipStream_t s, const Plan &p, const V *Av
     if (b.count[LT - kMinLogT])                                                                       \
         TRY(launch_num_bin<V, LT>(c, s, p, b.count[LT - kMinLogT], perm + b.offset[LT - kMinLogT], Aval, Bval, crp, \
                                   ccol, cval));
-    NUM_BIN(6) NUM_BIN(7) NUM_BIN(8) NUM_BIN(9) NUM_BIN(10) NUM_BIN(11) NUM_BIN(12) NUM_BIN(13)
+    NUM_BIN(6) NUM_BIN(7) NUM_BIN(8) NUM_BIN(9) NUM_BIN(10) NUM_BIN(11)
 #undef NUM_BIN
     return SMASH_OK;
 }
 
-size_t sym_heavy_lds(int64_t ncols)
+// Binning of the rows by `bin_of` into `perm` (block histograms, one scan
+// block, scatter), with the global-hash table sizes of heavy rows when
+// gsize_of is given.
+smash_status bin_rows(smash_ctx c, hipStream_t s, const Plan &p, const unsigned char *bin_of, const long long *ub,
+                      const int *wt, BinHdr *dh, int *perm, const int *gsize_of)
 {
-    const int wbits = ncols < kSymWindowBits ? (int)((ncols + 31) & ~31LL) : kSymWindowBits;
-    return (size_t)wbits / 32 * 4 + 2 * (kHeavyThreads / kWave) * kWave * sizeof(int);
+    const int m = (int)p.m;
+    TRY(launch(c, K_BIN_COUNT, s, [&] {
+        k_bin_count<<<p.nblk, 256, 0, s>>>(m, bin_of, ub, wt, p.bcount, ub ? p.bprod : nullptr, wt ? p.bw : nullptr);
+    }));
+    TRY(launch(c, K_BIN_SCAN, s, [&] {
+        k_bin_scan<<<1, 256, 0, s>>>(p.nblk, p.bcount, ub ? p.bprod : nullptr, wt ? p.bw : nullptr, dh,
+                                     ub ? &c->d_hdr->products : nullptr);
+    }));
+    TRY(launch(c, K_SCATTER, s, [&] {
+        k_scatter<<<p.nblk, 256, 0, s>>>(m, bin_of, p.bcount, dh, perm, gsize_of, p.gsz);
+    }));
+    return SMASH_OK;
 }
 
-template <typename V, int UNITS>
-size_t num_heavy_lds()
+// out[0..n] = exclusive prefix of cnt[0..n) (int or int64), total in *total.
+template <typename TIn>
+smash_status scan_counts(smash_ctx c, hipStream_t s, long long n, const TIn *cnt, long long *bsum,
+                         long long *out, long long *total)
 {
-    constexpr int W = UNITS * kChunkCols;
-    return (size_t)W * sizeof(V) + W / 32 * 4 + 2 * (kHeavyThreads / kWave) * kWave * sizeof(int) +
-           (kHeavyThreads / kWave) * kWave * sizeof(V);
+    const int nb = (int)blocks_for(std::max<long long>(n, 1), kScanItems);
+    TRY(launch(c, K_SCAN_REDUCE, s, [&] { k_scan_reduce<TIn><<<nb, kScanThreads, 0, s>>>(n, cnt, bsum); }));
+    TRY(launch(c, K_SCAN_TOP, s, [&] { k_scan_top<<<1, kScanThreads, 0, s>>>(nb, bsum, total); }));
+    TRY(launch(c, K_SCAN_APPLY, s, [&] { k_scan_apply<TIn><<<nb, kScanThreads, 0, s>>>(n, cnt, bsum, total, out); }));
+    return SMASH_OK;
 }
 
-template <typename V, int UNITS>
-smash_status launch_num_heavy(smash_ctx c, hipStream_t s, const Plan &p, int H, const V *Aval, const V *Bval,
-                              const int *bsplit, int nwin, const int64_t *crp, int32_t *ccol, V *cval)
+template <typename V, int LOGT>
+smash_status launch_seg_bin(smash_ctx c, hipStream_t s, const Plan &p, int bin, const V *Aval, const V *Bval,
+                            const int64_t *crp, int32_t *ccol, V *cval)
 {
-    const size_t lds = num_heavy_lds<V, UNITS>();
-    (void)hipFuncSetAttribute((const void *)k_num_heavy_dense<V, UNITS>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds);
-    const int *rows = p.sym_perm + p.hdr.sym.offset[kBinHeavy];
-    return launch(c, K_NUM_HEAVY, s, [&] {
-        k_num_heavy_dense<V, UNITS><<<(unsigned)((long long)H * nwin), kHeavyThreads, lds, s>>>(
-            p.A.row_ptr, p.A.col_idx, Aval, p.B.col_idx, Bval, bsplit, rows, nwin, p.nchunks, p.wcnt, p.woff,
-            (const long long *)crp, ccol, cval, &c->d_hdr->error, &c->d_hdr->heavy_windows);
+    const int cnt = p.hdr.seg.count[bin];
+    if (!cnt) return SMASH_OK;
+    const int *hrows = p.sym_perm + p.hdr.sym.offset[kBinHeavy];
+    const Seg *segs = p.segs + p.hdr.seg.offset[bin];
+    return launch(c, K_NUM_SEG, s, [&] {
+        k_num_seg<V, LOGT, 256><<<cnt, 256, 0, s>>>(p.A.row_ptr, p.A.col_idx, Aval, p.B.col_idx, Bval, p.bsplit,
+                                                     hrows, segs, p.nchunks, p.woff, (const long long *)crp, ccol,
+                                                     cval, &c->d_hdr->error);
     });
 }
 
@@ -322,25 +351,22 @@ smash_status numeric_impl(smash_ctx c, hipStream_t s, const Plan &p, const V *Av
     const int H = p.hdr.sym.count[kBinHeavy];
     if (H == 0) return SMASH_OK;
     if (p.heavy_mode == 0) {
-        int units = (int)c->opt[SMASH_OPT_WINDOW_UNITS];
-        if (units == 0) units = sizeof(V) == 4 ? 4 : 2;
-        if (sizeof(V) == 8 && units > 2) units = 2;
-        const int W = units * kChunkCols;
-        const int nwin = (int)((p.n + W - 1) / W);
-        const long long kdim = p.B.rows;
-        TRY(ensure(c, c->tmp_mem, (size_t)(kdim * (nwin + 1)) * sizeof(int), s));
-        int *bsplit = (int *)c->tmp_mem.ptr;
-        TRY(launch(c, K_BSPLIT, s, [&] {
-            k_bsplit<<<blocks_for(kdim * (nwin + 1), 256), 256, 0, s>>>((int)kdim, W, nwin, p.B.row_ptr, p.B.col_idx,
-                                                                       bsplit);
-        }));
-        switch (units) {
-        case 1: return launch_num_heavy<V, 1>(c, s, p, H, Aval, Bval, bsplit, nwin, crp, ccol, cval);
-        case 2: return launch_num_heavy<V, 2>(c, s, p, H, Aval, Bval, bsplit, nwin, crp, ccol, cval);
-        default:
-            if constexpr (sizeof(V) == 4) return launch_num_heavy<V, 4>(c, s, p, H, Aval, Bval, bsplit, nwin, crp, ccol, cval);
-            return fail(c, SMASH_ERR_INVALID_ARG, "window units %d not supported for this dtype", units);
+        TRY(launch_seg_bin<V, 8>(c, s, p, 0, Aval, Bval, crp, ccol, cval));
+        TRY(launch_seg_bin<V, 10>(c, s, p, 1, Aval, Bval, crp, ccol, cval));
+        TRY(launch_seg_bin<V, 12>(c, s, p, 2, Aval, Bval, crp, ccol, cval));
+        const int nd = p.hdr.seg.count[kSegDense];
+        if (nd) {
+            const size_t lds = (size_t)kChunkCols * (sizeof(V) + sizeof(int));
+            (void)hipFuncSetAttribute((const void *)k_num_dense<V>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            const int *hrows = p.sym_perm + p.hdr.sym.offset[kBinHeavy];
+            const Seg *segs = p.segs + p.hdr.seg.offset[kSegDense];
+            TRY(launch(c, K_NUM_DENSE, s, [&] {
+                k_num_dense<V><<<nd, kDenseThreads, lds, s>>>(p.A.row_ptr, p.A.col_idx, Aval, p.B.col_idx, Bval,
+                                                             p.bsplit, hrows, segs, p.nchunks, p.woff,
+                                                             (const long long *)crp, ccol, cval, &c->d_hdr->error);
+            }));
         }
+        return SMASH_OK;
     }
     // global-memory hash tables
     const unsigned long long slots = p.hdr.gneed[1];
@@ -350,10 +376,10 @@ smash_status numeric_impl(smash_ctx c, hipStream_t s, const Plan &p, const V *Av
     (void)hipFuncSetAttribute((const void *)k_num_global<V>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     const int *rows = p.num_perm + p.hdr.num.offset[kBinHeavy];
     return launch(c, K_NUM_GLOBAL, s, [&] {
-        k_num_global<V><<<H, kHeavyThreads, lds, s>>>(p.A.row_ptr, p.A.col_idx, Aval, p.B.row_ptr, p.B.col_idx, Bval,
-                                                      rows, (int)p.n, p.goff_num, (int *)c->gkeys.ptr,
-                                                      (V *)c->gvals.ptr, (const long long *)crp, ccol, cval,
-                                                      &c->d_hdr->error);
+        k_num_global<V><<<H, kGlobalThreads, lds, s>>>(p.A.row_ptr, p.A.col_idx, Aval, p.B.row_ptr, p.B.col_idx, Bval,
+                                                       rows, (int)p.n, p.goff_num, (int *)c->gkeys.ptr,
+                                                       (V *)c->gvals.ptr, (const long long *)crp, ccol, cval,
+                                                       &c->d_hdr->error);
     });
 }
 
@@ -425,7 +451,7 @@ void smash_destroy(smash_ctx c)
 {
     if (!c) return;
     DeviceGuard g(c->device);
-    for (Arena *a : {&c->plan_mem, &c->heavy_mem, &c->tmp_mem, &c->gkeys, &c->gvals})
+    for (Arena *a : {&c->plan_mem, &c->heavy_mem, &c->gkeys, &c->gvals})
         if (a->ptr) (void)hipFree(a->ptr);
     if (c->d_hdr) (void)hipFree(c->d_hdr);
     if (c->h_hdr) (void)hipHostFree(c->h_hdr);
@@ -448,13 +474,10 @@ smash_status smash_set_option(smash_ctx c, smash_option opt, int64_t v)
         if (v != 0 && v != 1) return fail(c, SMASH_ERR_INVALID_ARG, "option %d takes 0 or 1", (int)opt);
         break;
     case SMASH_OPT_LDS_ROW_MAX:
-        if (v < 32 || v > 4096) return fail(c, SMASH_ERR_INVALID_ARG, "LDS row max must be in [32, 4096]");
+        if (v < 32 || v > 1024) return fail(c, SMASH_ERR_INVALID_ARG, "LDS row max must be in [32, 1024]");
         break;
     case SMASH_OPT_HEAVY_MODE:
         if (v != 0 && v != 1) return fail(c, SMASH_ERR_INVALID_ARG, "heavy mode is 0 (windowed) or 1 (global hash)");
-        break;
-    case SMASH_OPT_WINDOW_UNITS:
-        if (v != 0 && v != 1 && v != 2 && v != 4) return fail(c, SMASH_ERR_INVALID_ARG, "window units are 0, 1, 2 or 4");
         break;
     default: return fail(c, SMASH_ERR_INVALID_ARG, "unknown option %d", (int)opt);
     }
@@ -465,7 +488,7 @@ smash_status smash_set_option(smash_ctx c, smash_option opt, int64_t v)
 
 smash_status smash_get_option(smash_ctx c, smash_option opt, int64_t *v)
 {
-    if (!c || !v || (int)opt < 0 || (int)opt > SMASH_OPT_TIMING) return SMASH_ERR_INVALID_ARG;
+    if (!c || !v || (int)opt < 0 || (int)opt >= SMASH_OPT_COUNT) return SMASH_ERR_INVALID_ARG;
     *v = c->opt[opt];
     return SMASH_OK;
 }
@@ -492,7 +515,7 @@ smash_status smash_spgemm_symbolic(smash_ctx c, const smash_csr *A, const smash_
     p.n = B->cols;
     p.heavy_mode = (int)c->opt[SMASH_OPT_HEAVY_MODE];
     p.lds_row_max = (int)c->opt[SMASH_OPT_LDS_ROW_MAX];
-    p.nchunks = (int)((p.n + kChunkCols - 1) / kChunkCols);
+    p.nchunks = (int)std::max<int64_t>(1, (p.n + kChunkCols - 1) / kChunkCols);
     const int64_t m = p.m;
     c->stats = smash_stats();
     c->stats.rows = m;
@@ -500,19 +523,18 @@ smash_status smash_spgemm_symbolic(smash_ctx c, const smash_csr *A, const smash_
     HIP_TRY(c, hipMemsetAsync(c->d_hdr, 0, sizeof(DevHdr), s));
     if (c->opt[SMASH_OPT_VALIDATE]) {
         TRY(launch(c, K_VALIDATE, s, [&] {
-            k_validate<<<blocks_for(A->rows + 1, 256), 256, 0, s>>>((int)A->rows, (int)A->cols, A->nnz, A->row_ptr,
-                                                                    A->col_idx, kErrCsrA, &c->d_hdr->error);
+            k_validate<<<blocks_for(std::max<int64_t>(A->rows, 1), 4), 256, 0, s>>>(
+                (int)A->rows, (int)A->cols, A->nnz, A->row_ptr, A->col_idx, kErrCsrA, &c->d_hdr->error);
         }));
         TRY(launch(c, K_VALIDATE, s, [&] {
-            k_validate<<<blocks_for(B->rows + 1, 256), 256, 0, s>>>((int)B->rows, (int)B->cols, B->nnz, B->row_ptr,
-                                                                    B->col_idx, kErrCsrB, &c->d_hdr->error);
+            k_validate<<<blocks_for(std::max<int64_t>(B->rows, 1), 4), 256, 0, s>>>(
+                (int)B->rows, (int)B->cols, B->nnz, B->row_ptr, B->col_idx, kErrCsrB, &c->d_hdr->error);
         }));
-        TRY(read_hdr(c, s));
-        TRY(device_errors(c, c->h_hdr->error));
     }
     if (m == 0) {
         HIP_TRY(c, hipMemsetAsync(C_row_ptr, 0, sizeof(int64_t), s));
-        HIP_TRY(c, hipStreamSynchronize(s));
+        TRY(read_hdr(c, s));
+        TRY(device_errors(c, c->h_hdr->error));
         *C_nnz = 0;
         p.hdr = DevHdr();
         p.valid = true;
@@ -520,16 +542,16 @@ smash_status smash_spgemm_symbolic(smash_ctx c, const smash_csr *A, const smash_
     }
 
     // per-row plan arrays
-    const int nb = (int)blocks_for(m, kScanItems);
     const bool global = p.heavy_mode == 1;
+    p.nblk = (int)blocks_for(m, kBinBlockRows);
+    const int nsb = (int)blocks_for(m, kScanItems);
     {
-        size_t need = 0;
-        need += 256 + m * sizeof(long long);          // ub
-        need += 256 + m * sizeof(int) * 4;            // cap, nnzc, sym_perm, num_perm
-        need += 512 + m * 2;                          // bins
-        need += 256 + (nb + 1) * sizeof(long long);   // bsum
-        if (global) need += 512 + 2 * m * sizeof(long long);
-        need += 4096;
+        const size_t need = carve_size({m * sizeof(long long), m * sizeof(int), m * sizeof(int), m * sizeof(int),
+                                        m * sizeof(int), (size_t)m, (size_t)m,
+                                        (size_t)p.nblk * kNumBins * sizeof(int), (size_t)p.nblk * 8,
+                                        (size_t)p.nblk * kNumBins * 8,
+                                        (size_t)(nsb + 1) * 8, global ? (size_t)m * 8 : 0,
+                                        global ? (size_t)(m + 1) * 8 : 0, global ? (size_t)(m + 1) * 8 : 0});
         TRY(ensure(c, c->plan_mem, need, s));
         Carve cv{(char *)c->plan_mem.ptr};
         p.ub = cv.take<long long>(m);
@@ -539,74 +561,86 @@ smash_status smash_spgemm_symbolic(smash_ctx c, const smash_csr *A, const smash_
         p.num_perm = cv.take<int>(m);
         p.sym_bin = cv.take<unsigned char>(m);
         p.num_bin = cv.take<unsigned char>(m);
-        p.bsum = cv.take<long long>(nb + 1);
+        p.bcount = cv.take<int>((size_t)p.nblk * kNumBins);
+        p.bprod = cv.take<unsigned long long>(p.nblk);
+        p.bw = cv.take<long long>((size_t)p.nblk * kNumBins);
+        p.bsum = cv.take<long long>(nsb + 1);
         if (global) {
-            p.goff_sym = cv.take<long long>(m);
-            p.goff_num = cv.take<long long>(m);
+            p.gsz = cv.take<long long>(m);
+            p.goff_sym = cv.take<long long>(m + 1);
+            p.goff_num = cv.take<long long>(m + 1);
         }
     }
 
+    // a1/a2: products per row, bins, rows grouped by bin
     TRY(launch(c, K_ANALYZE, s, [&] {
         k_analyze<<<blocks_for(m, 4), 256, 0, s>>>((int)m, (int)p.n, p.lds_row_max, A->row_ptr, A->col_idx, B->row_ptr,
-                                                   p.ub, p.cap, p.nnzc, p.sym_bin, c->d_hdr);
+                                                   p.ub, p.cap, p.nnzc, p.sym_bin);
     }));
-    TRY(launch(c, K_BIN_OFFSETS, s, [&] { k_bin_offsets<<<1, 1, 0, s>>>(&c->d_hdr->sym); }));
-    TRY(launch(c, K_SCATTER, s, [&] {
-        k_scatter<<<blocks_for(m, 256), 256, 0, s>>>((int)m, p.sym_bin, &c->d_hdr->sym, p.sym_perm,
-                                                     global ? p.cap : nullptr, &c->d_hdr->gcursor[0], p.goff_sym);
-    }));
+    TRY(bin_rows(c, s, p, p.sym_bin, p.ub, nullptr, &c->d_hdr->sym, p.sym_perm, global ? p.cap : nullptr));
     TRY(read_hdr(c, s));
+    TRY(device_errors(c, c->h_hdr->error));
     p.hdr = *c->h_hdr;
-
-    // symbolic per bin
-    TRY(run_sym_bins(c, s, p));
     const int H = p.hdr.sym.count[kBinHeavy];
     const int *heavy_rows = p.sym_perm + p.hdr.sym.offset[kBinHeavy];
-    if (H > 0) {
-        if (!global) {
-            const size_t cells = (size_t)H * p.nchunks;
-            TRY(ensure(c, c->heavy_mem, 2 * cells * sizeof(int) + 512, s));
-            Carve cv{(char *)c->heavy_mem.ptr};
-            p.wcnt = cv.take<int>(cells);
-            p.woff = cv.take<int>(cells);
-            const size_t lds = sym_heavy_lds(p.n);
-            (void)hipFuncSetAttribute((const void *)k_sym_heavy, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            TRY(launch(c, K_SYM_HEAVY, s, [&] {
-                k_sym_heavy<<<H, kHeavyThreads, lds, s>>>(A->row_ptr, A->col_idx, B->row_ptr, B->col_idx, heavy_rows,
-                                                          (int)p.n, p.nchunks, p.wcnt, p.nnzc, &c->d_hdr->error);
-            }));
-        } else {
-            const unsigned long long slots = p.hdr.gneed[0];
-            TRY(ensure(c, c->gkeys, slots * sizeof(int), s));
-            TRY(launch(c, K_FILL, s, [&] {
-                k_fill_i32<<<2048, 256, 0, s>>>((long long)slots, (int *)c->gkeys.ptr, kEmpty);
-            }));
-            TRY(launch(c, K_SYM_GLOBAL, s, [&] {
-                k_sym_global<<<H, kHeavyThreads, 0, s>>>(A->row_ptr, A->col_idx, B->row_ptr, B->col_idx, heavy_rows,
-                                                         p.cap, p.goff_sym, (int *)c->gkeys.ptr, p.nnzc,
-                                                         &c->d_hdr->error);
-            }));
-        }
+    if (global && H > 0)
+        TRY(scan_counts<long long>(c, s, H, p.gsz, p.bsum, p.goff_sym, (long long *)&c->d_hdr->gneed[0]));
+
+    // a3: symbolic per bin
+    TRY(run_sym_bins(c, s, p));
+    if (H > 0 && !global) {
+        const long long kdim = p.B.rows;
+        const size_t cells = (size_t)H * p.nchunks;
+        const int nhb = (int)blocks_for(H, 256);
+        const size_t need = carve_size({(size_t)(kdim * (p.nchunks + 1)) * sizeof(int), cells * sizeof(int),
+                                        cells * sizeof(int), (size_t)nhb * kSegBins * sizeof(int), cells * sizeof(Seg)});
+        TRY(ensure(c, c->heavy_mem, need, s));
+        Carve cv{(char *)c->heavy_mem.ptr};
+        p.bsplit = cv.take<int>((size_t)(kdim * (p.nchunks + 1)));
+        p.wcnt = cv.take<int>(cells);
+        p.woff = cv.take<int>(cells);
+        p.seg_bcount = cv.take<int>((size_t)nhb * kSegBins);
+        p.segs = cv.take<Seg>(cells);
+        TRY(launch(c, K_BSPLIT, s, [&] {
+            k_bsplit<<<blocks_for(kdim * (p.nchunks + 1), 256), 256, 0, s>>>((int)kdim, p.nchunks, B->row_ptr,
+                                                                            B->col_idx, p.bsplit);
+        }));
+        const int nwin = (p.nchunks + kSymWinChunks - 1) / kSymWinChunks;
+        TRY(launch(c, K_SYM_HEAVY, s, [&] {
+            k_sym_heavy<<<(unsigned)((long long)H * nwin), kSymHeavyThreads, 0, s>>>(
+                A->row_ptr, A->col_idx, B->col_idx, p.bsplit, heavy_rows, nwin, p.nchunks, p.wcnt, p.nnzc);
+        }));
+    } else if (H > 0) {
+        TRY(read_hdr(c, s));
+        const unsigned long long need = c->h_hdr->gneed[0];
+        TRY(ensure(c, c->gkeys, need * sizeof(int), s));
+        TRY(launch(c, K_FILL, s, [&] { k_fill_i32<<<2048, 256, 0, s>>>((long long)need, (int *)c->gkeys.ptr, kEmpty); }));
+        TRY(launch(c, K_SYM_GLOBAL, s, [&] {
+            k_sym_global<<<H, kGlobalThreads, 0, s>>>(A->row_ptr, A->col_idx, B->row_ptr, B->col_idx, heavy_rows, p.cap,
+                                                      p.goff_sym, (int *)c->gkeys.ptr, p.nnzc, &c->d_hdr->error);
+        }));
     }
 
-    // C_row_ptr = exclusive scan of the row counts
-    TRY(launch(c, K_SCAN_REDUCE, s, [&] { k_scan_reduce<<<nb, kScanThreads, 0, s>>>((int)m, p.nnzc, p.bsum); }));
-    TRY(launch(c, K_SCAN_TOP, s, [&] { k_scan_top<<<1, kScanThreads, 0, s>>>(nb, p.bsum, &c->d_hdr->nnz_c); }));
-    TRY(launch(c, K_SCAN_APPLY, s, [&] {
-        k_scan_apply<<<nb, kScanThreads, 0, s>>>((int)m, p.nnzc, p.bsum, &c->d_hdr->nnz_c, (long long *)C_row_ptr);
-    }));
-    // numeric bins of the plan
+    // a4: C_row_ptr = exclusive scan of the row counts
+    TRY(scan_counts<int>(c, s, m, p.nnzc, p.bsum, (long long *)C_row_ptr, &c->d_hdr->nnz_c));
+    // numeric plan: bins of the light rows, segments of the heavy rows
     TRY(launch(c, K_NUM_BINS, s, [&] {
-        k_num_bins<<<blocks_for(m, 256), 256, 0, s>>>((int)m, p.nnzc, p.sym_bin, p.num_bin, c->d_hdr);
+        k_num_bins<<<blocks_for(m, 256), 256, 0, s>>>((int)m, p.nnzc, p.sym_bin, p.num_bin);
     }));
-    TRY(launch(c, K_BIN_OFFSETS, s, [&] { k_bin_offsets<<<1, 1, 0, s>>>(&c->d_hdr->num); }));
-    TRY(launch(c, K_SCATTER, s, [&] {
-        k_scatter<<<blocks_for(m, 256), 256, 0, s>>>((int)m, p.num_bin, &c->d_hdr->num, p.num_perm,
-                                                     global ? p.nnzc : nullptr, &c->d_hdr->gcursor[1], p.goff_num);
-    }));
+    TRY(bin_rows(c, s, p, p.num_bin, nullptr, p.nnzc, &c->d_hdr->num, p.num_perm, global ? p.nnzc : nullptr));
+    if (H > 0 && global)
+        TRY(scan_counts<long long>(c, s, H, p.gsz, p.bsum, p.goff_num, (long long *)&c->d_hdr->gneed[1]));
     if (H > 0 && !global) {
+        const int nhb = (int)blocks_for(H, 256);
         TRY(launch(c, K_CHUNK_PREFIX, s, [&] {
-            k_chunk_prefix<<<blocks_for(H, 256), 256, 0, s>>>(H, p.nchunks, p.wcnt, p.woff);
+            k_chunk_prefix<<<nhb, 256, 0, s>>>(H, p.nchunks, p.wcnt, p.woff);
+        }));
+        TRY(launch(c, K_SEG_PLAN, s, [&] {
+            k_seg_plan<<<nhb, 256, 0, s>>>(0, H, p.nchunks, p.wcnt, p.seg_bcount, &c->d_hdr->seg, p.segs);
+        }));
+        TRY(launch(c, K_SEG_SCAN, s, [&] { k_seg_scan<<<1, kWave, 0, s>>>(nhb, p.seg_bcount, &c->d_hdr->seg); }));
+        TRY(launch(c, K_SEG_PLAN, s, [&] {
+            k_seg_plan<<<nhb, 256, 0, s>>>(1, H, p.nchunks, p.wcnt, p.seg_bcount, &c->d_hdr->seg, p.segs);
         }));
     }
     TRY(read_hdr(c, s));
@@ -618,6 +652,10 @@ smash_status smash_spgemm_symbolic(smash_ctx c, const smash_csr *A, const smash_
     c->stats.rows_empty = p.hdr.sym.count[kBinEmpty];
     c->stats.rows_heavy = H;
     c->stats.rows_lds = m - H - p.hdr.sym.count[kBinEmpty];
+    c->stats.heavy_segments = global ? 0 : (p.hdr.seg.offset[kSegBins] - p.hdr.seg.count[kSegDense]);
+    c->stats.heavy_dense_chunks = global ? 0 : p.hdr.seg.count[kSegDense];
+    c->stats.nnz_heavy = p.hdr.num.wsum[kBinHeavy];
+    c->stats.nnz_dense = global ? 0 : p.hdr.seg.nnz[kSegDense];
     c->stats.global_slots = global ? (int64_t)(p.hdr.gneed[0] + p.hdr.gneed[1]) : 0;
     p.valid = true;
     return SMASH_OK;
@@ -639,7 +677,7 @@ smash_status smash_spgemm_numeric(smash_ctx c, smash_dtype dtype, const smash_cs
     if (p.m == 0 || p.hdr.nnz_c == 0) return SMASH_OK;
     DeviceGuard g(c->device);
     if (!g.ok) return fail(c, SMASH_ERR_HIP, "hipSetDevice(%d) failed", c->device);
-    HIP_TRY(c, hipMemsetAsync(&c->d_hdr->error, 0, 2 * sizeof(int), s));
+    HIP_TRY(c, hipMemsetAsync(&c->d_hdr->error, 0, sizeof(int), s));
     smash_status st;
     if (dtype == SMASH_F32)
         st = numeric_impl<float>(c, s, p, (const float *)A->val, (const float *)B->val, C_row_ptr, C_col_idx,
@@ -649,7 +687,6 @@ smash_status smash_spgemm_numeric(smash_ctx c, smash_dtype dtype, const smash_cs
                                   (double *)C_val);
     if (st != SMASH_OK) return st;
     TRY(read_hdr(c, s));
-    c->stats.heavy_windows = c->h_hdr->heavy_windows;
     return device_errors(c, c->h_hdr->error);
 }
 

@@ -9,22 +9,30 @@
 // exact symbolic pass, and written back as sorted CSR (Write-back Phase).
 //
 // MI355X mapping (not the PIUMA design of the paper):
-//   * one 64-lane wavefront, or a group of wavefronts, owns one output row
-//     and its LDS table; rows are binned by table size so every bin launches
-//     a workgroup shape that fits its rows (the paper's windows sized to the
-//     scratchpad);
-//   * the products of a row are enumerated "flat": a wave loads 64 entries
-//     of A's row, prefix-sums the lengths of the B rows they select, and
-//     every lane takes one product per step, so a long B row and many short
-//     ones keep all 64 lanes busy (the paper splits rows between two
-//     threads for the same reason, "SMASH Version 2: Tokenization");
+//   * a group of 64-lane wavefronts owns one output row (or one column
+//     segment of a heavy row) and its LDS table; rows are binned by table
+//     size so each bin launches a workgroup shape that fits its rows (the
+//     paper's windows sized to the scratchpad);
+//   * the products of a row are enumerated "flat": the group loads a chunk of
+//     A's row, prefix-sums the lengths of the B rows it selects, and every
+//     thread takes products q = t, t + G, ... of the concatenation, so a long
+//     B row and many short ones keep every lane busy (the paper gives each
+//     row two threads for the same reason, "SMASH Version 2: Tokenization");
+//     several products per thread are loaded before any is merged, to keep
+//     loads in flight;
 //   * slots come from a multiplicative (Fibonacci) hash of the column, which
 //     spreads clustered columns like the paper's low-order-bit hash of
 //     version 2, with +1 linear probing;
-//   * rows whose output does not fit an LDS table take the heavy-row path:
-//     either column windows accumulated densely in LDS (the paper's per-row
-//     dense/sparse decision of the Window Distribution Phase), or a hash
-//     table in global memory (version 3, "Fragmenting Memory").
+//   * heavy rows (output bound above the LDS row limit) are cut into column
+//     segments of at most kSegCap entries using per-8192-column counts from
+//     the symbolic phase.  Sparse segments are hashed in LDS; chunks denser
+//     than kSegCap are accumulated directly by column (the paper's per-row
+//     dense/sparse decision of the Window Distribution Phase).  Optionally a
+//     heavy row instead uses one hash table in global memory (version 3,
+//     "Fragmenting Memory").
+//   * output is written in column order: bitonic sort of small tables, rank
+//     from an occupancy bitmap for segments and dense chunks, staged in LDS so
+//     the global stores are coalesced.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -34,16 +42,20 @@ namespace smash {
 
 constexpr int kWave = 64;
 constexpr int kEmpty = -1;              // empty-slot tag (Algorithm "SMASH SETUP": EMPTY = -1)
-constexpr int kMinLogT = 6;             // smallest LDS table: 64 slots
-constexpr int kMaxLogT = 13;            // largest LDS table: 8192 slots
+constexpr int kMinLogT = 6;             // smallest LDS row table: 64 slots
+constexpr int kMaxLogT = 11;            // largest LDS row table: 2048 slots
 constexpr int kLdsBins = kMaxLogT - kMinLogT + 1;
 constexpr int kBinHeavy = kLdsBins;
 constexpr int kBinEmpty = kLdsBins + 1;
 constexpr int kNumBins = kLdsBins + 2;
 constexpr int kChunkCols = 8192;        // column granularity of heavy-row counts
 constexpr int kChunkWords = kChunkCols / 32;
-constexpr int kSymWindowBits = 1 << 20; // symbolic heavy-row bitmap window (128 KiB)
-constexpr int kHeavyThreads = 1024;
+constexpr int kSymWinChunks = 16;       // symbolic heavy window: 16 chunks, 16 KiB bitmap
+constexpr int kSegCap = 2048;           // entries of one hashed segment (table of 4096 slots)
+constexpr int kSegMaxSpan = 16;         // chunks spanned by one hashed segment
+constexpr int kSegBins = 4;             // hashed segments with <=128, <=512, <=2048 entries; dense chunks
+constexpr int kSegDense = 3;
+constexpr int kBinBlockRows = 1024;     // rows per block of the binning kernels
 
 enum : int {
     kErrProbe = 1,      // a hash table ran out of slots (inconsistent sizes)
@@ -53,20 +65,30 @@ enum : int {
 };
 
 struct BinHdr {
+    long long wsum[kNumBins]; // sum of the per-row weights (output entries) per bin
     int count[kNumBins];      // rows per bin
     int offset[kNumBins + 1]; // exclusive offsets of the bins in the row permutation
-    int cursor[kNumBins];     // scatter cursors
+};
+
+struct SegHdr {
+    long long nnz[kSegBins];  // output entries per segment bin
+    int count[kSegBins];
+    int offset[kSegBins + 1];
 };
 
 struct DevHdr {
     unsigned long long products;       // sum over rows of products
-    unsigned long long gneed[2];       // global-hash slots needed: [0] symbolic, [1] numeric
-    unsigned long long gcursor[2];     // global-hash slots handed out so far
+    unsigned long long gneed[2];       // global-hash slots: [0] symbolic, [1] numeric
     long long nnz_c;
     BinHdr sym, num;
+    SegHdr seg;
     int error;
-    int heavy_windows;
-    int pad[2];
+    int pad;
+};
+
+// A column segment of a heavy row: heavy index, chunk range, entry count.
+struct Seg {
+    int h, c0, c1, count;
 };
 
 // ------------------------------------------------------------------ helpers
@@ -74,7 +96,7 @@ struct DevHdr {
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 
 // Orders LDS accesses of one wavefront (lanes execute in lockstep; the fence
-// keeps the compiler from moving LDS reads above earlier writes).
+// keeps the compiler from moving LDS accesses across it).
 __device__ __forceinline__ void wave_sync()
 {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -89,12 +111,13 @@ __device__ __forceinline__ void group_sync()
     else __syncthreads();
 }
 
-__device__ __forceinline__ int wave_incl_scan(int v)
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v)
 {
     const int lane = lane_id();
 #pragma unroll
     for (int d = 1; d < kWave; d <<= 1) {
-        int t = __shfl_up(v, d, kWave);
+        T t = __shfl_up(v, d, kWave);
         if (lane >= d) v += t;
     }
     return v;
@@ -121,27 +144,19 @@ __device__ __forceinline__ unsigned slot_of(int key, int logT)
 
 // log2 of the global hash table size of a heavy row with at most n keys
 // (load factor at most one half).
-__device__ __forceinline__ int gtable_log2(long long n)
+__host__ __device__ __forceinline__ int gtable_log2(long long n)
 {
-    return ceil_log2(2LL * (n > 1 ? n : 1));
+    long long x = 2 * (n > 1 ? n : 1);
+    int l = 0;
+    while ((1LL << l) < x) ++l;
+    return l;
 }
 
-// Bin of a row for the symbolic phase, from its product count ub and output
-// bound cap = min(ub, cols).
-__device__ __forceinline__ int sym_bin(long long ub, int cap, int lds_row_max)
+// Bin of a light row from its table bound (cap for symbolic, exact count for
+// numeric): table of next_pow2(2 * bound) slots, at least 64.
+__device__ __forceinline__ int lds_bin(long long bound)
 {
-    if (ub == 0) return kBinEmpty;
-    if (cap > lds_row_max) return kBinHeavy;
-    int lt = ceil_log2(2LL * cap);
-    return (lt < kMinLogT ? kMinLogT : lt) - kMinLogT;
-}
-
-// Bin of a row for the numeric phase, from its exact output count.
-__device__ __forceinline__ int num_bin(int nc, bool heavy)
-{
-    if (heavy) return kBinHeavy;
-    if (nc == 0) return kBinEmpty;
-    int lt = ceil_log2(2LL * nc);
+    int lt = ceil_log2(2LL * bound);
     return (lt < kMinLogT ? kMinLogT : lt) - kMinLogT;
 }
 
@@ -150,12 +165,7 @@ template <typename T, int THREADS>
 __device__ __forceinline__ T block_excl_scan(T v, T *s_tmp /* THREADS/64 + 1 */, T &total)
 {
     const int lane = lane_id(), wave = threadIdx.x / kWave;
-    T incl = v;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        T t = __shfl_up(incl, d, kWave);
-        if (lane >= d) incl += t;
-    }
+    T incl = wave_incl_scan(v);
     if (lane == kWave - 1) s_tmp[wave] = incl;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -172,43 +182,84 @@ __device__ __forceinline__ T block_excl_scan(T v, T *s_tmp /* THREADS/64 + 1 */,
 
 // ----------------------------------------------------- product enumeration
 //
+// Shared LDS scratch of one group of G threads.
+template <typename V, int G>
+struct EnumScratch {
+    int incl[G];        // inclusive prefix of the B range lengths of the chunk
+    int bs[G];          // B range start of each A entry of the chunk
+    V a[G];             // value of each A entry of the chunk
+    int wsum[G / kWave + 1];
+};
+
 // Calls sink(j, a * b) (or sink(j) without values) for every product of the
-// A entries [e0, e1) of one row, restricted to the B ranges returned by
-// get(e, &bstart, &blen, &a).  The waves of a group stride over chunks of 64
-// A entries; within a chunk each lane takes products q = lane, lane + 64, ...
-// of the concatenated B ranges and finds its A entry by a 6-step search of
-// the chunk's inclusive length prefix (kept in LDS, one 64-entry slice per
-// wave).
-template <typename V, bool WITH_VAL, typename Get, typename Sink>
-__device__ __forceinline__ void wave_products(int e0, int e1, int wave_in_group, int waves_in_group,
-                                              int *s_incl, int *s_bs, V *s_a,
-                                              const int *__restrict__ Bcol, const V *__restrict__ Bval,
-                                              Get get, Sink sink)
+// A entries [e0, e1) of one row, each restricted to the B range returned by
+// get(e, &bstart, &blen, &a).  All G threads of the group (thread index gt)
+// cooperate on each chunk of G A entries; thread gt takes products
+// q = gt, gt + G, ... of the chunk and finds its A entry by binary search
+// of the chunk's prefix.  U products are loaded before any is merged.
+template <typename V, bool WITH_VAL, int G, int U, typename Get, typename Sink>
+__device__ __forceinline__ void group_products(int e0, int e1, int gt, EnumScratch<V, G> &S,
+                                               const int *__restrict__ Bcol, const V *__restrict__ Bval,
+                                               Get get, Sink sink)
 {
-    const int lane = lane_id();
-    for (int base = e0 + wave_in_group * kWave; base < e1; base += waves_in_group * kWave) {
-        const int e = base + lane;
+    constexpr int WG = G / kWave;
+    const int lane = lane_id(), wg = gt / kWave;
+    for (int base = e0; base < e1; base += G) {
+        const int e = base + gt;
         int bs = 0, bl = 0;
         V a = V(0);
         if (e < e1) get(e, bs, bl, a);
-        const int incl = wave_incl_scan(bl);
-        const int total = __shfl(incl, kWave - 1, kWave);
-        s_incl[lane] = incl;
-        s_bs[lane] = bs;
-        if constexpr (WITH_VAL) s_a[lane] = a;
-        wave_sync();
-        for (int q = lane; q < total; q += kWave) {
-            int src = 0;
-#pragma unroll
-            for (int step = 32; step > 0; step >>= 1)
-                if (s_incl[src + step - 1] <= q) src += step;
-            const int excl = src ? s_incl[src - 1] : 0;
-            const int pos = s_bs[src] + (q - excl);
-            const int j = Bcol[pos];
-            if constexpr (WITH_VAL) sink(j, s_a[src] * Bval[pos]);
-            else sink(j);
+        int incl = wave_incl_scan(bl);
+        if constexpr (WG > 1) {
+            if (lane == kWave - 1) S.wsum[wg] = incl;
+            group_sync<WG>();
+            int add = 0;
+            for (int w = 0; w < wg; ++w) add += S.wsum[w];
+            incl += add;
         }
-        wave_sync();
+        S.incl[gt] = incl;
+        S.bs[gt] = bs;
+        if constexpr (WITH_VAL) S.a[gt] = a;
+        group_sync<WG>();
+        const int total = S.incl[G - 1];
+        for (int q0 = 0; q0 < total; q0 += G * U) {
+            int pos[U];
+            V av[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int q = q0 + u * G + gt;
+                pos[u] = -1;
+                av[u] = V(0);
+                if (q < total) {
+                    int src = 0;
+#pragma unroll
+                    for (int step = G / 2; step > 0; step >>= 1)
+                        if (S.incl[src + step - 1] <= q) src += step;
+                    const int excl = src ? S.incl[src - 1] : 0;
+                    pos[u] = S.bs[src] + (q - excl);
+                    if constexpr (WITH_VAL) av[u] = S.a[src];
+                }
+            }
+            int j[U];
+            V bv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                j[u] = 0;
+                bv[u] = V(0);
+                if (pos[u] >= 0) {
+                    j[u] = Bcol[pos[u]];
+                    if constexpr (WITH_VAL) bv[u] = Bval[pos[u]];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (pos[u] >= 0) {
+                    if constexpr (WITH_VAL) sink(j[u], av[u] * bv[u]);
+                    else sink(j[u]);
+                }
+            }
+        }
+        group_sync<WG>();
     }
 }
 
@@ -254,173 +305,217 @@ __device__ __forceinline__ void lds_insert_add(int *keys, V *vals, int logT, int
     atomicOr(err, kErrProbe);
 }
 
+// --------------------------------------------------------------- validation
+
+// Checks the CSR preconditions of one matrix, one wave per row; sets `flag`
+// in *err on failure.
+__global__ __launch_bounds__(256) void k_validate(int rows, int cols, long long nnz, const int *__restrict__ rp,
+                                                  const int *__restrict__ ci, int flag, int *err)
+{
+    const int lane = lane_id();
+    const long long row = (long long)blockIdx.x * 4 + threadIdx.x / kWave;
+    bool bad = false;
+    if (row == 0 && lane == 0 && (rp[0] != 0 || (long long)rp[rows] != nnz)) bad = true;
+    if (row < rows) {
+        const int a = rp[row], b = rp[row + 1];
+        if (b < a || a < 0 || (long long)b > nnz) {
+            bad = true;
+        } else {
+            for (int p = a + lane; p < b; p += kWave) {
+                const int c = ci[p];
+                if (c < 0 || c >= cols || (p > a && c <= ci[p - 1])) bad = true;
+            }
+        }
+    }
+    if (__ballot(bad) && lane == 0) atomicOr(err, flag);
+}
+
 // --------------------------------------------------------- analysis & bins
 
 // Row analysis (step a1): products ub_i = sum_k nnz(B_k) over row i of A, the
-// output bound cap_i = min(ub_i, cols), the symbolic bin of the row, and the
-// totals.  One wave per row, four rows per block.
+// output bound cap_i = min(ub_i, cols) and the row's symbolic bin.  One wave
+// per row, four rows per block.
 __global__ __launch_bounds__(256) void k_analyze(int m, int ncols, int lds_row_max,
                                                  const int *__restrict__ Arp, const int *__restrict__ Acol,
                                                  const int *__restrict__ Brp, long long *__restrict__ ub_out,
                                                  int *__restrict__ cap_out, int *__restrict__ nnzc,
-                                                 unsigned char *__restrict__ bin_out, DevHdr *hdr)
+                                                 unsigned char *__restrict__ bin_out)
 {
-    __shared__ int s_hist[kNumBins];
-    __shared__ unsigned long long s_prod, s_gslots;
-    if (threadIdx.x < kNumBins) s_hist[threadIdx.x] = 0;
-    if (threadIdx.x == 0) { s_prod = 0; s_gslots = 0; }
-    __syncthreads();
     const int lane = lane_id();
     const int row = blockIdx.x * 4 + threadIdx.x / kWave;
-    if (row < m) {
-        const int e0 = Arp[row], e1 = Arp[row + 1];
-        long long ub = 0;
-        for (int e = e0 + lane; e < e1; e += kWave) {
-            const int k = Acol[e];
-            ub += Brp[k + 1] - Brp[k];
-        }
-        ub = wave_sum(ub);
-        if (lane == 0) {
-            const int cap = (int)(ub < ncols ? ub : ncols);
-            const int b = sym_bin(ub, cap, lds_row_max);
-            ub_out[row] = ub;
-            cap_out[row] = cap;
-            nnzc[row] = 0;
-            bin_out[row] = (unsigned char)b;
-            atomicAdd(&s_hist[b], 1);
-            atomicAdd(&s_prod, (unsigned long long)ub);
-            if (b == kBinHeavy) atomicAdd(&s_gslots, 1ull << gtable_log2(cap));
-        }
+    if (row >= m) return;
+    const int e0 = Arp[row], e1 = Arp[row + 1];
+    long long ub = 0;
+    for (int e = e0 + lane; e < e1; e += kWave) {
+        const int k = Acol[e];
+        ub += Brp[k + 1] - Brp[k];
     }
-    __syncthreads();
-    if (threadIdx.x < kNumBins && s_hist[threadIdx.x]) atomicAdd(&hdr->sym.count[threadIdx.x], s_hist[threadIdx.x]);
-    if (threadIdx.x == 0) {
-        if (s_prod) atomicAdd(&hdr->products, s_prod);
-        if (s_gslots) atomicAdd(&hdr->gneed[0], s_gslots);
+    ub = wave_sum(ub);
+    if (lane == 0) {
+        const int cap = (int)(ub < ncols ? ub : ncols);
+        int b;
+        if (ub == 0) b = kBinEmpty;
+        else if (cap > lds_row_max) b = kBinHeavy;
+        else b = lds_bin(cap);
+        ub_out[row] = ub;
+        cap_out[row] = cap;
+        nnzc[row] = 0;
+        bin_out[row] = (unsigned char)b;
     }
 }
 
-// Exclusive offsets of the bins and scatter cursors (one thread).
-__global__ void k_bin_offsets(BinHdr *h)
-{
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    int run = 0;
-    for (int b = 0; b < kNumBins; ++b) {
-        h->offset[b] = run;
-        h->cursor[b] = run;
-        run += h->count[b];
-    }
-    h->offset[kNumBins] = run;
-}
-
-// Groups row ids by bin (empty rows are left out).  Rows of the heavy bin
-// that use the global hash table also get their table's slot offset.
-__global__ __launch_bounds__(256) void k_scatter(int m, const unsigned char *__restrict__ bin_of,
-                                                 BinHdr *h, int *__restrict__ perm,
-                                                 const int *__restrict__ heavy_size /* nullable */,
-                                                 unsigned long long *gcursor, long long *__restrict__ goff)
-{
-    __shared__ int s_cnt[kNumBins], s_base[kNumBins];
-    __shared__ unsigned long long s_gsum, s_gbase;
-    if (threadIdx.x < kNumBins) s_cnt[threadIdx.x] = 0;
-    if (threadIdx.x == 0) s_gsum = 0;
-    __syncthreads();
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int b = i < m ? (int)bin_of[i] : -1;
-    const int local = b >= 0 ? atomicAdd(&s_cnt[b], 1) : 0;
-    unsigned long long gsz = 0, gloc = 0;
-    if (b == kBinHeavy && heavy_size) {
-        gsz = 1ull << gtable_log2(heavy_size[i]);
-        gloc = atomicAdd(&s_gsum, gsz);
-    }
-    __syncthreads();
-    if (threadIdx.x < kNumBins && threadIdx.x != kBinEmpty && s_cnt[threadIdx.x])
-        s_base[threadIdx.x] = atomicAdd(&h->cursor[threadIdx.x], s_cnt[threadIdx.x]);
-    if (threadIdx.x == 0 && heavy_size && s_gsum) s_gbase = atomicAdd(gcursor, s_gsum);
-    __syncthreads();
-    if (b >= 0 && b != kBinEmpty) {
-        const int pos = s_base[b] + local;
-        perm[pos] = i;
-        if (b == kBinHeavy && heavy_size) goff[pos - h->offset[kBinHeavy]] = (long long)(s_gbase + gloc);
-    }
-}
-
-// Numeric bins from the exact row counts; heavy rows stay heavy.  Also sums
-// the global-hash slots the heavy rows need in global mode.
+// Numeric bin of every row from its exact count (heavy rows stay heavy).
 __global__ __launch_bounds__(256) void k_num_bins(int m, const int *__restrict__ nnzc,
                                                   const unsigned char *__restrict__ sym_bin_of,
-                                                  unsigned char *__restrict__ bin_out, DevHdr *hdr)
+                                                  unsigned char *__restrict__ bin_out)
 {
-    __shared__ int s_hist[kNumBins];
-    __shared__ unsigned long long s_gslots;
-    if (threadIdx.x < kNumBins) s_hist[threadIdx.x] = 0;
-    if (threadIdx.x == 0) s_gslots = 0;
-    __syncthreads();
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < m) {
-        const bool heavy = sym_bin_of[i] == kBinHeavy;
-        const int b = num_bin(nnzc[i], heavy);
-        bin_out[i] = (unsigned char)b;
-        atomicAdd(&s_hist[b], 1);
-        if (heavy) atomicAdd(&s_gslots, 1ull << gtable_log2(nnzc[i]));
-    }
-    __syncthreads();
-    if (threadIdx.x < kNumBins && s_hist[threadIdx.x]) atomicAdd(&hdr->num.count[threadIdx.x], s_hist[threadIdx.x]);
-    if (threadIdx.x == 0 && s_gslots) atomicAdd(&hdr->gneed[1], s_gslots);
+    if (i >= m) return;
+    const int b = sym_bin_of[i];
+    const int nc = nnzc[i];
+    bin_out[i] = (unsigned char)(b == kBinHeavy ? kBinHeavy : (nc == 0 ? kBinEmpty : lds_bin(nc)));
 }
 
-// --------------------------------------------------------------- validation
-
-// Checks the CSR preconditions of one matrix; sets `flag` in *err on failure.
-__global__ __launch_bounds__(256) void k_validate(int rows, int cols, long long nnz, const int *__restrict__ rp,
-                                                  const int *__restrict__ ci, int flag, int *err)
+// Per-block bin histograms (kBinBlockRows rows per block, no global atomics):
+// bcount[blk * kNumBins + b], the block's per-bin sum of the row weights wt
+// (bw, when wt is given) and the block's sum of products (bprod, when ub is
+// given).
+__global__ __launch_bounds__(256) void k_bin_count(int m, const unsigned char *__restrict__ bin_of,
+                                                   const long long *__restrict__ ub, const int *__restrict__ wt,
+                                                   int *__restrict__ bcount, unsigned long long *__restrict__ bprod,
+                                                   long long *__restrict__ bw)
 {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    bool bad = false;
-    if (i == 0 && (rp[0] != 0 || (long long)rp[rows] != nnz)) bad = true;
-    if (i < rows) {
-        const int a = rp[i], b = rp[i + 1];
-        if (b < a || a < 0 || (long long)b > nnz) bad = true;
-        else {
-            for (int p = a; p < b; ++p) {
-                const int c = ci[p];
-                if (c < 0 || c >= cols || (p > a && c <= ci[p - 1])) { bad = true; break; }
-            }
+    __shared__ int s_hist[kNumBins];
+    __shared__ unsigned long long s_w[kNumBins];
+    __shared__ unsigned long long s_prod;
+    if (threadIdx.x < kNumBins) {
+        s_hist[threadIdx.x] = 0;
+        s_w[threadIdx.x] = 0;
+    }
+    if (threadIdx.x == 0) s_prod = 0;
+    __syncthreads();
+    unsigned long long prod = 0;
+    for (int r = threadIdx.x; r < kBinBlockRows; r += 256) {
+        const long long i = (long long)blockIdx.x * kBinBlockRows + r;
+        if (i < m) {
+            const int b = bin_of[i];
+            atomicAdd(&s_hist[b], 1);
+            if (wt) atomicAdd(&s_w[b], (unsigned long long)wt[i]);
+            if (ub) prod += (unsigned long long)ub[i];
         }
     }
-    if (bad) atomicOr(err, flag);
+    prod = wave_sum(prod);
+    if (lane_id() == 0 && prod) atomicAdd(&s_prod, prod);
+    __syncthreads();
+    if (threadIdx.x < kNumBins) {
+        bcount[blockIdx.x * kNumBins + threadIdx.x] = s_hist[threadIdx.x];
+        if (bw) bw[blockIdx.x * kNumBins + threadIdx.x] = (long long)s_w[threadIdx.x];
+    }
+    if (threadIdx.x == 0 && bprod) bprod[blockIdx.x] = s_prod;
+}
+
+// Bin totals and offsets, and every block's base inside each bin (one block).
+__global__ __launch_bounds__(256) void k_bin_scan(int nblk, int *__restrict__ bcount,
+                                                  const unsigned long long *__restrict__ bprod,
+                                                  const long long *__restrict__ bw, BinHdr *h,
+                                                  unsigned long long *products)
+{
+    __shared__ int s_tot[kNumBins];
+    __shared__ long long s_wt[kNumBins];
+    // one wave per bin scans the block counts in place (exclusive)
+    const int lane = lane_id(), wave = threadIdx.x / kWave;
+    for (int b = wave; b < kNumBins; b += 256 / kWave) {
+        int run = 0;
+        for (int c0 = 0; c0 < nblk; c0 += kWave) {
+            const int c = c0 + lane;
+            const int v = c < nblk ? bcount[c * kNumBins + b] : 0;
+            const int incl = wave_incl_scan(v);
+            if (c < nblk) bcount[c * kNumBins + b] = run + incl - v;
+            run += __shfl(incl, kWave - 1, kWave);
+        }
+        long long ws = 0;
+        if (bw)
+            for (int c = lane; c < nblk; c += kWave) ws += bw[c * kNumBins + b];
+        ws = wave_sum(ws);
+        if (lane == 0) {
+            s_tot[b] = run;
+            s_wt[b] = ws;
+        }
+    }
+    unsigned long long p = 0;
+    if (bprod)
+        for (int c = threadIdx.x; c < nblk; c += 256) p += bprod[c];
+    p = wave_sum(p);
+    __shared__ unsigned long long s_p[4];
+    if (lane == 0) s_p[wave] = p;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int b = 0; b < kNumBins; ++b) {
+            h->count[b] = s_tot[b];
+            h->wsum[b] = s_wt[b];
+            h->offset[b] = run;
+            run += s_tot[b];
+        }
+        h->offset[kNumBins] = run;
+        if (bprod && products) *products = s_p[0] + s_p[1] + s_p[2] + s_p[3];
+    }
+}
+
+// Groups row ids by bin (empty rows are left out): perm[offset[b] + block base
+// + rank in block].  For the heavy bin, also records the row's global-hash
+// table size (gsz, by heavy index) when gsize_of is given.
+__global__ __launch_bounds__(256) void k_scatter(int m, const unsigned char *__restrict__ bin_of,
+                                                 const int *__restrict__ bbase, const BinHdr *h,
+                                                 int *__restrict__ perm, const int *__restrict__ gsize_of,
+                                                 long long *__restrict__ gsz)
+{
+    __shared__ int s_cnt[kNumBins];
+    if (threadIdx.x < kNumBins) s_cnt[threadIdx.x] = 0;
+    __syncthreads();
+    for (int r = threadIdx.x; r < kBinBlockRows; r += 256) {
+        const long long i = (long long)blockIdx.x * kBinBlockRows + r;
+        if (i >= m) break;
+        const int b = bin_of[i];
+        const int local = atomicAdd(&s_cnt[b], 1);
+        if (b == kBinEmpty) continue;
+        const int pos = h->offset[b] + bbase[blockIdx.x * kNumBins + b] + local;
+        perm[pos] = (int)i;
+        if (b == kBinHeavy && gsize_of) gsz[pos - h->offset[kBinHeavy]] = 1LL << gtable_log2(gsize_of[i]);
+    }
 }
 
 // ------------------------------------------------------- symbolic, LDS hash
 
-// One row per group of WPR waves (RPW groups per block; RPW > 1 only with
-// WPR = 1).  Counts the distinct columns of each row with an LDS key table
-// of 2^LOGT slots (step a3).
+// Light rows: one row per group of WPR waves (RPW groups per block; RPW > 1
+// only with WPR = 1).  Counts the distinct columns of each row with an LDS
+// key table of 2^LOGT slots (step a3).
 template <int LOGT, int WPR, int RPW>
-__global__ __launch_bounds__(kWave *WPR *RPW) void k_sym_lds(const int *__restrict__ Arp, const int *__restrict__ Acol,
-                                                             const int *__restrict__ Brp, const int *__restrict__ Bcol,
-                                                             const int *__restrict__ rows, int nrows,
-                                                             int *__restrict__ nnzc, int *err)
+__global__ __launch_bounds__(kWave *WPR *RPW) void k_sym_rows(const int *__restrict__ Arp, const int *__restrict__ Acol,
+                                                              const int *__restrict__ Brp, const int *__restrict__ Bcol,
+                                                              const int *__restrict__ rows, int nrows,
+                                                              int *__restrict__ nnzc, int *err)
 {
     static_assert(RPW == 1 || WPR == 1, "multi-row blocks use one wave per row");
     constexpr int T = 1 << LOGT;
+    constexpr int G = WPR * kWave;
     __shared__ int s_keys[RPW][T];
-    __shared__ int s_incl[RPW * WPR][kWave];
-    __shared__ int s_bs[RPW * WPR][kWave];
+    __shared__ EnumScratch<float, G> s_en[RPW];
     __shared__ int s_cnt[RPW];
     const int lane = lane_id(), wave = threadIdx.x / kWave;
-    const int g = wave / WPR, wg = wave % WPR;
+    const int g = wave / WPR;
+    const int gt = threadIdx.x - g * G;
     const int r = blockIdx.x * RPW + g;
     const bool active = r < nrows;
     const int row = active ? rows[r] : 0;
-    for (int t = wg * kWave + lane; t < T; t += WPR * kWave) s_keys[g][t] = kEmpty;
-    if (wg == 0 && lane == 0) s_cnt[g] = 0;
+    int *keys = s_keys[g];
+    for (int t = gt; t < T; t += G) keys[t] = kEmpty;
+    if (gt == 0) s_cnt[g] = 0;
     group_sync<WPR>();
     int mine = 0;
     if (active) {
-        int *keys = s_keys[g];
-        wave_products<float, false>(
-            Arp[row], Arp[row + 1], wg, WPR, s_incl[wave], s_bs[wave], (float *)nullptr, Bcol, (const float *)nullptr,
+        group_products<float, false, G, 2>(
+            Arp[row], Arp[row + 1], gt, s_en[g], Bcol, (const float *)nullptr,
             [&](int e, int &bs, int &bl, float &) {
                 const int k = Acol[e];
                 bs = Brp[k];
@@ -431,13 +526,13 @@ __global__ __launch_bounds__(kWave *WPR *RPW) void k_sym_lds(const int *__restri
     mine = wave_sum(mine);
     if (lane == 0 && mine) atomicAdd(&s_cnt[g], mine);
     group_sync<WPR>();
-    if (active && wg == 0 && lane == 0) nnzc[row] = s_cnt[g];
+    if (active && gt == 0) nnzc[row] = s_cnt[g];
 }
 
 // -------------------------------------------------------- numeric, LDS hash
 
-// Key-value bitonic sort of n2 (a power of two) LDS entries by a group of
-// G threads whose index in the group is gt.
+// Key-value bitonic sort of n2 (a power of two) LDS entries by a group of G
+// threads whose index in the group is gt.
 template <typename V, int WPR>
 __device__ __forceinline__ void group_bitonic(int *keys, V *vals, int n2, int gt)
 {
@@ -462,11 +557,11 @@ __device__ __forceinline__ void group_bitonic(int *keys, V *vals, int n2, int gt
     }
 }
 
-// Numeric phase of light rows (steps a5 and a7): products merged in an LDS
-// tag/value table of 2^LOGT slots, then the occupied slots compacted,
-// sorted by column and written at the row's offset in C.
+// Light rows (steps a5 and a7): products merged in an LDS tag/value table of
+// 2^LOGT slots, then the occupied slots compacted, sorted by column and
+// written at the row's offset in C.
 template <typename V, int LOGT, int WPR, int RPW>
-__global__ __launch_bounds__(kWave *WPR *RPW) void k_num_lds(
+__global__ __launch_bounds__(kWave *WPR *RPW) void k_num_rows(
     const int *__restrict__ Arp, const int *__restrict__ Acol, const V *__restrict__ Aval,
     const int *__restrict__ Brp, const int *__restrict__ Bcol, const V *__restrict__ Bval,
     const int *__restrict__ rows, int nrows, const long long *__restrict__ Crp, int *__restrict__ Ccol,
@@ -479,13 +574,11 @@ __global__ __launch_bounds__(kWave *WPR *RPW) void k_num_lds(
     static_assert(SPT >= 1, "table smaller than its group");
     __shared__ int s_keys[RPW][T];
     __shared__ V s_vals[RPW][T];
-    __shared__ int s_incl[RPW * WPR][kWave];
-    __shared__ int s_bs[RPW * WPR][kWave];
-    __shared__ V s_a[RPW * WPR][kWave];
+    __shared__ EnumScratch<V, G> s_en[RPW];
     __shared__ int s_scan[RPW][WPR + 1];
     const int lane = lane_id(), wave = threadIdx.x / kWave;
     const int g = wave / WPR, wg = wave % WPR;
-    const int gt = wg * kWave + lane;
+    const int gt = threadIdx.x - g * G;
     const int r = blockIdx.x * RPW + g;
     const bool active = r < nrows;
     const int row = active ? rows[r] : 0;
@@ -497,8 +590,8 @@ __global__ __launch_bounds__(kWave *WPR *RPW) void k_num_lds(
     }
     group_sync<WPR>();
     if (active) {
-        wave_products<V, true>(
-            Arp[row], Arp[row + 1], wg, WPR, s_incl[wave], s_bs[wave], s_a[wave], Bcol, Bval,
+        group_products<V, true, G, 2>(
+            Arp[row], Arp[row + 1], gt, s_en[g], Bcol, Bval,
             [&](int e, int &bs, int &bl, V &a) {
                 const int k = Acol[e];
                 bs = Brp[k];
@@ -518,7 +611,7 @@ __global__ __launch_bounds__(kWave *WPR *RPW) void k_num_lds(
         vr[s] = vals[gt * SPT + s];
         cnt += kr[s] != kEmpty;
     }
-    int incl = wave_incl_scan(cnt);
+    const int incl = wave_incl_scan(cnt);
     if (lane == kWave - 1) s_scan[g][wg] = incl;
     group_sync<WPR>();
     int wbase = 0, total = 0;
@@ -555,13 +648,14 @@ __global__ __launch_bounds__(kWave *WPR *RPW) void k_num_lds(
 
 // ---------------------------------------------------------------- row scan
 
-// C_row_ptr = exclusive prefix of the row counts, in three passes over
-// blocks of kScanItems rows.
+// out = exclusive prefix of cnt (int or int64 counts) in three passes over
+// blocks of kScanItems entries; out[n] and *total receive the sum.
 constexpr int kScanThreads = 256;
 constexpr int kScanPer = 16;
 constexpr int kScanItems = kScanThreads * kScanPer;
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(int m, const int *__restrict__ cnt,
+template <typename TIn>
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(long long n, const TIn *__restrict__ cnt,
                                                               long long *__restrict__ bsum)
 {
     __shared__ long long s_tmp[kScanThreads / kWave + 1];
@@ -569,7 +663,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(int m, const int *
     long long s = 0;
 #pragma unroll
     for (int t = 0; t < kScanPer; ++t)
-        if (base + t < m) s += cnt[base + t];
+        if (base + t < n) s += cnt[base + t];
     long long total;
     block_excl_scan<long long, kScanThreads>(s, s_tmp, total);
     if (threadIdx.x == 0) bsum[blockIdx.x] = total;
@@ -596,31 +690,32 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_top(int nb, long long *__
     if (threadIdx.x == 0) *total_out = s_carry;
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_apply(int m, const int *__restrict__ cnt,
+template <typename TIn>
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(long long n, const TIn *__restrict__ cnt,
                                                              const long long *__restrict__ boff,
                                                              const long long *__restrict__ total,
                                                              long long *__restrict__ out)
 {
     __shared__ long long s_tmp[kScanThreads / kWave + 1];
     const long long base = (long long)blockIdx.x * kScanItems + threadIdx.x * kScanPer;
-    int v[kScanPer];
+    long long v[kScanPer];
     long long s = 0;
 #pragma unroll
     for (int t = 0; t < kScanPer; ++t) {
-        v[t] = base + t < m ? cnt[base + t] : 0;
+        v[t] = base + t < n ? (long long)cnt[base + t] : 0;
         s += v[t];
     }
     long long tot;
     long long run = block_excl_scan<long long, kScanThreads>(s, s_tmp, tot) + boff[blockIdx.x];
 #pragma unroll
     for (int t = 0; t < kScanPer; ++t) {
-        if (base + t < m) out[base + t] = run;
+        if (base + t < n) out[base + t] = run;
         run += v[t];
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) out[m] = *total;
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = *total;
 }
 
-// ------------------------------------------------- heavy rows: windowed path
+// ------------------------------------------------------ heavy rows: chunks
 
 // lower_bound of `x` in the ascending columns Bcol[lo, hi).
 __device__ __forceinline__ int lower_bound_col(const int *__restrict__ Bcol, int lo, int hi, int x)
@@ -633,85 +728,111 @@ __device__ __forceinline__ int lower_bound_col(const int *__restrict__ Bcol, int
     return lo;
 }
 
-// Symbolic phase of heavy rows: one block per row marks the row's columns in
-// an LDS bitmap over windows of kSymWindowBits columns and records the
-// number of columns in every kChunkCols-wide chunk (wcnt) and in the row.
-__global__ __launch_bounds__(kHeavyThreads) void k_sym_heavy(
-    const int *__restrict__ Arp, const int *__restrict__ Acol, const int *__restrict__ Brp,
-    const int *__restrict__ Bcol, const int *__restrict__ rows, int ncols, int nchunks,
-    int *__restrict__ wcnt, int *__restrict__ nnzc, int *err)
-{
-    extern __shared__ unsigned s_dyn[];
-    constexpr int NW = kHeavyThreads / kWave;
-    unsigned *bm = s_dyn;                                           // window bitmap
-    const int wbits = ncols < kSymWindowBits ? ((ncols + 31) & ~31) : kSymWindowBits;
-    const int words = wbits / 32;
-    int *s_incl = (int *)(bm + words);                              // [NW][64]
-    int *s_bs = s_incl + NW * kWave;                                // [NW][64]
-    __shared__ int s_row_total;
-    const int lane = lane_id(), wave = threadIdx.x / kWave;
-    const int row = rows[blockIdx.x];
-    const int e0 = Arp[row], e1 = Arp[row + 1];
-    const int nwin = (ncols + kSymWindowBits - 1) / kSymWindowBits;
-    if (threadIdx.x == 0) s_row_total = 0;
-    for (int w = 0; w < nwin; ++w) {
-        const int lo = w * kSymWindowBits;
-        const int hi = lo + wbits < ncols ? lo + wbits : ncols;
-        for (int t = threadIdx.x; t < words; t += kHeavyThreads) bm[t] = 0u;
-        __syncthreads();
-        wave_products<float, false>(
-            e0, e1, wave, NW, s_incl + wave * kWave, s_bs + wave * kWave, (float *)nullptr, Bcol,
-            (const float *)nullptr,
-            [&](int e, int &bs, int &bl, float &) {
-                const int k = Acol[e];
-                int b0 = Brp[k], b1 = Brp[k + 1];
-                if (nwin > 1) {
-                    b0 = lower_bound_col(Bcol, b0, b1, lo);
-                    b1 = lower_bound_col(Bcol, b0, b1, hi);
-                }
-                bs = b0;
-                bl = b1 - b0;
-            },
-            [&](int j) {
-                const int jl = j - lo;
-                atomicOr(&bm[jl >> 5], 1u << (jl & 31));
-            });
-        __syncthreads();
-        // per-chunk counts: kChunkWords words per chunk
-        const int first_chunk = lo / kChunkCols;
-        const int wchunks = (words + kChunkWords - 1) / kChunkWords;
-        int local = 0;
-        for (int c = wave; c < wchunks; c += NW) {
-            int pc = 0;
-            for (int t = lane; t < kChunkWords; t += kWave) {
-                const int wd = c * kChunkWords + t;
-                if (wd < words) pc += __popc(bm[wd]);
-            }
-            pc = wave_sum(pc);
-            if (lane == 0 && first_chunk + c < nchunks) wcnt[(long long)blockIdx.x * nchunks + first_chunk + c] = pc;
-            local += pc;
-        }
-        if (lane == 0 && local) atomicAdd(&s_row_total, local);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) nnzc[row] = s_row_total;
-}
-
-// Split points of every B row at the numeric window boundaries:
-// Bsplit[k * (nwin + 1) + w] = first position of row k with column >= w * W.
-__global__ __launch_bounds__(256) void k_bsplit(int brows, int W, int nwin, const int *__restrict__ Brp,
+// Split points of every B row at the chunk boundaries:
+// Bsplit[k * (nchunks + 1) + c] = first position of row k with column >= c * kChunkCols.
+__global__ __launch_bounds__(256) void k_bsplit(int brows, int nchunks, const int *__restrict__ Brp,
                                                 const int *__restrict__ Bcol, int *__restrict__ Bsplit)
 {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long per = nwin + 1;
+    const long long per = nchunks + 1;
     if (t >= (long long)brows * per) return;
-    const int k = (int)(t / per), w = (int)(t % per);
+    const int k = (int)(t / per), c = (int)(t % per);
     const int b0 = Brp[k], b1 = Brp[k + 1];
     int pos;
-    if (w == 0) pos = b0;
-    else if (w == nwin) pos = b1;
-    else pos = lower_bound_col(Bcol, b0, b1, w * W);
+    if (c == 0) pos = b0;
+    else if (c == nchunks) pos = b1;
+    else pos = lower_bound_col(Bcol, b0, b1, c * kChunkCols);
     Bsplit[t] = pos;
+}
+
+// Symbolic phase of heavy rows: block (h, w) marks the columns of heavy row h
+// that fall in symbolic window w (kSymWinChunks chunks) in an LDS bitmap and
+// stores the number of columns of every chunk (wcnt) and adds them to the
+// row's count.  Each thread walks R consecutive products and ORs their bits
+// into a register until the bitmap word changes, so the LDS atomics of a
+// dense B row are merged and the lanes of one instruction hit distinct words.
+constexpr int kSymHeavyThreads = 256;
+constexpr int kSymRun = 16;
+
+__global__ __launch_bounds__(kSymHeavyThreads) void k_sym_heavy(
+    const int *__restrict__ Arp, const int *__restrict__ Acol, const int *__restrict__ Bcol,
+    const int *__restrict__ Bsplit, const int *__restrict__ rows, int nwin, int nchunks,
+    int *__restrict__ wcnt, int *__restrict__ nnzc)
+{
+    constexpr int G = kSymHeavyThreads;
+    constexpr int WG = G / kWave;
+    constexpr int WORDS = kSymWinChunks * kChunkWords;
+    __shared__ unsigned bm[WORDS];
+    __shared__ EnumScratch<float, G> S;
+    const int h = blockIdx.x / nwin, w = blockIdx.x % nwin;
+    const int row = rows[h];
+    const int gt = threadIdx.x, lane = lane_id(), wg = gt / kWave;
+    const int c0 = w * kSymWinChunks;
+    const int c1 = c0 + kSymWinChunks < nchunks ? c0 + kSymWinChunks : nchunks;
+    const int lo = c0 * kChunkCols;
+    const long long per = nchunks + 1;
+    for (int t = gt; t < WORDS; t += G) bm[t] = 0u;
+    __syncthreads();
+    const int e0 = Arp[row], e1 = Arp[row + 1];
+    for (int base = e0; base < e1; base += G) {
+        const int e = base + gt;
+        int bs = 0, bl = 0;
+        if (e < e1) {
+            const long long k = Acol[e];
+            bs = Bsplit[k * per + c0];
+            bl = Bsplit[k * per + c1] - bs;
+        }
+        int incl = wave_incl_scan(bl);
+        if (lane == kWave - 1) S.wsum[wg] = incl;
+        __syncthreads();
+        int add = 0;
+        for (int v = 0; v < wg; ++v) add += S.wsum[v];
+        incl += add;
+        S.incl[gt] = incl;
+        S.bs[gt] = bs;
+        __syncthreads();
+        const int total = S.incl[G - 1];
+        for (int q0 = gt * kSymRun; q0 < total; q0 += G * kSymRun) {
+            const int q1 = q0 + kSymRun < total ? q0 + kSymRun : total;
+            int src = 0;
+#pragma unroll
+            for (int step = G / 2; step > 0; step >>= 1)
+                if (S.incl[src + step - 1] <= q0) src += step;
+            int excl = src ? S.incl[src - 1] : 0;
+            int end = S.incl[src];
+            int pos = S.bs[src] + (q0 - excl);
+            int cur = -1;
+            unsigned bits = 0u;
+            for (int q = q0; q < q1; ++q) {
+                while (q >= end) {              // next A entry with a non-empty range
+                    ++src;
+                    excl = end;
+                    end = S.incl[src];
+                    pos = S.bs[src];
+                }
+                const int jl = Bcol[pos++] - lo;
+                const int wd = jl >> 5;
+                if (wd != cur) {
+                    if (cur >= 0) atomicOr(&bm[cur], bits);
+                    cur = wd;
+                    bits = 0u;
+                }
+                bits |= 1u << (jl & 31);
+            }
+            if (cur >= 0) atomicOr(&bm[cur], bits);
+        }
+        __syncthreads();
+    }
+    // per-chunk counts: one wave per chunk
+    int local = 0;
+    for (int c = wg; c < c1 - c0; c += WG) {
+        int pc = 0;
+        for (int t = lane; t < kChunkWords; t += kWave) pc += __popc(bm[c * kChunkWords + t]);
+        pc = wave_sum(pc);
+        if (lane == 0) wcnt[(long long)h * nchunks + c0 + c] = pc;
+        local += pc;
+    }
+    if (lane == 0 && local) atomicAdd(&nnzc[row], local);
 }
 
 // Exclusive prefix of the chunk counts of every heavy row (row-relative output
@@ -729,87 +850,275 @@ __global__ __launch_bounds__(256) void k_chunk_prefix(int nheavy, int nchunks, c
     }
 }
 
-// Numeric phase of heavy rows, windowed: block (h, w) accumulates the
-// products of heavy row h whose columns fall in window w (UNITS chunks) into
-// a dense LDS array plus an occupancy bitmap, then writes the window's
-// entries in column order at their final offsets (bitmap rank).
-template <typename V, int UNITS>
-__global__ __launch_bounds__(kHeavyThreads) void k_num_heavy_dense(
+// Cuts every heavy row into segments (one thread per heavy row): a chunk
+// with more than kSegCap columns is a dense segment of its own; otherwise
+// consecutive chunks are merged while the count stays <= kSegCap and the
+// span <= kSegMaxSpan chunks.  Pass 0 counts segments per block and bin;
+// pass 1 writes them at offset[bin] + block base + rank in block.
+__device__ __forceinline__ int seg_bin(int count, bool dense)
+{
+    return dense ? kSegDense : (count <= 128 ? 0 : (count <= 512 ? 1 : 2));
+}
+
+template <typename F>
+__device__ __forceinline__ void plan_row_segments(const int *__restrict__ wc, int nchunks, F emit)
+{
+    int c = 0;
+    while (c < nchunks) {
+        const int n0 = wc[c];
+        if (n0 == 0) { ++c; continue; }
+        if (n0 > kSegCap) { emit(c, c + 1, n0, true); ++c; continue; }
+        const int start = c;
+        int sum = 0, last = c;
+        while (c < nchunks && c - start < kSegMaxSpan) {
+            const int n = wc[c];
+            if (n > kSegCap || sum + n > kSegCap) break;
+            sum += n;
+            if (n) last = c;
+            ++c;
+        }
+        emit(start, last + 1, sum, false);
+        c = last + 1;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_seg_plan(int pass, int nheavy, int nchunks, const int *__restrict__ wcnt,
+                                                  int *__restrict__ bcount, SegHdr *sh, Seg *__restrict__ segs)
+{
+    __shared__ int s_cnt[kSegBins];
+    __shared__ unsigned long long s_nnz[kSegBins];
+    if (threadIdx.x < kSegBins) {
+        s_cnt[threadIdx.x] = 0;
+        s_nnz[threadIdx.x] = 0;
+    }
+    __syncthreads();
+    const int h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h < nheavy) {
+        const int *wc = wcnt + (long long)h * nchunks;
+        if (pass == 0) {
+            int local[kSegBins] = {0, 0, 0, 0};
+            long long lnnz[kSegBins] = {0, 0, 0, 0};
+            plan_row_segments(wc, nchunks, [&](int, int, int n, bool dense) {
+                const int b = seg_bin(n, dense);
+                ++local[b];
+                lnnz[b] += n;
+            });
+            for (int b = 0; b < kSegBins; ++b) {
+                if (local[b]) atomicAdd(&s_cnt[b], local[b]);
+                if (lnnz[b]) atomicAdd(&s_nnz[b], (unsigned long long)lnnz[b]);
+            }
+        } else {
+            plan_row_segments(wc, nchunks, [&](int a, int b, int n, bool dense) {
+                const int bin = seg_bin(n, dense);
+                const int pos = sh->offset[bin] + bcount[blockIdx.x * kSegBins + bin] + atomicAdd(&s_cnt[bin], 1);
+                segs[pos] = Seg{h, a, b, n};
+            });
+        }
+    }
+    __syncthreads();
+    if (pass == 0 && threadIdx.x < kSegBins) {
+        bcount[blockIdx.x * kSegBins + threadIdx.x] = s_cnt[threadIdx.x];
+        if (s_nnz[threadIdx.x]) atomicAdd((unsigned long long *)&sh->nnz[threadIdx.x], s_nnz[threadIdx.x]);
+    }
+}
+
+// Segment bin totals, offsets and per-block bases (one block).
+__global__ __launch_bounds__(kWave) void k_seg_scan(int nblk, int *__restrict__ bcount, SegHdr *sh)
+{
+    const int lane = lane_id();
+    int tot[kSegBins];
+    for (int b = 0; b < kSegBins; ++b) {
+        int run = 0;
+        for (int c0 = 0; c0 < nblk; c0 += kWave) {
+            const int c = c0 + lane;
+            const int v = c < nblk ? bcount[c * kSegBins + b] : 0;
+            const int incl = wave_incl_scan(v);
+            if (c < nblk) bcount[c * kSegBins + b] = run + incl - v;
+            run += __shfl(incl, kWave - 1, kWave);
+        }
+        tot[b] = run;
+    }
+    if (lane == 0) {
+        int run = 0;
+        for (int b = 0; b < kSegBins; ++b) {
+            sh->count[b] = tot[b];
+            sh->offset[b] = run;
+            run += tot[b];
+        }
+        sh->offset[kSegBins] = run;
+    }
+}
+
+// Hashed segment of a heavy row: products of the row whose columns lie in
+// chunks [c0, c1) merged in an LDS table of 2^LOGT slots; entries ranked by
+// an occupancy bitmap of the segment's columns, staged in column order in
+// the table's own storage and copied out with coalesced stores.
+constexpr int kSegWords = kSegMaxSpan * kChunkWords;
+constexpr int kSegPrefGroup = 8;        // bitmap words per prefix entry
+
+template <typename V, int LOGT, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_num_seg(
     const int *__restrict__ Arp, const int *__restrict__ Acol, const V *__restrict__ Aval,
     const int *__restrict__ Bcol, const V *__restrict__ Bval, const int *__restrict__ Bsplit,
-    const int *__restrict__ rows, int nwin, int nchunks, const int *__restrict__ wcnt,
+    const int *__restrict__ heavy_rows, const Seg *__restrict__ segs, int nchunks,
     const int *__restrict__ woff, const long long *__restrict__ Crp, int *__restrict__ Ccol,
-    V *__restrict__ Cval, int *err, int *nonempty)
+    V *__restrict__ Cval, int *err)
 {
-    constexpr int W = UNITS * kChunkCols;
-    constexpr int WORDS = W / 32;
-    constexpr int NW = kHeavyThreads / kWave;
-    constexpr int WPT = (WORDS + kHeavyThreads - 1) / kHeavyThreads;
-    extern __shared__ unsigned char s_raw[];
-    V *acc = (V *)s_raw;                                   // [W]
-    unsigned *bm = (unsigned *)(acc + W);                  // [WORDS]
-    int *s_incl = (int *)(bm + WORDS);                     // [NW][64]
-    int *s_bs = s_incl + NW * kWave;                       // [NW][64]
-    V *s_a = (V *)(s_bs + NW * kWave);                     // [NW][64]
-    __shared__ long long s_tmp[kHeavyThreads / kWave + 1];
-    const int h = blockIdx.x / nwin, w = blockIdx.x % nwin;
-    const long long cb = (long long)h * nchunks;
-    const int c0 = w * UNITS;
-    int count = 0;
-#pragma unroll
-    for (int u = 0; u < UNITS; ++u)
-        if (c0 + u < nchunks) count += wcnt[cb + c0 + u];
-    if (count == 0) return;
-    if (threadIdx.x == 0) atomicAdd(nonempty, 1);
-    const int row = rows[h];
-    const long long out0 = Crp[row] + woff[cb + c0];
-    for (int t = threadIdx.x; t < W; t += kHeavyThreads) acc[t] = V(0);
-    for (int t = threadIdx.x; t < WORDS; t += kHeavyThreads) bm[t] = 0u;
+    constexpr int T = 1 << LOGT;
+    constexpr int SPT = T / THREADS;
+    static_assert(SPT >= 1, "table smaller than the block");
+    __shared__ int keys[T];
+    __shared__ V vals[T];
+    __shared__ unsigned bm[kSegWords];
+    __shared__ int pref[kSegWords / kSegPrefGroup];
+    __shared__ EnumScratch<V, THREADS> S;
+    __shared__ int s_tmp[THREADS / kWave + 1];
+    const Seg sg = segs[blockIdx.x];
+    const int row = heavy_rows[sg.h];
+    const int gt = threadIdx.x;
+    const int lo = sg.c0 * kChunkCols;
+    const int words = (sg.c1 - sg.c0) * kChunkWords;
+    const long long per = nchunks + 1;
+    for (int t = gt; t < T; t += THREADS) {
+        keys[t] = kEmpty;
+        vals[t] = V(0);
+    }
+    for (int t = gt; t < words; t += THREADS) bm[t] = 0u;
     __syncthreads();
-    const int lane = lane_id(), wave = threadIdx.x / kWave;
-    const int lo = w * W;
-    const long long per = nwin + 1;
-    wave_products<V, true>(
-        Arp[row], Arp[row + 1], wave, NW, s_incl + wave * kWave, s_bs + wave * kWave, s_a + wave * kWave, Bcol, Bval,
+    group_products<V, true, THREADS, 2>(
+        Arp[row], Arp[row + 1], gt, S, Bcol, Bval,
         [&](int e, int &bs, int &bl, V &a) {
             const long long k = Acol[e];
-            bs = Bsplit[k * per + w];
-            bl = Bsplit[k * per + w + 1] - bs;
+            bs = Bsplit[k * per + sg.c0];
+            bl = Bsplit[k * per + sg.c1] - bs;
+            a = Aval[e];
+        },
+        [&](int j, V p) { lds_insert_add(keys, vals, LOGT, j, p, err); });
+    __syncthreads();
+    int kr[SPT];
+    V vr[SPT];
+#pragma unroll
+    for (int s = 0; s < SPT; ++s) {
+        kr[s] = keys[s * THREADS + gt];
+        vr[s] = vals[s * THREADS + gt];
+        if (kr[s] != kEmpty) {
+            const int jl = kr[s] - lo;
+            atomicOr(&bm[jl >> 5], 1u << (jl & 31));
+        }
+    }
+    __syncthreads();
+    // prefix of popcounts per group of kSegPrefGroup words
+    const int ngroups = words / kSegPrefGroup;
+    int tot_all = 0;
+    for (int g0 = 0; g0 < ngroups; g0 += THREADS) {
+        const int g = g0 + gt;
+        int pc = 0;
+        if (g < ngroups)
+#pragma unroll
+            for (int q = 0; q < kSegPrefGroup; ++q) pc += __popc(bm[g * kSegPrefGroup + q]);
+        int tot;
+        const int ex = block_excl_scan<int, THREADS>(pc, s_tmp, tot);
+        if (g < ngroups) pref[g] = tot_all + ex;
+        tot_all += tot;
+    }
+    __syncthreads();
+    if (gt == 0 && tot_all != sg.count) atomicOr(err, kErrCount);
+#pragma unroll
+    for (int s = 0; s < SPT; ++s) {
+        if (kr[s] == kEmpty) continue;
+        const int jl = kr[s] - lo;
+        const int wd = jl >> 5;
+        int rank = pref[wd / kSegPrefGroup];
+        for (int q = wd & ~(kSegPrefGroup - 1); q < wd; ++q) rank += __popc(bm[q]);
+        rank += __popc(bm[wd] & ((1u << (jl & 31)) - 1u));
+        if (rank < T) {
+            keys[rank] = kr[s];
+            vals[rank] = vr[s];
+        }
+    }
+    __syncthreads();
+    const long long out0 = Crp[row] + woff[(long long)sg.h * nchunks + sg.c0];
+    const int n = tot_all < sg.count ? tot_all : sg.count;
+    for (int t = gt; t < n; t += THREADS) {
+        Ccol[out0 + t] = keys[t];
+        Cval[out0 + t] = vals[t];
+    }
+}
+
+// Dense chunk of a heavy row: products whose columns lie in chunk c0 added
+// directly into an LDS array indexed by column, with a per-column flag; the
+// flagged columns are compacted in column order in LDS and copied out with
+// coalesced stores.
+constexpr int kDenseThreads = 512;
+
+template <typename V>
+__global__ __launch_bounds__(kDenseThreads) void k_num_dense(
+    const int *__restrict__ Arp, const int *__restrict__ Acol, const V *__restrict__ Aval,
+    const int *__restrict__ Bcol, const V *__restrict__ Bval, const int *__restrict__ Bsplit,
+    const int *__restrict__ heavy_rows, const Seg *__restrict__ segs, int nchunks,
+    const int *__restrict__ woff, const long long *__restrict__ Crp, int *__restrict__ Ccol,
+    V *__restrict__ Cval, int *err)
+{
+    constexpr int CPT = kChunkCols / kDenseThreads;   // columns per thread in the compaction
+    extern __shared__ unsigned char s_raw[];
+    V *acc = (V *)s_raw;                                // [kChunkCols]
+    int *flag = (int *)(acc + kChunkCols);              // [kChunkCols]
+    __shared__ EnumScratch<V, kDenseThreads> S;
+    __shared__ int s_tmp[kDenseThreads / kWave + 1];
+    const Seg sg = segs[blockIdx.x];
+    const int row = heavy_rows[sg.h];
+    const int gt = threadIdx.x;
+    const int lo = sg.c0 * kChunkCols;
+    const long long per = nchunks + 1;
+    for (int t = gt; t < kChunkCols; t += kDenseThreads) {
+        acc[t] = V(0);
+        flag[t] = 0;
+    }
+    __syncthreads();
+    group_products<V, true, kDenseThreads, 2>(
+        Arp[row], Arp[row + 1], gt, S, Bcol, Bval,
+        [&](int e, int &bs, int &bl, V &a) {
+            const long long k = Acol[e];
+            bs = Bsplit[k * per + sg.c0];
+            bl = Bsplit[k * per + sg.c0 + 1] - bs;
             a = Aval[e];
         },
         [&](int j, V p) {
             const int jl = j - lo;
             atomicAdd(&acc[jl], p);
-            atomicOr(&bm[jl >> 5], 1u << (jl & 31));
+            flag[jl] = 1;
         });
     __syncthreads();
-    // rank of every set bit: thread t owns words [t*WPT, (t+1)*WPT)
-    int pc = 0;
+    V vr[CPT];
+    int cnt = 0;
+    unsigned present = 0u;
 #pragma unroll
-    for (int q = 0; q < WPT; ++q) {
-        const int wd = threadIdx.x * WPT + q;
-        if (wd < WORDS) pc += __popc(bm[wd]);
-    }
-    long long tot;
-    long long rank = block_excl_scan<long long, kHeavyThreads>((long long)pc, s_tmp, tot);
-    if (threadIdx.x == 0 && tot != count) atomicOr(err, kErrCount);
-#pragma unroll
-    for (int q = 0; q < WPT; ++q) {
-        const int wd = threadIdx.x * WPT + q;
-        if (wd >= WORDS) break;
-        unsigned bits = bm[wd];
-        while (bits) {
-            const int b = __ffs(bits) - 1;
-            bits &= bits - 1;
-            const int jl = wd * 32 + b;
-            if (rank < count) {
-                Ccol[out0 + rank] = lo + jl;
-                Cval[out0 + rank] = acc[jl];
-            }
-            ++rank;
+    for (int q = 0; q < CPT; ++q) {
+        const int jl = gt * CPT + q;
+        vr[q] = acc[jl];
+        if (flag[jl]) {
+            present |= 1u << q;
+            ++cnt;
         }
     }
-    (void)lane;
+    int tot;
+    int pos = block_excl_scan<int, kDenseThreads>(cnt, s_tmp, tot);
+    if (gt == 0 && tot != sg.count) atomicOr(err, kErrCount);
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+        if (present & (1u << q)) {
+            flag[pos] = lo + gt * CPT + q;
+            acc[pos] = vr[q];
+            ++pos;
+        }
+    }
+    __syncthreads();
+    const long long out0 = Crp[row] + woff[(long long)sg.h * nchunks + sg.c0];
+    const int n = tot < sg.count ? tot : sg.count;
+    for (int t = gt; t < n; t += kDenseThreads) {
+        Ccol[out0 + t] = flag[t];
+        Cval[out0 + t] = acc[t];
+    }
 }
 
 // ---------------------------------------------- heavy rows: global hash path
@@ -832,32 +1141,26 @@ __global__ __launch_bounds__(256) void k_fill_i32(long long n, int *__restrict__
         p[t] = v;
 }
 
-template <typename V>
-__global__ __launch_bounds__(256) void k_fill_zero(long long n, V *__restrict__ p)
-{
-    for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long long)gridDim.x * blockDim.x)
-        p[t] = V(0);
-}
+constexpr int kGlobalThreads = 1024;
 
 // Symbolic phase of heavy rows in global mode: one block per row inserts the
 // row's columns in its global key table (device-scope CAS) and counts them.
-__global__ __launch_bounds__(kHeavyThreads) void k_sym_global(
+__global__ __launch_bounds__(kGlobalThreads) void k_sym_global(
     const int *__restrict__ Arp, const int *__restrict__ Acol, const int *__restrict__ Brp,
     const int *__restrict__ Bcol, const int *__restrict__ rows, const int *__restrict__ cap,
     const long long *__restrict__ goff, int *gkeys, int *__restrict__ nnzc, int *err)
 {
-    constexpr int NW = kHeavyThreads / kWave;
-    __shared__ int s_incl[NW][kWave], s_bs[NW][kWave];
+    __shared__ EnumScratch<float, kGlobalThreads> S;
     __shared__ int s_cnt;
-    const int lane = lane_id(), wave = threadIdx.x / kWave;
+    const int lane = lane_id();
     const int row = rows[blockIdx.x];
     const int logT = gtable_log2(cap[row]);
     const unsigned mask = (1u << logT) - 1;
     int *keys = gkeys + goff[blockIdx.x];
     if (threadIdx.x == 0) s_cnt = 0;
     int mine = 0;
-    wave_products<float, false>(
-        Arp[row], Arp[row + 1], wave, NW, s_incl[wave], s_bs[wave], (float *)nullptr, Bcol, (const float *)nullptr,
+    group_products<float, false, kGlobalThreads, 2>(
+        Arp[row], Arp[row + 1], threadIdx.x, S, Bcol, (const float *)nullptr,
         [&](int e, int &bs, int &bl, float &) {
             const int k = Acol[e];
             bs = Brp[k];
@@ -891,21 +1194,18 @@ __global__ __launch_bounds__(kHeavyThreads) void k_sym_global(
 constexpr int kGlobalRankBits = 1 << 19;
 
 template <typename V>
-__global__ __launch_bounds__(kHeavyThreads) void k_num_global(
+__global__ __launch_bounds__(kGlobalThreads) void k_num_global(
     const int *__restrict__ Arp, const int *__restrict__ Acol, const V *__restrict__ Aval,
     const int *__restrict__ Brp, const int *__restrict__ Bcol, const V *__restrict__ Bval,
     const int *__restrict__ rows, int ncols, const long long *__restrict__ goff, int *gkeys, V *gvals,
     const long long *__restrict__ Crp, int *__restrict__ Ccol, V *__restrict__ Cval, int *err)
 {
-    constexpr int NW = kHeavyThreads / kWave;
     constexpr int WORDS = kGlobalRankBits / 32;
-    constexpr int WPT = WORDS / kHeavyThreads;
+    constexpr int WPT = WORDS / kGlobalThreads;
     extern __shared__ unsigned s_bm[];                     // [WORDS]
-    __shared__ int s_incl[NW][kWave], s_bs[NW][kWave];
-    __shared__ V s_a[NW][kWave];
-    __shared__ long long s_tmp[kHeavyThreads / kWave + 1];
-    __shared__ int s_base[kHeavyThreads];
-    const int wave = threadIdx.x / kWave;
+    __shared__ EnumScratch<V, kGlobalThreads> S;
+    __shared__ long long s_tmp[kGlobalThreads / kWave + 1];
+    __shared__ int s_base[kGlobalThreads];
     const int row = rows[blockIdx.x];
     const long long rb = Crp[row];
     const int nc = (int)(Crp[row + 1] - rb);
@@ -914,14 +1214,14 @@ __global__ __launch_bounds__(kHeavyThreads) void k_num_global(
     const unsigned mask = (unsigned)T - 1;
     int *keys = gkeys + goff[blockIdx.x];
     V *vals = gvals + goff[blockIdx.x];
-    for (int t = threadIdx.x; t < T; t += kHeavyThreads) {
+    for (int t = threadIdx.x; t < T; t += kGlobalThreads) {
         keys[t] = kEmpty;
         vals[t] = V(0);
     }
     __threadfence();
     __syncthreads();
-    wave_products<V, true>(
-        Arp[row], Arp[row + 1], wave, NW, s_incl[wave], s_bs[wave], s_a[wave], Bcol, Bval,
+    group_products<V, true, kGlobalThreads, 2>(
+        Arp[row], Arp[row + 1], threadIdx.x, S, Bcol, Bval,
         [&](int e, int &bs, int &bl, V &a) {
             const int k = Acol[e];
             bs = Brp[k];
@@ -949,9 +1249,9 @@ __global__ __launch_bounds__(kHeavyThreads) void k_num_global(
     long long done = 0;
     for (int lo = 0; lo < ncols; lo += kGlobalRankBits) {
         const int hi = lo + kGlobalRankBits < ncols ? lo + kGlobalRankBits : ncols;
-        for (int t = threadIdx.x; t < WORDS; t += kHeavyThreads) s_bm[t] = 0u;
+        for (int t = threadIdx.x; t < WORDS; t += kGlobalThreads) s_bm[t] = 0u;
         __syncthreads();
-        for (int t = threadIdx.x; t < T; t += kHeavyThreads) {
+        for (int t = threadIdx.x; t < T; t += kGlobalThreads) {
             const int j = gload(&keys[t]);
             if (j != kEmpty && j >= lo && j < hi) atomicOr(&s_bm[(j - lo) >> 5], 1u << ((j - lo) & 31));
         }
@@ -959,10 +1259,10 @@ __global__ __launch_bounds__(kHeavyThreads) void k_num_global(
         int pc = 0;
         for (int q = 0; q < WPT; ++q) pc += __popc(s_bm[threadIdx.x * WPT + q]);
         long long tot;
-        const long long ex = block_excl_scan<long long, kHeavyThreads>((long long)pc, s_tmp, tot);
+        const long long ex = block_excl_scan<long long, kGlobalThreads>((long long)pc, s_tmp, tot);
         s_base[threadIdx.x] = (int)ex;
         __syncthreads();
-        for (int t = threadIdx.x; t < T; t += kHeavyThreads) {
+        for (int t = threadIdx.x; t < T; t += kGlobalThreads) {
             const int j = gload(&keys[t]);
             if (j == kEmpty || j < lo || j >= hi) continue;
             const int jl = j - lo, wd = jl >> 5, owner = wd / WPT;

@@ -79,6 +79,7 @@ def test_rmat_s16(sm, ctx, oracle_mod, s16, dtype):
     full_check(sm, ctx, s16, None, dtype, oracle_mod, False, "s16")
     st = ctx.stats()
     assert st["rows_heavy"] > 0 and st["rows_lds"] > 0
+    assert st["heavy_segments"] > 0 and st["heavy_dense_chunks"] > 0
 
 
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
@@ -89,17 +90,14 @@ def test_rmat_s16_global_hash(sm, ctx, oracle_mod, s16, dtype):
 
 
 @pytest.mark.parametrize("mode", [0, 1])
-@pytest.mark.parametrize("units", [1, 2, 4])
-def test_forced_heavy_rows(sm, ctx, oracle_mod, mode, units):
-    # every row with more than 32 outputs takes the heavy-row path
+@pytest.mark.parametrize("row_max", [32, 300])
+def test_forced_heavy_rows(sm, ctx, oracle_mod, mode, row_max):
+    # every row with more than row_max outputs takes the heavy-row path
     A = syn.rmat(13, 8, 0x77, np.float32)
-    ctx.set_option(sm.OPT_LDS_ROW_MAX, 32)
+    ctx.set_option(sm.OPT_LDS_ROW_MAX, row_max)
     ctx.set_option(sm.OPT_HEAVY_MODE, mode)
-    ctx.set_option(sm.OPT_WINDOW_UNITS, units)
     for dtype in (np.float32, np.float64):
-        if dtype == np.float64 and units == 4:
-            continue
-        full_check(sm, ctx, A, None, dtype, oracle_mod, False, f"forced heavy mode={mode} units={units}")
+        full_check(sm, ctx, A, None, dtype, oracle_mod, False, f"forced heavy mode={mode} row_max={row_max}")
         assert ctx.stats()["rows_heavy"] > 100
 
 
