@@ -328,7 +328,7 @@ smash_status scan_counts(smash_ctx c, hipStream_t s, long long n, const TIn *cnt
     return SMASH_OK;
 }
 
-template <typename V, int LOGT>
+template <typename V, int LOGT, int THREADS>
 smash_status launch_seg_bin(smash_ctx c, hipStream_t s, const Plan &p, int bin, const V *Aval, const V *Bval,
                             const int64_t *crp, int32_t *ccol, V *cval)
 {
@@ -337,7 +337,7 @@ smash_status launch_seg_bin(smash_ctx c, hipStream_t s, const Plan &p, int bin, 
     const int *hrows = p.sym_perm + p.hdr.sym.offset[kBinHeavy];
     const Seg *segs = p.segs + p.hdr.seg.offset[bin];
     return launch(c, K_NUM_SEG, s, [&] {
-        k_num_seg<V, LOGT, 256><<<cnt, 256, 0, s>>>(p.A.row_ptr, p.A.col_idx, Aval, p.B.col_idx, Bval, p.bsplit,
+        k_num_seg<V, LOGT, THREADS><<<cnt, THREADS, 0, s>>>(p.A.row_ptr, p.A.col_idx, Aval, p.B.col_idx, Bval, p.bsplit,
                                                      hrows, segs, p.nchunks, p.woff, (const long long *)crp, ccol,
                                                      cval, &c->d_hdr->error);
     });
@@ -351,12 +351,12 @@ smash_status numeric_impl(smash_ctx c, hipStream_t s, const Plan &p, const V *Av
     const int H = p.hdr.sym.count[kBinHeavy];
     if (H == 0) return SMASH_OK;
     if (p.heavy_mode == 0) {
-        TRY(launch_seg_bin<V, 8>(c, s, p, 0, Aval, Bval, crp, ccol, cval));
-        TRY(launch_seg_bin<V, 10>(c, s, p, 1, Aval, Bval, crp, ccol, cval));
-        TRY(launch_seg_bin<V, 12>(c, s, p, 2, Aval, Bval, crp, ccol, cval));
+        TRY(launch_seg_bin<V, 8, 256>(c, s, p, 0, Aval, Bval, crp, ccol, cval));
+        TRY(launch_seg_bin<V, 10, 256>(c, s, p, 1, Aval, Bval, crp, ccol, cval));
+        TRY(launch_seg_bin<V, 11, 256>(c, s, p, 2, Aval, Bval, crp, ccol, cval));
         const int nd = p.hdr.seg.count[kSegDense];
         if (nd) {
-            const size_t lds = (size_t)kChunkCols * (sizeof(V) + sizeof(int));
+            const size_t lds = (size_t)kChunkCols * sizeof(double);
             (void)hipFuncSetAttribute((const void *)k_num_dense<V>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             const int *hrows = p.sym_perm + p.hdr.sym.offset[kBinHeavy];
             const Seg *segs = p.segs + p.hdr.seg.offset[kSegDense];
@@ -636,11 +636,13 @@ smash_status smash_spgemm_symbolic(smash_ctx c, const smash_csr *A, const smash_
             k_chunk_prefix<<<nhb, 256, 0, s>>>(H, p.nchunks, p.wcnt, p.woff);
         }));
         TRY(launch(c, K_SEG_PLAN, s, [&] {
-            k_seg_plan<<<nhb, 256, 0, s>>>(0, H, p.nchunks, p.wcnt, p.seg_bcount, &c->d_hdr->seg, p.segs);
+            k_seg_plan<<<nhb, 256, 0, s>>>(0, H, p.nchunks, p.wcnt, p.woff, heavy_rows, A->row_ptr,
+                                           (const long long *)C_row_ptr, p.seg_bcount, &c->d_hdr->seg, p.segs);
         }));
         TRY(launch(c, K_SEG_SCAN, s, [&] { k_seg_scan<<<1, kWave, 0, s>>>(nhb, p.seg_bcount, &c->d_hdr->seg); }));
         TRY(launch(c, K_SEG_PLAN, s, [&] {
-            k_seg_plan<<<nhb, 256, 0, s>>>(1, H, p.nchunks, p.wcnt, p.seg_bcount, &c->d_hdr->seg, p.segs);
+            k_seg_plan<<<nhb, 256, 0, s>>>(1, H, p.nchunks, p.wcnt, p.woff, heavy_rows, A->row_ptr,
+                                           (const long long *)C_row_ptr, p.seg_bcount, &c->d_hdr->seg, p.segs);
         }));
     }
     TRY(read_hdr(c, s));

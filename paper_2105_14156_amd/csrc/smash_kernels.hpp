@@ -51,9 +51,9 @@ constexpr int kNumBins = kLdsBins + 2;
 constexpr int kChunkCols = 8192;        // column granularity of heavy-row counts
 constexpr int kChunkWords = kChunkCols / 32;
 constexpr int kSymWinChunks = 16;       // symbolic heavy window: 16 chunks, 16 KiB bitmap
-constexpr int kSegCap = 2048;           // entries of one hashed segment (table of 4096 slots)
-constexpr int kSegMaxSpan = 16;         // chunks spanned by one hashed segment
-constexpr int kSegBins = 4;             // hashed segments with <=128, <=512, <=2048 entries; dense chunks
+constexpr int kSegCap = 1024;           // entries of one hashed segment (table of 2048 slots)
+constexpr int kSegMaxSpan = 8;          // chunks spanned by one hashed segment
+constexpr int kSegBins = 4;             // hashed segments with <=128, <=512, <=1024 entries; dense chunks
 constexpr int kSegDense = 3;
 constexpr int kBinBlockRows = 1024;     // rows per block of the binning kernels
 
@@ -86,9 +86,11 @@ struct DevHdr {
     int pad;
 };
 
-// A column segment of a heavy row: heavy index, chunk range, entry count.
+// A column segment of a heavy row: the row, its A entries, the chunk range,
+// the number of output entries and their offset in C.
 struct Seg {
-    int h, c0, c1, count;
+    int row, e0, e1, c0, c1, count;
+    long long out;
 };
 
 // ------------------------------------------------------------------ helpers
@@ -185,18 +187,25 @@ __device__ __forceinline__ T block_excl_scan(T v, T *s_tmp /* THREADS/64 + 1 */,
 // Shared LDS scratch of one group of G threads.
 template <typename V, int G>
 struct EnumScratch {
-    int incl[G];        // inclusive prefix of the B range lengths of the chunk
+    int pincl[G];       // inclusive prefix of the piece counts of the long B ranges
+    int sincl[G];       // inclusive prefix of the lengths of the short B ranges
     int bs[G];          // B range start of each A entry of the chunk
+    int be[G];          // B range end of each A entry of the chunk
     V a[G];             // value of each A entry of the chunk
-    int wsum[G / kWave + 1];
+    int wsum[2 * (G / kWave)];
 };
 
-// Calls sink(j, a * b) (or sink(j) without values) for every product of the
-// A entries [e0, e1) of one row, each restricted to the B range returned by
-// get(e, &bstart, &blen, &a).  All G threads of the group (thread index gt)
-// cooperate on each chunk of G A entries; thread gt takes products
-// q = gt, gt + G, ... of the chunk and finds its A entry by binary search
-// of the chunk's prefix.  U products are loaded before any is merged.
+// Calls sink(j, a * b) -- the product formed in double -- (or sink(j)
+// without values) for every product of the A entries [e0, e1) of one row,
+// each restricted to the B range returned by get(e, &bstart, &blen, &a).  The
+// G threads of the group (thread index gt) take the row in chunks of G A
+// entries.  B ranges of at least 64 entries are cut into pieces of 64
+// products: each wave takes U consecutive pieces at a time, finds their A
+// entry with one search that all its lanes share, and every lane loads one
+// product per piece (coalesced, no per-lane search).  Shorter ranges, which
+// carry few of the products, are enumerated flat: thread gt takes products
+// q = gt, gt + G, ... and finds its A entry by binary search.  U products per
+// thread are located and loaded before any is merged.
 template <typename V, bool WITH_VAL, int G, int U, typename Get, typename Sink>
 __device__ __forceinline__ void group_products(int e0, int e1, int gt, EnumScratch<V, G> &S,
                                                const int *__restrict__ Bcol, const V *__restrict__ Bval,
@@ -209,46 +218,100 @@ __device__ __forceinline__ void group_products(int e0, int e1, int gt, EnumScrat
         int bs = 0, bl = 0;
         V a = V(0);
         if (e < e1) get(e, bs, bl, a);
-        int incl = wave_incl_scan(bl);
+        const bool lng = bl >= kWave;
+        int ip = wave_incl_scan(lng ? (bl + kWave - 1) / kWave : 0);
+        int is = wave_incl_scan(lng ? 0 : bl);
         if constexpr (WG > 1) {
-            if (lane == kWave - 1) S.wsum[wg] = incl;
+            if (lane == kWave - 1) {
+                S.wsum[wg] = ip;
+                S.wsum[WG + wg] = is;
+            }
             group_sync<WG>();
-            int add = 0;
-            for (int w = 0; w < wg; ++w) add += S.wsum[w];
-            incl += add;
+            int ap = 0, as = 0;
+            for (int w = 0; w < wg; ++w) {
+                ap += S.wsum[w];
+                as += S.wsum[WG + w];
+            }
+            ip += ap;
+            is += as;
         }
-        S.incl[gt] = incl;
+        S.pincl[gt] = ip;
+        S.sincl[gt] = is;
         S.bs[gt] = bs;
+        S.be[gt] = bs + bl;
         if constexpr (WITH_VAL) S.a[gt] = a;
         group_sync<WG>();
-        const int total = S.incl[G - 1];
-        for (int q0 = 0; q0 < total; q0 += G * U) {
+        const int ptot = S.pincl[G - 1], stot = S.sincl[G - 1];
+        // long ranges, piece by piece
+        for (int pc0 = wg * U; pc0 < ptot; pc0 += WG * U) {
+            int src = 0;
+#pragma unroll
+            for (int step = G / 2; step > 0; step >>= 1)
+                if (S.pincl[src + step - 1] <= pc0) src += step;
             int pos[U];
-            V av[U];
+            double av[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int pc = pc0 + u;
+                pos[u] = -1;
+                av[u] = 0.0;
+                if (pc < ptot) {
+                    while (S.pincl[src] <= pc) ++src;
+                    const int pex = src ? S.pincl[src - 1] : 0;
+                    const int p = S.bs[src] + (pc - pex) * kWave + lane;
+                    if (p < S.be[src]) {
+                        pos[u] = p;
+                        if constexpr (WITH_VAL) av[u] = (double)S.a[src];
+                    }
+                }
+            }
+            int j[U];
+            double bv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                j[u] = 0;
+                bv[u] = 0.0;
+                if (pos[u] >= 0) {
+                    j[u] = Bcol[pos[u]];
+                    if constexpr (WITH_VAL) bv[u] = (double)Bval[pos[u]];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (pos[u] >= 0) {
+                    if constexpr (WITH_VAL) sink(j[u], av[u] * bv[u]);
+                    else sink(j[u]);
+                }
+            }
+        }
+        // short ranges, flat
+        for (int q0 = 0; q0 < stot; q0 += G * U) {
+            int pos[U];
+            double av[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int q = q0 + u * G + gt;
                 pos[u] = -1;
-                av[u] = V(0);
-                if (q < total) {
+                av[u] = 0.0;
+                if (q < stot) {
                     int src = 0;
 #pragma unroll
                     for (int step = G / 2; step > 0; step >>= 1)
-                        if (S.incl[src + step - 1] <= q) src += step;
-                    const int excl = src ? S.incl[src - 1] : 0;
+                        if (S.sincl[src + step - 1] <= q) src += step;
+                    const int excl = src ? S.sincl[src - 1] : 0;
                     pos[u] = S.bs[src] + (q - excl);
-                    if constexpr (WITH_VAL) av[u] = S.a[src];
+                    if constexpr (WITH_VAL) av[u] = (double)S.a[src];
                 }
             }
             int j[U];
-            V bv[U];
+            double bv[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 j[u] = 0;
-                bv[u] = V(0);
+                bv[u] = 0.0;
                 if (pos[u] >= 0) {
                     j[u] = Bcol[pos[u]];
-                    if constexpr (WITH_VAL) bv[u] = Bval[pos[u]];
+                    if constexpr (WITH_VAL) bv[u] = (double)Bval[pos[u]];
                 }
             }
 #pragma unroll
@@ -284,9 +347,9 @@ __device__ __forceinline__ int lds_insert_key(int *keys, int logT, int key, int 
     return 0;
 }
 
-// Claims or finds the slot of `key` and adds `p` to its value.
-template <typename V>
-__device__ __forceinline__ void lds_insert_add(int *keys, V *vals, int logT, int key, V p, int *err)
+// Claims or finds the slot of `key` and adds `p` to its value (values are
+// accumulated in double: the LDS FP64 atomic add is the fast one on gfx950).
+__device__ __forceinline__ void lds_insert_add(int *keys, double *vals, int logT, int key, double p, int *err)
 {
     const unsigned mask = (1u << logT) - 1;
     unsigned h = slot_of(key, logT);
@@ -514,7 +577,7 @@ __global__ __launch_bounds__(kWave *WPR *RPW) void k_sym_rows(const int *__restr
     group_sync<WPR>();
     int mine = 0;
     if (active) {
-        group_products<float, false, G, 2>(
+        group_products<float, false, G, 4>(
             Arp[row], Arp[row + 1], gt, s_en[g], Bcol, (const float *)nullptr,
             [&](int e, int &bs, int &bl, float &) {
                 const int k = Acol[e];
@@ -573,7 +636,7 @@ __global__ __launch_bounds__(kWave *WPR *RPW) void k_num_rows(
     constexpr int SPT = T / G;          // slots per thread in the compaction
     static_assert(SPT >= 1, "table smaller than its group");
     __shared__ int s_keys[RPW][T];
-    __shared__ V s_vals[RPW][T];
+    __shared__ double s_vals[RPW][T];
     __shared__ EnumScratch<V, G> s_en[RPW];
     __shared__ int s_scan[RPW][WPR + 1];
     const int lane = lane_id(), wave = threadIdx.x / kWave;
@@ -583,14 +646,14 @@ __global__ __launch_bounds__(kWave *WPR *RPW) void k_num_rows(
     const bool active = r < nrows;
     const int row = active ? rows[r] : 0;
     int *keys = s_keys[g];
-    V *vals = s_vals[g];
+    double *vals = s_vals[g];
     for (int t = gt; t < T; t += G) {
         keys[t] = kEmpty;
-        vals[t] = V(0);
+        vals[t] = 0.0;
     }
     group_sync<WPR>();
     if (active) {
-        group_products<V, true, G, 2>(
+        group_products<V, true, G, 4>(
             Arp[row], Arp[row + 1], gt, s_en[g], Bcol, Bval,
             [&](int e, int &bs, int &bl, V &a) {
                 const int k = Acol[e];
@@ -598,12 +661,12 @@ __global__ __launch_bounds__(kWave *WPR *RPW) void k_num_rows(
                 bl = Brp[k + 1] - bs;
                 a = Aval[e];
             },
-            [&](int j, V p) { lds_insert_add(keys, vals, LOGT, j, p, err); });
+            [&](int j, double p) { lds_insert_add(keys, vals, LOGT, j, p, err); });
     }
     group_sync<WPR>();
     // compaction of the occupied slots to the front of the table
     int kr[SPT];
-    V vr[SPT];
+    double vr[SPT];
     int cnt = 0;
 #pragma unroll
     for (int s = 0; s < SPT; ++s) {
@@ -633,7 +696,7 @@ __global__ __launch_bounds__(kWave *WPR *RPW) void k_num_rows(
     const int n2 = total <= 1 ? 1 : (1 << ceil_log2(total));
     for (int t = total + gt; t < n2; t += G) keys[t] = 0x7fffffff;
     group_sync<WPR>();
-    group_bitonic<V, WPR>(keys, vals, n2, gt);
+    group_bitonic<double, WPR>(keys, vals, n2, gt);
     if (active) {
         const long long rb = Crp[row];
         const int nc = (int)(Crp[row + 1] - rb);
@@ -641,7 +704,7 @@ __global__ __launch_bounds__(kWave *WPR *RPW) void k_num_rows(
         const int nw = total < nc ? total : nc;
         for (int t = gt; t < nw; t += G) {
             Ccol[rb + t] = keys[t];
-            Cval[rb + t] = vals[t];
+            Cval[rb + t] = (V)vals[t];
         }
     }
 }
@@ -746,13 +809,10 @@ __global__ __launch_bounds__(256) void k_bsplit(int brows, int nchunks, const in
 }
 
 // Symbolic phase of heavy rows: block (h, w) marks the columns of heavy row h
-// that fall in symbolic window w (kSymWinChunks chunks) in an LDS bitmap and
+// that fall in symbolic window w (kSymWinChunks chunks) in an LDS bitmap, then
 // stores the number of columns of every chunk (wcnt) and adds them to the
-// row's count.  Each thread walks R consecutive products and ORs their bits
-// into a register until the bitmap word changes, so the LDS atomics of a
-// dense B row are merged and the lanes of one instruction hit distinct words.
+// row's count.
 constexpr int kSymHeavyThreads = 256;
-constexpr int kSymRun = 16;
 
 __global__ __launch_bounds__(kSymHeavyThreads) void k_sym_heavy(
     const int *__restrict__ Arp, const int *__restrict__ Acol, const int *__restrict__ Bcol,
@@ -773,56 +833,18 @@ __global__ __launch_bounds__(kSymHeavyThreads) void k_sym_heavy(
     const long long per = nchunks + 1;
     for (int t = gt; t < WORDS; t += G) bm[t] = 0u;
     __syncthreads();
-    const int e0 = Arp[row], e1 = Arp[row + 1];
-    for (int base = e0; base < e1; base += G) {
-        const int e = base + gt;
-        int bs = 0, bl = 0;
-        if (e < e1) {
+    group_products<float, false, G, 4>(
+        Arp[row], Arp[row + 1], gt, S, Bcol, (const float *)nullptr,
+        [&](int e, int &bs, int &bl, float &) {
             const long long k = Acol[e];
             bs = Bsplit[k * per + c0];
             bl = Bsplit[k * per + c1] - bs;
-        }
-        int incl = wave_incl_scan(bl);
-        if (lane == kWave - 1) S.wsum[wg] = incl;
-        __syncthreads();
-        int add = 0;
-        for (int v = 0; v < wg; ++v) add += S.wsum[v];
-        incl += add;
-        S.incl[gt] = incl;
-        S.bs[gt] = bs;
-        __syncthreads();
-        const int total = S.incl[G - 1];
-        for (int q0 = gt * kSymRun; q0 < total; q0 += G * kSymRun) {
-            const int q1 = q0 + kSymRun < total ? q0 + kSymRun : total;
-            int src = 0;
-#pragma unroll
-            for (int step = G / 2; step > 0; step >>= 1)
-                if (S.incl[src + step - 1] <= q0) src += step;
-            int excl = src ? S.incl[src - 1] : 0;
-            int end = S.incl[src];
-            int pos = S.bs[src] + (q0 - excl);
-            int cur = -1;
-            unsigned bits = 0u;
-            for (int q = q0; q < q1; ++q) {
-                while (q >= end) {              // next A entry with a non-empty range
-                    ++src;
-                    excl = end;
-                    end = S.incl[src];
-                    pos = S.bs[src];
-                }
-                const int jl = Bcol[pos++] - lo;
-                const int wd = jl >> 5;
-                if (wd != cur) {
-                    if (cur >= 0) atomicOr(&bm[cur], bits);
-                    cur = wd;
-                    bits = 0u;
-                }
-                bits |= 1u << (jl & 31);
-            }
-            if (cur >= 0) atomicOr(&bm[cur], bits);
-        }
-        __syncthreads();
-    }
+        },
+        [&](int j) {
+            const int jl = j - lo;
+            atomicOr(&bm[jl >> 5], 1u << (jl & 31));
+        });
+    __syncthreads();
     // per-chunk counts: one wave per chunk
     int local = 0;
     for (int c = wg; c < c1 - c0; c += WG) {
@@ -883,6 +905,8 @@ __device__ __forceinline__ void plan_row_segments(const int *__restrict__ wc, in
 }
 
 __global__ __launch_bounds__(256) void k_seg_plan(int pass, int nheavy, int nchunks, const int *__restrict__ wcnt,
+                                                  const int *__restrict__ woff, const int *__restrict__ heavy_rows,
+                                                  const int *__restrict__ Arp, const long long *__restrict__ Crp,
                                                   int *__restrict__ bcount, SegHdr *sh, Seg *__restrict__ segs)
 {
     __shared__ int s_cnt[kSegBins];
@@ -908,10 +932,14 @@ __global__ __launch_bounds__(256) void k_seg_plan(int pass, int nheavy, int nchu
                 if (lnnz[b]) atomicAdd(&s_nnz[b], (unsigned long long)lnnz[b]);
             }
         } else {
+            const int row = heavy_rows[h];
+            const int e0 = Arp[row], e1 = Arp[row + 1];
+            const long long rb = Crp[row];
+            const int *wo = woff + (long long)h * nchunks;
             plan_row_segments(wc, nchunks, [&](int a, int b, int n, bool dense) {
                 const int bin = seg_bin(n, dense);
                 const int pos = sh->offset[bin] + bcount[blockIdx.x * kSegBins + bin] + atomicAdd(&s_cnt[bin], 1);
-                segs[pos] = Seg{h, a, b, n};
+                segs[pos] = Seg{row, e0, e1, a, b, n, rb + wo[a]};
             });
         }
     }
@@ -968,35 +996,34 @@ __global__ __launch_bounds__(THREADS) void k_num_seg(
     constexpr int SPT = T / THREADS;
     static_assert(SPT >= 1, "table smaller than the block");
     __shared__ int keys[T];
-    __shared__ V vals[T];
+    __shared__ double vals[T];
     __shared__ unsigned bm[kSegWords];
     __shared__ int pref[kSegWords / kSegPrefGroup];
     __shared__ EnumScratch<V, THREADS> S;
     __shared__ int s_tmp[THREADS / kWave + 1];
     const Seg sg = segs[blockIdx.x];
-    const int row = heavy_rows[sg.h];
     const int gt = threadIdx.x;
     const int lo = sg.c0 * kChunkCols;
     const int words = (sg.c1 - sg.c0) * kChunkWords;
     const long long per = nchunks + 1;
     for (int t = gt; t < T; t += THREADS) {
         keys[t] = kEmpty;
-        vals[t] = V(0);
+        vals[t] = 0.0;
     }
     for (int t = gt; t < words; t += THREADS) bm[t] = 0u;
     __syncthreads();
-    group_products<V, true, THREADS, 2>(
-        Arp[row], Arp[row + 1], gt, S, Bcol, Bval,
+    group_products<V, true, THREADS, 4>(
+        sg.e0, sg.e1, gt, S, Bcol, Bval,
         [&](int e, int &bs, int &bl, V &a) {
             const long long k = Acol[e];
             bs = Bsplit[k * per + sg.c0];
             bl = Bsplit[k * per + sg.c1] - bs;
             a = Aval[e];
         },
-        [&](int j, V p) { lds_insert_add(keys, vals, LOGT, j, p, err); });
+        [&](int j, double p) { lds_insert_add(keys, vals, LOGT, j, p, err); });
     __syncthreads();
     int kr[SPT];
-    V vr[SPT];
+    double vr[SPT];
 #pragma unroll
     for (int s = 0; s < SPT; ++s) {
         kr[s] = keys[s * THREADS + gt];
@@ -1037,18 +1064,19 @@ __global__ __launch_bounds__(THREADS) void k_num_seg(
         }
     }
     __syncthreads();
-    const long long out0 = Crp[row] + woff[(long long)sg.h * nchunks + sg.c0];
+    const long long out0 = sg.out;
     const int n = tot_all < sg.count ? tot_all : sg.count;
     for (int t = gt; t < n; t += THREADS) {
         Ccol[out0 + t] = keys[t];
-        Cval[out0 + t] = vals[t];
+        Cval[out0 + t] = (V)vals[t];
     }
 }
 
 // Dense chunk of a heavy row: products whose columns lie in chunk c0 added
-// directly into an LDS array indexed by column, with a per-column flag; the
-// flagged columns are compacted in column order in LDS and copied out with
-// coalesced stores.
+// directly into an LDS array of doubles indexed by column, with an occupancy
+// bitmap; each wave then ranks its own 512 columns with ballots and writes its
+// entries straight to C in column order (consecutive lanes, consecutive
+// addresses).
 constexpr int kDenseThreads = 512;
 
 template <typename V>
@@ -1059,65 +1087,66 @@ __global__ __launch_bounds__(kDenseThreads) void k_num_dense(
     const int *__restrict__ woff, const long long *__restrict__ Crp, int *__restrict__ Ccol,
     V *__restrict__ Cval, int *err)
 {
-    constexpr int CPT = kChunkCols / kDenseThreads;   // columns per thread in the compaction
+    constexpr int NW = kDenseThreads / kWave;
+    constexpr int CPW = kChunkCols / NW;              // columns ranked by each wave
+    constexpr int ROUNDS = CPW / kWave;
     extern __shared__ unsigned char s_raw[];
-    V *acc = (V *)s_raw;                                // [kChunkCols]
-    int *flag = (int *)(acc + kChunkCols);              // [kChunkCols]
+    double *acc = (double *)s_raw;                      // [kChunkCols]
+    __shared__ unsigned bm[kChunkWords];
     __shared__ EnumScratch<V, kDenseThreads> S;
-    __shared__ int s_tmp[kDenseThreads / kWave + 1];
+    __shared__ int s_wt[NW];
     const Seg sg = segs[blockIdx.x];
-    const int row = heavy_rows[sg.h];
-    const int gt = threadIdx.x;
+    const int gt = threadIdx.x, lane = lane_id(), wg = gt / kWave;
     const int lo = sg.c0 * kChunkCols;
     const long long per = nchunks + 1;
-    for (int t = gt; t < kChunkCols; t += kDenseThreads) {
-        acc[t] = V(0);
-        flag[t] = 0;
-    }
+    for (int t = gt; t < kChunkCols; t += kDenseThreads) acc[t] = 0.0;
+    for (int t = gt; t < kChunkWords; t += kDenseThreads) bm[t] = 0u;
     __syncthreads();
-    group_products<V, true, kDenseThreads, 2>(
-        Arp[row], Arp[row + 1], gt, S, Bcol, Bval,
+    group_products<V, true, kDenseThreads, 4>(
+        sg.e0, sg.e1, gt, S, Bcol, Bval,
         [&](int e, int &bs, int &bl, V &a) {
             const long long k = Acol[e];
             bs = Bsplit[k * per + sg.c0];
             bl = Bsplit[k * per + sg.c0 + 1] - bs;
             a = Aval[e];
         },
-        [&](int j, V p) {
+        [&](int j, double p) {
             const int jl = j - lo;
             atomicAdd(&acc[jl], p);
-            flag[jl] = 1;
+            atomicOr(&bm[jl >> 5], 1u << (jl & 31));
         });
     __syncthreads();
-    V vr[CPT];
-    int cnt = 0;
-    unsigned present = 0u;
+    double vr[ROUNDS];
+    unsigned long long msk[ROUNDS];
+    int wcount = 0;
 #pragma unroll
-    for (int q = 0; q < CPT; ++q) {
-        const int jl = gt * CPT + q;
-        vr[q] = acc[jl];
-        if (flag[jl]) {
-            present |= 1u << q;
-            ++cnt;
-        }
+    for (int r = 0; r < ROUNDS; ++r) {
+        const int jl = wg * CPW + r * kWave + lane;
+        vr[r] = acc[jl];
+        msk[r] = __ballot((bm[jl >> 5] >> (jl & 31)) & 1u);
+        wcount += __popcll(msk[r]);
     }
-    int tot;
-    int pos = block_excl_scan<int, kDenseThreads>(cnt, s_tmp, tot);
-    if (gt == 0 && tot != sg.count) atomicOr(err, kErrCount);
-#pragma unroll
-    for (int q = 0; q < CPT; ++q) {
-        if (present & (1u << q)) {
-            flag[pos] = lo + gt * CPT + q;
-            acc[pos] = vr[q];
-            ++pos;
-        }
-    }
+    if (lane == 0) s_wt[wg] = wcount;
     __syncthreads();
-    const long long out0 = Crp[row] + woff[(long long)sg.h * nchunks + sg.c0];
-    const int n = tot < sg.count ? tot : sg.count;
-    for (int t = gt; t < n; t += kDenseThreads) {
-        Ccol[out0 + t] = flag[t];
-        Cval[out0 + t] = acc[t];
+    int run = 0, tot = 0;
+    for (int w = 0; w < NW; ++w) {
+        const int t = s_wt[w];
+        if (w < wg) run += t;
+        tot += t;
+    }
+    if (gt == 0 && tot != sg.count) atomicOr(err, kErrCount);
+    const long long out0 = sg.out;
+    const unsigned long long below = (1ull << lane) - 1ull;
+#pragma unroll
+    for (int r = 0; r < ROUNDS; ++r) {
+        if ((msk[r] >> lane) & 1ull) {
+            const int p = run + __popcll(msk[r] & below);
+            if (p < sg.count) {
+                Ccol[out0 + p] = lo + wg * CPW + r * kWave + lane;
+                Cval[out0 + p] = (V)vr[r];
+            }
+        }
+        run += __popcll(msk[r]);
     }
 }
 
@@ -1228,7 +1257,8 @@ __global__ __launch_bounds__(kGlobalThreads) void k_num_global(
             bl = Brp[k + 1] - bs;
             a = Aval[e];
         },
-        [&](int j, V p) {
+        [&](int j, double pd) {
+            const V p = (V)pd;
             unsigned hh = slot_of(j, logT);
             for (unsigned probe = 0; probe <= mask; ++probe) {
                 int cur = gload(&keys[hh]);
