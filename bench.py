@@ -45,7 +45,25 @@ def parse():
     ap.add_argument("--heavy-mode", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle time for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (counter calibration)")
     return ap.parse_args()
+
+
+def copy_calibration(mib: int, reps: int = 3):
+    """A plain copy of known size, for scaling the FETCH_SIZE / WRITE_SIZE
+    counters: each launch reads and writes mib MiB."""
+    import torch
+    n = mib << 20
+    x = torch.ones(n, dtype=torch.uint8, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    print(json.dumps({"copy_bytes_per_launch": n, "launches": reps, "gbs": round(2 * n / dt / 1e9, 1)}), flush=True)
 
 
 def log(msg):
@@ -81,6 +99,9 @@ def cpu_baseline(A, B, target_s):
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
               f"(the multi-GPU row sharding is described in DESIGN.md, not built)", file=sys.stderr)

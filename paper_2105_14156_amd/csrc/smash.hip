@@ -591,15 +591,15 @@ smash_status smash_spgemm_symbolic(smash_ctx c, const smash_csr *A, const smash_
     if (H > 0 && !global) {
         const long long kdim = p.B.rows;
         const size_t cells = (size_t)H * p.nchunks;
-        const int nhb = (int)blocks_for(H, 256);
         const size_t need = carve_size({(size_t)(kdim * (p.nchunks + 1)) * sizeof(int), cells * sizeof(int),
-                                        cells * sizeof(int), (size_t)nhb * kSegBins * sizeof(int), cells * sizeof(Seg)});
+                                        cells * sizeof(int), (size_t)kSegBins * p.nchunks * sizeof(int),
+                                        cells * sizeof(Seg)});
         TRY(ensure(c, c->heavy_mem, need, s));
         Carve cv{(char *)c->heavy_mem.ptr};
         p.bsplit = cv.take<int>((size_t)(kdim * (p.nchunks + 1)));
         p.wcnt = cv.take<int>(cells);
         p.woff = cv.take<int>(cells);
-        p.seg_bcount = cv.take<int>((size_t)nhb * kSegBins);
+        p.seg_bcount = cv.take<int>((size_t)kSegBins * p.nchunks);
         p.segs = cv.take<Seg>(cells);
         TRY(launch(c, K_BSPLIT, s, [&] {
             k_bsplit<<<blocks_for(kdim * (p.nchunks + 1), 256), 256, 0, s>>>((int)kdim, p.nchunks, B->row_ptr,
@@ -608,7 +608,7 @@ smash_status smash_spgemm_symbolic(smash_ctx c, const smash_csr *A, const smash_
         const int nwin = (p.nchunks + kSymWinChunks - 1) / kSymWinChunks;
         TRY(launch(c, K_SYM_HEAVY, s, [&] {
             k_sym_heavy<<<(unsigned)((long long)H * nwin), kSymHeavyThreads, 0, s>>>(
-                A->row_ptr, A->col_idx, B->col_idx, p.bsplit, heavy_rows, nwin, p.nchunks, p.wcnt, p.nnzc);
+                A->row_ptr, A->col_idx, B->col_idx, p.bsplit, heavy_rows, H, p.nchunks, p.wcnt, p.nnzc);
         }));
     } else if (H > 0) {
         TRY(read_hdr(c, s));
@@ -635,11 +635,15 @@ smash_status smash_spgemm_symbolic(smash_ctx c, const smash_csr *A, const smash_
         TRY(launch(c, K_CHUNK_PREFIX, s, [&] {
             k_chunk_prefix<<<nhb, 256, 0, s>>>(H, p.nchunks, p.wcnt, p.woff);
         }));
+        TRY(launch(c, K_FILL, s, [&] {
+            k_fill_i32<<<blocks_for(kSegBins * p.nchunks, 256), 256, 0, s>>>((long long)kSegBins * p.nchunks,
+                                                                           p.seg_bcount, 0);
+        }));
         TRY(launch(c, K_SEG_PLAN, s, [&] {
             k_seg_plan<<<nhb, 256, 0, s>>>(0, H, p.nchunks, p.wcnt, p.woff, heavy_rows, A->row_ptr,
                                            (const long long *)C_row_ptr, p.seg_bcount, &c->d_hdr->seg, p.segs);
         }));
-        TRY(launch(c, K_SEG_SCAN, s, [&] { k_seg_scan<<<1, kWave, 0, s>>>(nhb, p.seg_bcount, &c->d_hdr->seg); }));
+        TRY(launch(c, K_SEG_SCAN, s, [&] { k_seg_scan<<<1, kWave, 0, s>>>(p.nchunks, p.seg_bcount, &c->d_hdr->seg); }));
         TRY(launch(c, K_SEG_PLAN, s, [&] {
             k_seg_plan<<<nhb, 256, 0, s>>>(1, H, p.nchunks, p.wcnt, p.woff, heavy_rows, A->row_ptr,
                                            (const long long *)C_row_ptr, p.seg_bcount, &c->d_hdr->seg, p.segs);

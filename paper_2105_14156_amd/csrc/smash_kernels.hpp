@@ -138,6 +138,15 @@ __device__ __forceinline__ int ceil_log2(long long x)
     return x <= 1 ? 0 : 64 - __clzll((unsigned long long)(x - 1));
 }
 
+// Output stores of C bypass cache retention: C is written once and never
+// read back by the product, and keeping it out of L2 and the MALL leaves
+// room for B and the split table, which every row re-reads.
+template <typename T>
+__device__ __forceinline__ void store_c(T *p, T v)
+{
+    __builtin_nontemporal_store(v, p);
+}
+
 // Fibonacci hashing of a column index onto 2^logT slots.
 __device__ __forceinline__ unsigned slot_of(int key, int logT)
 {
@@ -703,8 +712,8 @@ __global__ __launch_bounds__(kWave *WPR *RPW) void k_num_rows(
         if (gt == 0 && nc != total) atomicOr(err, kErrCount);
         const int nw = total < nc ? total : nc;
         for (int t = gt; t < nw; t += G) {
-            Ccol[rb + t] = keys[t];
-            Cval[rb + t] = (V)vals[t];
+            store_c(&Ccol[rb + t], keys[t]);
+            store_c(&Cval[rb + t], (V)vals[t]);
         }
     }
 }
@@ -808,7 +817,7 @@ __global__ __launch_bounds__(256) void k_bsplit(int brows, int nchunks, const in
     Bsplit[t] = pos;
 }
 
-// Symbolic phase of heavy rows: block (h, w) marks the columns of heavy row h
+// Symbolic phase of heavy rows: block (w, h) marks the columns of heavy row h
 // that fall in symbolic window w (kSymWinChunks chunks) in an LDS bitmap, then
 // stores the number of columns of every chunk (wcnt) and adds them to the
 // row's count.
@@ -816,7 +825,7 @@ constexpr int kSymHeavyThreads = 256;
 
 __global__ __launch_bounds__(kSymHeavyThreads) void k_sym_heavy(
     const int *__restrict__ Arp, const int *__restrict__ Acol, const int *__restrict__ Bcol,
-    const int *__restrict__ Bsplit, const int *__restrict__ rows, int nwin, int nchunks,
+    const int *__restrict__ Bsplit, const int *__restrict__ rows, int nheavy, int nchunks,
     int *__restrict__ wcnt, int *__restrict__ nnzc)
 {
     constexpr int G = kSymHeavyThreads;
@@ -824,7 +833,8 @@ __global__ __launch_bounds__(kSymHeavyThreads) void k_sym_heavy(
     constexpr int WORDS = kSymWinChunks * kChunkWords;
     __shared__ unsigned bm[WORDS];
     __shared__ EnumScratch<float, G> S;
-    const int h = blockIdx.x / nwin, w = blockIdx.x % nwin;
+    // window-major: blocks launched together share one column window of B
+    const int w = blockIdx.x / nheavy, h = blockIdx.x % nheavy;
     const int row = rows[h];
     const int gt = threadIdx.x, lane = lane_id(), wg = gt / kWave;
     const int c0 = w * kSymWinChunks;
@@ -904,77 +914,95 @@ __device__ __forceinline__ void plan_row_segments(const int *__restrict__ wc, in
     }
 }
 
+// Segments are laid out bin by bin and, within a bin, chunk by chunk (by
+// their first chunk): blocks launched together then work on the same column
+// slice of B, which stays in L2.  Pass 0 counts segments per (bin, chunk) in
+// hist; k_seg_scan turns the counts into offsets (and cursors); pass 1 writes
+// every segment at its (bin, chunk) cursor.  Blocks aggregate their counts
+// in LDS (one global atomic per block and group) when the kSegBins x nchunks
+// histogram fits kSegPlanLds entries.
+constexpr int kSegPlanLds = 4096;
+
 __global__ __launch_bounds__(256) void k_seg_plan(int pass, int nheavy, int nchunks, const int *__restrict__ wcnt,
                                                   const int *__restrict__ woff, const int *__restrict__ heavy_rows,
                                                   const int *__restrict__ Arp, const long long *__restrict__ Crp,
-                                                  int *__restrict__ bcount, SegHdr *sh, Seg *__restrict__ segs)
+                                                  int *__restrict__ hist, SegHdr *sh, Seg *__restrict__ segs)
 {
-    __shared__ int s_cnt[kSegBins];
     __shared__ unsigned long long s_nnz[kSegBins];
-    if (threadIdx.x < kSegBins) {
-        s_cnt[threadIdx.x] = 0;
-        s_nnz[threadIdx.x] = 0;
-    }
+    __shared__ int s_cnt[kSegPlanLds];
+    const int cells = kSegBins * nchunks;
+    const bool local = cells <= kSegPlanLds;
+    if (threadIdx.x < kSegBins) s_nnz[threadIdx.x] = 0;
+    if (local)
+        for (int t = threadIdx.x; t < cells; t += 256) s_cnt[t] = 0;
     __syncthreads();
     const int h = blockIdx.x * blockDim.x + threadIdx.x;
+    const int *wc = wcnt + (long long)h * nchunks;
+    // count this block's segments per (bin, chunk)
     if (h < nheavy) {
-        const int *wc = wcnt + (long long)h * nchunks;
-        if (pass == 0) {
-            int local[kSegBins] = {0, 0, 0, 0};
-            long long lnnz[kSegBins] = {0, 0, 0, 0};
-            plan_row_segments(wc, nchunks, [&](int, int, int n, bool dense) {
-                const int b = seg_bin(n, dense);
-                ++local[b];
+        long long lnnz[kSegBins] = {0, 0, 0, 0};
+        plan_row_segments(wc, nchunks, [&](int a, int, int n, bool dense) {
+            const int b = seg_bin(n, dense);
+            if (pass == 0) {
+                if (local) atomicAdd(&s_cnt[b * nchunks + a], 1);
+                else atomicAdd(&hist[(long long)b * nchunks + a], 1);
                 lnnz[b] += n;
-            });
-            for (int b = 0; b < kSegBins; ++b) {
-                if (local[b]) atomicAdd(&s_cnt[b], local[b]);
-                if (lnnz[b]) atomicAdd(&s_nnz[b], (unsigned long long)lnnz[b]);
+            } else if (local) {
+                atomicAdd(&s_cnt[b * nchunks + a], 1);
             }
-        } else {
-            const int row = heavy_rows[h];
-            const int e0 = Arp[row], e1 = Arp[row + 1];
-            const long long rb = Crp[row];
-            const int *wo = woff + (long long)h * nchunks;
-            plan_row_segments(wc, nchunks, [&](int a, int b, int n, bool dense) {
-                const int bin = seg_bin(n, dense);
-                const int pos = sh->offset[bin] + bcount[blockIdx.x * kSegBins + bin] + atomicAdd(&s_cnt[bin], 1);
-                segs[pos] = Seg{row, e0, e1, a, b, n, rb + wo[a]};
-            });
-        }
+        });
+        if (pass == 0)
+            for (int b = 0; b < kSegBins; ++b)
+                if (lnnz[b]) atomicAdd(&s_nnz[b], (unsigned long long)lnnz[b]);
     }
     __syncthreads();
-    if (pass == 0 && threadIdx.x < kSegBins) {
-        bcount[blockIdx.x * kSegBins + threadIdx.x] = s_cnt[threadIdx.x];
-        if (s_nnz[threadIdx.x]) atomicAdd((unsigned long long *)&sh->nnz[threadIdx.x], s_nnz[threadIdx.x]);
+    if (pass == 0) {
+        if (local)
+            for (int t = threadIdx.x; t < cells; t += 256)
+                if (s_cnt[t]) atomicAdd(&hist[t], s_cnt[t]);
+        if (threadIdx.x < kSegBins && s_nnz[threadIdx.x])
+            atomicAdd((unsigned long long *)&sh->nnz[threadIdx.x], s_nnz[threadIdx.x]);
+        return;
+    }
+    // pass 1: reserve this block's range of every group, then place
+    if (local)
+        for (int t = threadIdx.x; t < cells; t += 256)
+            s_cnt[t] = s_cnt[t] ? atomicAdd(&hist[t], s_cnt[t]) : 0;
+    __syncthreads();
+    if (h < nheavy) {
+        const int row = heavy_rows[h];
+        const int e0 = Arp[row], e1 = Arp[row + 1];
+        const long long rb = Crp[row];
+        const int *wo = woff + (long long)h * nchunks;
+        plan_row_segments(wc, nchunks, [&](int a, int b, int n, bool dense) {
+            const int bin = seg_bin(n, dense);
+            const int cell = bin * nchunks + a;
+            const int pos = local ? atomicAdd(&s_cnt[cell], 1) : atomicAdd(&hist[cell], 1);
+            segs[pos] = Seg{row, e0, e1, a, b, n, rb + wo[a]};
+        });
     }
 }
 
-// Segment bin totals, offsets and per-block bases (one block).
-__global__ __launch_bounds__(kWave) void k_seg_scan(int nblk, int *__restrict__ bcount, SegHdr *sh)
+// Offsets of the segment bins and of every (bin, chunk) group; hist becomes
+// the write cursor of each group (one wave).
+__global__ __launch_bounds__(kWave) void k_seg_scan(int nchunks, int *__restrict__ hist, SegHdr *sh)
 {
     const int lane = lane_id();
-    int tot[kSegBins];
+    int run = 0;
     for (int b = 0; b < kSegBins; ++b) {
-        int run = 0;
-        for (int c0 = 0; c0 < nblk; c0 += kWave) {
+        if (lane == 0) sh->offset[b] = run;
+        const int start = run;
+        for (int c0 = 0; c0 < nchunks; c0 += kWave) {
             const int c = c0 + lane;
-            const int v = c < nblk ? bcount[c * kSegBins + b] : 0;
+            const long long at = (long long)b * nchunks + c;
+            const int v = c < nchunks ? hist[at] : 0;
             const int incl = wave_incl_scan(v);
-            if (c < nblk) bcount[c * kSegBins + b] = run + incl - v;
+            if (c < nchunks) hist[at] = run + incl - v;
             run += __shfl(incl, kWave - 1, kWave);
         }
-        tot[b] = run;
+        if (lane == 0) sh->count[b] = run - start;
     }
-    if (lane == 0) {
-        int run = 0;
-        for (int b = 0; b < kSegBins; ++b) {
-            sh->count[b] = tot[b];
-            sh->offset[b] = run;
-            run += tot[b];
-        }
-        sh->offset[kSegBins] = run;
-    }
+    if (lane == 0) sh->offset[kSegBins] = run;
 }
 
 // Hashed segment of a heavy row: products of the row whose columns lie in
@@ -1067,8 +1095,8 @@ __global__ __launch_bounds__(THREADS) void k_num_seg(
     const long long out0 = sg.out;
     const int n = tot_all < sg.count ? tot_all : sg.count;
     for (int t = gt; t < n; t += THREADS) {
-        Ccol[out0 + t] = keys[t];
-        Cval[out0 + t] = (V)vals[t];
+        store_c(&Ccol[out0 + t], keys[t]);
+        store_c(&Cval[out0 + t], (V)vals[t]);
     }
 }
 
@@ -1142,8 +1170,8 @@ __global__ __launch_bounds__(kDenseThreads) void k_num_dense(
         if ((msk[r] >> lane) & 1ull) {
             const int p = run + __popcll(msk[r] & below);
             if (p < sg.count) {
-                Ccol[out0 + p] = lo + wg * CPW + r * kWave + lane;
-                Cval[out0 + p] = (V)vr[r];
+                store_c(&Ccol[out0 + p], lo + wg * CPW + r * kWave + lane);
+                store_c(&Cval[out0 + p], (V)vr[r]);
             }
         }
         run += __popcll(msk[r]);
@@ -1301,8 +1329,8 @@ __global__ __launch_bounds__(kGlobalThreads) void k_num_global(
             rank += __popc(s_bm[wd] & ((1u << (jl & 31)) - 1u));
             const long long pos = done + rank;
             if (pos < nc) {
-                Ccol[rb + pos] = j;
-                Cval[rb + pos] = gload_v(&vals[t]);
+                store_c(&Ccol[rb + pos], j);
+                store_c(&Cval[rb + pos], gload_v(&vals[t]));
             }
         }
         done += tot;

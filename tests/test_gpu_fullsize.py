@@ -1,0 +1,100 @@
+"""Full-size GPU parity for RMAT scale 19, edge factor 16, C = A.A in FP32: the
+benchmark's workload, in the benchmark's launch configuration.
+
+The whole C does not fit the oracle's time budget, so it is checked
+- structurally everywhere: every row's count against the oracle's exact
+  per-row count (hence all of C_row_ptr);
+- entry by entry on sampled rows (the 16 rows with most products, rows from
+  every row class, and seeded random rows) against the oracle;
+- globally by Freivalds' check with plain torch ops in float64:
+  |(C x)_i - (A (B x))_i| <= 1e-5 (|A| (|B| |x|))_i, a bound that follows from
+  the per-entry tolerance |c_ij - c*_ij| <= 1e-5 sum_k |a_ik b_kj|.
+"""
+import numpy as np
+import pytest
+
+import synthetic as syn
+from tests._parity import check_rows
+
+pytestmark = pytest.mark.gpu
+
+
+def _spmv(torch, rp, col, val, x, m, absolute=False, chunk=1 << 27):
+    """y = M x for CSR M on the GPU (float64), over blocks of whole rows of
+    at most about `chunk` entries, with torch's gather and segment_reduce
+    (no atomics)."""
+    rp_h = rp.cpu().numpy()
+    y = torch.zeros(m, dtype=torch.float64, device=x.device)
+    r0 = 0
+    while r0 < m:
+        r1 = int(np.searchsorted(rp_h, rp_h[r0] + chunk, side="right")) - 1
+        r1 = min(max(r1, r0 + 1), m)
+        s, e = int(rp_h[r0]), int(rp_h[r1])
+        v = val[s:e].double()
+        if absolute:
+            v = v.abs()
+        prod = v * x[col[s:e].long()]
+        y[r0:r1] = torch.segment_reduce(prod, "sum", offsets=rp[r0:r1 + 1] - s)
+        r0 = r1
+    return y
+
+
+@pytest.mark.timeout(900)
+def test_rmat_s19_full_size(oracle_mod):
+    import torch
+    from paper_2105_14156_amd import smash
+    assert torch.cuda.is_available()
+    A = syn.workload_s19(np.float32).A
+    print(f"s19: A {A.rows}x{A.cols} nnz {A.nnz}", flush=True)
+    ctx = smash.Context(0)
+    dA = smash.to_device(A)
+    C = ctx.spgemm(dA, dA)
+    torch.cuda.synchronize()
+    st = ctx.stats()
+    print("gpu done", st, flush=True)
+    assert st["rows_heavy"] > 0 and st["heavy_dense_chunks"] > 0 and st["heavy_segments"] > 0
+
+    # 1. every row's count
+    rp = C.row_ptr.cpu().numpy()
+    assert rp[0] == 0
+    nz = oracle_mod.row_nnz(A, A)
+    assert np.array_equal(np.diff(rp), nz), "row counts differ from the oracle"
+    print("row counts ok", flush=True)
+
+    # 2. sampled rows, entry by entry
+    ub = oracle_mod.products_per_row(A, A)
+    top = np.argsort(-ub, kind="stable")[:16]
+    r = syn.uniform01(0x519, 0, 4000)
+    rand = (r * A.rows).astype(np.int64)
+    by_class = []
+    for lo, hi in [(1, 32), (33, 512), (513, 1024), (1025, 8192), (8193, 65536), (65537, 1 << 40)]:
+        cls = np.nonzero((ub >= lo) & (ub <= hi))[0]
+        if cls.size:
+            by_class.append(cls[(syn.uniform01(lo, 0, 50) * cls.size).astype(np.int64)])
+    sel = np.unique(np.concatenate([top, rand] + by_class))
+    ref = oracle_mod.spgemm(A, A, rows=sel)
+    starts = rp[sel]
+    lens = rp[sel + 1] - starts
+    idx = np.repeat(starts - np.concatenate([[0], np.cumsum(lens)[:-1]]), lens) + np.arange(lens.sum())
+    tidx = torch.from_numpy(idx).cuda()
+    col = C.col_idx.index_select(0, tidx).cpu().numpy()
+    val = C.val.index_select(0, tidx).cpu().numpy()
+    srp = np.concatenate([[0], np.cumsum(lens)])
+    margin = check_rows(srp, col, val, ref, np.float32, "s19 sampled rows")
+    print(f"{sel.size} sampled rows ok ({lens.sum()} entries, max err/absmass {margin:.2e})", flush=True)
+
+    # 3. Freivalds on the whole product
+    crp = C.row_ptr
+    arp = dA.row_ptr.long()
+    for s in range(3):
+        x = torch.from_numpy(2 * syn.uniform01(0xF4E1 + s, 0, A.cols) - 1).cuda()
+        cx = _spmv(torch, crp, C.col_idx, C.val, x, A.rows)
+        bx = _spmv(torch, arp, dA.col_idx, dA.val, x, A.rows)
+        abx = _spmv(torch, arp, dA.col_idx, dA.val, bx, A.rows)
+        bnd_b = _spmv(torch, arp, dA.col_idx, dA.val, x.abs(), A.rows, absolute=True)
+        bnd = _spmv(torch, arp, dA.col_idx, dA.val, bnd_b, A.rows, absolute=True)
+        err = (cx - abx).abs()
+        ok = err <= 1e-5 * bnd + 1e-9 * bnd
+        assert bool(ok.all()), f"Freivalds check failed on {int((~ok).sum())} rows"
+        print(f"Freivalds {s} ok: max err/bound {float((err / bnd.clamp_min(1e-300)).max()):.2e}", flush=True)
+    ctx.close()
