@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--workload", default="s19", choices=sorted(WORKLOADS))
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--heavy-mode", type=int, default=0)
+    ap.add_argument("--path", default="plain", choices=["plain", "fused"],
+                    help="plain: symbolic + numeric; fused: learned-capacity single pass for LDS rows")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle time for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -123,11 +125,16 @@ def main():
     ctx = smash.Context(0)
     ctx.set_option(smash.OPT_HEAVY_MODE, args.heavy_mode)
     stream = torch.cuda.current_stream()
+    if args.path == "fused":
+        ctx.predictor_load()
+        run = lambda: ctx.spgemm_fused(dA, dB, stream)
+    else:
+        run = lambda: ctx.spgemm(dA, dB, stream)
 
     C = None
     for i in range(args.warmup):
         C = None
-        C = ctx.spgemm(dA, dB, stream)
+        C = run()
         log(f"warmup {i + 1}/{args.warmup} done")
     torch.cuda.synchronize()
     st = ctx.stats()
@@ -139,7 +146,7 @@ def main():
     t0 = time.perf_counter()
     for i in range(args.steps):
         C = None
-        C = ctx.spgemm(dA, dB, stream)
+        C = run()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     log(f"timed {args.steps} steps in {elapsed:.3f} s")
@@ -178,7 +185,8 @@ def main():
         "vs_baseline": None,
         "dtype": args.dtype,
         "data": "synthetic",
-        "config": {"workload": name, "description": desc, "path": "plain two-phase (symbolic + numeric)",
+        "config": {"workload": name, "description": desc, "path": "plain two-phase (symbolic + numeric)" if args.path == "plain"
+                   else "fused single pass with learned row capacities",
                    "heavy_mode": "lds_segments" if args.heavy_mode == 0 else "global_hash",
                    "rows": A.rows, "cols": B.cols, "nnz_a": A.nnz, "nnz_b": B.nnz, "nnz_c": nnz_c,
                    "products": products},

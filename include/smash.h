@@ -101,6 +101,8 @@ typedef struct {
     int64_t global_slots;       /* global hash table slots (global mode) */
     int64_t nnz_heavy;          /* entries of C in heavy rows */
     int64_t nnz_dense;          /* entries of C in dense chunks of heavy rows */
+    int64_t fused_rows;         /* rows completed by the fused pass (smash_spgemm_fused) */
+    int64_t fused_overflow;     /* rows the fused pass handed back (prediction too small) */
 } smash_stats;
 
 /* Allocation callback of smash_spgemm: return device memory of at least
@@ -158,6 +160,76 @@ smash_status smash_spgemm(smash_ctx ctx, smash_dtype dtype, const smash_csr *A, 
 
 /* Counters of the last symbolic (and numeric) call on ctx. */
 smash_status smash_get_stats(smash_ctx ctx, smash_stats *out);
+
+/* ------------------------------------------------- learned row-size predictor
+ *
+ * A small MLP (6 -> 64 -> 64 -> 1, ReLU, FP32) maps six per-row features of
+ * C = A * B to log2(1 + nnz(C_i)); the fused pass (smash_spgemm_fused) sizes
+ * its LDS tables from it instead of running a symbolic phase.  Parameters
+ * are packed floats: W1[64][6], b1[64], W2[64][64], b2[64], w3[64], b3
+ * (SMASH_MLP_PARAMS floats).  Features are standardized as (f - mean) / std
+ * with mean_std = {mean[6], std[6]}.  This predictor is the library's
+ * addition; the paper sizes output from per-row product counts (Window
+ * Distribution Phase) and names flop-estimate-based distribution as future
+ * work (Conclusions, Future Work). */
+#define SMASH_MLP_FEATURES 6
+#define SMASH_MLP_PARAMS 4673
+
+/* Features of every row i of C = A * B (device float[A.rows * 6], row-major):
+ * log2(1 + x) of nnz(A_i), ub_i = sum_k nnz(B_k), max_k nnz(B_k),
+ * min_k nnz(B_k), min(ub_i, B.cols) and sum_k nnz(B_k)^2 / ub_i; zeros for
+ * empty rows. */
+smash_status smash_features(smash_ctx ctx, const smash_csr *A, const smash_csr *B, float *feats, hipStream_t stream);
+
+/* yhat[i] = network output for feats[i] (all device pointers; m rows). */
+smash_status smash_mlp_predict(smash_ctx ctx, int64_t m, const float *feats, const float *params,
+                               const float *mean_std, float *yhat, hipStream_t stream);
+
+/* Mean squared error of the network over the n samples feats[idx[s]] with
+ * targets targets[idx[s]], and its gradient with respect to params (device
+ * float[SMASH_MLP_PARAMS]).  *loss is written on the host (synchronizes). */
+smash_status smash_mlp_loss_grad(smash_ctx ctx, const float *feats, const float *targets, const int32_t *idx,
+                                 int64_t n, const float *mean_std, const float *params, float *grad, double *loss,
+                                 hipStream_t stream);
+
+typedef struct {
+    int32_t epochs;   /* passes over the data */
+    int32_t batch;    /* samples per Adam step (the last step of an epoch may be smaller) */
+    float lr, beta1, beta2, eps;   /* Adam hyper-parameters */
+} smash_train_args;
+
+/* Mini-batch Adam training of params (device, in/out) on n samples.  orders
+ * (device int32[epochs * n]) holds one permutation of 0..n-1 per epoch; the
+ * steps of epoch e take consecutive batches of orders[e*n ...].
+ * epoch_loss (host, epochs entries) receives the mean batch loss of every
+ * epoch.  Synchronizes once at the end. */
+smash_status smash_mlp_train(smash_ctx ctx, const float *feats, const float *targets, int64_t n,
+                             const float *mean_std, float *params, const int32_t *orders,
+                             const smash_train_args *args, double *epoch_loss, hipStream_t stream);
+
+/* Installs a predictor in ctx: host params (SMASH_MLP_PARAMS floats), host
+ * mean_std (12 floats) and the capacity margin delta (log2 units): a row's
+ * capacity is clamp(ceil(2^(yhat + delta) - 1), max(max_k nnz(B_k), 1),
+ * min(ub_i, B.cols)). */
+smash_status smash_predictor_set(smash_ctx ctx, const float *params, const float *mean_std, float delta);
+
+/* Fused single pass: C = A * B like smash_spgemm, without a symbolic phase
+ * for the rows the installed predictor sizes into LDS (predicted capacity
+ * <= SMASH_OPT_LDS_ROW_MAX): those rows are hashed, counted, sorted and
+ * staged in one kernel; rows whose columns exceed their capacity, and rows
+ * predicted above the LDS limit, go through the exact two-phase path (a row
+ * is never lost to a bad prediction; only time is).  Staged rows are copied
+ * to their final offsets after the row-pointer scan.  The result is the same
+ * canonical C as smash_spgemm.  Errors: NO_PLAN if no predictor is
+ * installed, and those of smash_spgemm. */
+smash_status smash_spgemm_fused(smash_ctx ctx, smash_dtype dtype, const smash_csr *A, const smash_csr *B,
+                                smash_alloc_fn alloc, void *user, int64_t *C_row_ptr,
+                                int32_t **C_col_idx, void **C_val, int64_t *C_nnz, hipStream_t stream);
+
+/* Loads a predictor file: 8 bytes "SMASHMLP", int32 version (1), int32
+ * SMASH_MLP_PARAMS, float delta, float mean_std[12], float params[...],
+ * little-endian.  Errors: INVALID_ARG (unreadable or malformed file). */
+smash_status smash_predictor_load(smash_ctx ctx, const char *path);
 
 /* Per-kernel timing (SMASH_OPT_TIMING = 1).  For kernel index `index`
  * (0 .. smash_kernel_count()-1) returns its static name, the number of

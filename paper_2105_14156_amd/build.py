@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libsmash.so")
 SOURCES = [os.path.join(HERE, "csrc", "smash.hip")]
-DEPS = SOURCES + [os.path.join(HERE, "csrc", "smash_kernels.hpp"), os.path.join(ROOT, "include", "smash.h")]
+DEPS = SOURCES + [os.path.join(HERE, "csrc", h) for h in ("smash_kernels.hpp", "smash_mlp.hpp", "smash_fused.hpp")] \
+    + [os.path.join(ROOT, "include", "smash.h")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

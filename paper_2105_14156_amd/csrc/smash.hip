@@ -12,6 +12,8 @@
 //             heavy-row kernels -> [read error flags back]
 #include "smash.h"
 #include "smash_kernels.hpp"
+#include "smash_mlp.hpp"
+#include "smash_fused.hpp"
 
 #include <algorithm>
 #include <cstdarg>
@@ -27,13 +29,15 @@ namespace {
 enum KernelId {
     K_VALIDATE, K_ANALYZE, K_BIN_COUNT, K_BIN_SCAN, K_SCATTER, K_SYM_ROWS, K_BSPLIT, K_SYM_HEAVY,
     K_SYM_GLOBAL, K_FILL, K_SCAN_REDUCE, K_SCAN_TOP, K_SCAN_APPLY, K_NUM_BINS, K_CHUNK_PREFIX,
-    K_SEG_PLAN, K_SEG_SCAN, K_NUM_ROWS, K_NUM_SEG, K_NUM_DENSE, K_NUM_GLOBAL, K_COUNT
+    K_SEG_PLAN, K_SEG_SCAN, K_NUM_ROWS, K_NUM_SEG, K_NUM_DENSE, K_NUM_GLOBAL, K_FEATURES, K_MLP_PREDICT,
+    K_MLP_FWD, K_MLP_BWD, K_ADAM, K_FUSED_ROWS, K_FUSED_AUX, K_FUSED_COPY, K_COUNT
 };
 
 const char *const kKernelNames[K_COUNT] = {
     "validate", "analyze", "bin_count", "bin_scan", "scatter", "sym_rows", "bsplit", "sym_heavy",
     "sym_global", "fill", "scan_reduce", "scan_top", "scan_apply", "num_bins", "chunk_prefix",
-    "seg_plan", "seg_scan", "num_rows", "num_seg", "num_dense", "num_global"};
+    "seg_plan", "seg_scan", "num_rows", "num_seg", "num_dense", "num_global", "features", "mlp_predict",
+    "mlp_fwd", "mlp_bwd", "adam", "fused_rows", "fused_aux", "fused_copy"};
 
 // Grow-only device buffer.
 struct Arena {
@@ -78,6 +82,15 @@ struct Plan {
     long long *bsum = nullptr, *gsz = nullptr, *goff_sym = nullptr, *goff_num = nullptr;
     int *bsplit = nullptr, *wcnt = nullptr, *woff = nullptr, *seg_bcount = nullptr;
     Seg *segs = nullptr;
+    // fused pass (rows sized by the predictor)
+    bool fused = false;
+    int fused_dtype = 0;
+    float *feats = nullptr;
+    int *maxb = nullptr, *cap_pred = nullptr, *fcap = nullptr, *f_perm = nullptr;
+    unsigned char *fbin = nullptr, *fstatus = nullptr;
+    long long *stage_off = nullptr;
+    int *stage_col = nullptr;
+    void *stage_val = nullptr;
 };
 
 struct Pending {
@@ -93,7 +106,9 @@ struct smash_ctx_s {
     int64_t opt[5] = {1, 1024, 0, 0, 0};
     DevHdr *h_hdr = nullptr;   // pinned host mirror
     DevHdr *d_hdr = nullptr;
-    Arena plan_mem, heavy_mem, gkeys, gvals;
+    Arena plan_mem, heavy_mem, gkeys, gvals, mlp_mem, pred_mem, fused_mem, stage_mem;
+    bool has_predictor = false;
+    float pred_delta = 0.f;
     Plan plan;
     smash_stats stats{};
     std::vector<hipEvent_t> event_pool;
@@ -383,6 +398,94 @@ smash_status numeric_impl(smash_ctx c, hipStream_t s, const Plan &p, const V *Av
     });
 }
 
+template <typename V, int LOGT>
+smash_status launch_fused_bin(smash_ctx c, hipStream_t s, const Plan &p, int cnt, const int *rows)
+{
+    using S = BinShape<LOGT>;
+    return launch(c, K_FUSED_ROWS, s, [&] {
+        k_fused_rows<V, LOGT, S::WPR, S::RPW><<<blocks_for(cnt, S::RPW), S::THREADS, 0, s>>>(
+            p.A.row_ptr, p.A.col_idx, (const V *)p.A.val, p.B.row_ptr, p.B.col_idx, (const V *)p.B.val, rows, cnt,
+            p.fcap, p.stage_off, p.stage_col, (V *)p.stage_val, p.nnzc, p.fstatus);
+    });
+}
+
+template <typename V>
+smash_status run_fused_bins(smash_ctx c, hipStream_t s, const Plan &p, const BinHdr &b)
+{
+#define FUSED_BIN(LT)                                                                                  \
+    if (b.count[LT - kMinLogT])                                                                        \
+        TRY(launch_fused_bin<V, LT>(c, s, p, b.count[LT - kMinLogT], p.f_perm + b.offset[LT - kMinLogT]));
+    FUSED_BIN(6) FUSED_BIN(7) FUSED_BIN(8) FUSED_BIN(9) FUSED_BIN(10) FUSED_BIN(11)
+#undef FUSED_BIN
+    return SMASH_OK;
+}
+
+smash_status bin_rows(smash_ctx c, hipStream_t s, const Plan &p, const unsigned char *bin_of, const long long *ub,
+                      const int *wt, BinHdr *dh, int *perm, const int *gsize_of);
+template <typename TIn>
+smash_status scan_counts(smash_ctx c, hipStream_t s, long long n, const TIn *cnt, long long *bsum, long long *out,
+                         long long *total);
+smash_status read_hdr(smash_ctx c, hipStream_t s);
+
+// The fused stage of smash_spgemm_fused: features, predicted capacities,
+// fused bins, staging offsets, the fused kernels, and removal of the rows
+// they completed from the two-phase plan.
+smash_status fused_stage(smash_ctx c, hipStream_t s, Plan &p)
+{
+    const int m = (int)p.m;
+    const size_t vb = p.fused_dtype == SMASH_F32 ? 4 : 8;
+    const size_t need = carve_size({(size_t)m * kFeat * 4, (size_t)m * 4, (size_t)m * 4, (size_t)m * 4,
+                                    (size_t)m * 4, (size_t)m, (size_t)m, (size_t)(m + 1) * 8});
+    TRY(ensure(c, c->fused_mem, need, s));
+    Carve cv{(char *)c->fused_mem.ptr};
+    p.feats = cv.take<float>((size_t)m * kFeat);
+    p.maxb = cv.take<int>(m);
+    p.cap_pred = cv.take<int>(m);
+    p.fcap = cv.take<int>(m);
+    p.f_perm = cv.take<int>(m);
+    p.fbin = cv.take<unsigned char>(m);
+    p.fstatus = cv.take<unsigned char>(m);
+    p.stage_off = cv.take<long long>(m + 1);
+    const float *prm = (const float *)c->pred_mem.ptr;
+    TRY(launch(c, K_FEATURES, s, [&] {
+        k_features<<<blocks_for(m, 4), 256, 0, s>>>(m, (int)p.n, p.A.row_ptr, p.A.col_idx, p.B.row_ptr, p.feats,
+                                                    nullptr, p.maxb);
+    }));
+    TRY(launch(c, K_MLP_PREDICT, s, [&] {
+        k_mlp_predict<<<blocks_for(m, 256), 256, 0, s>>>(m, (int)p.n, p.feats, prm, prm + kParams, c->pred_delta,
+                                                         p.ub, p.maxb, nullptr, p.cap_pred);
+    }));
+    TRY(launch(c, K_FUSED_AUX, s, [&] {
+        k_fused_bins<<<blocks_for(m, 256), 256, 0, s>>>(m, p.ub, p.cap_pred, p.lds_row_max, p.fbin, p.fcap);
+    }));
+    TRY(bin_rows(c, s, p, p.fbin, nullptr, nullptr, &c->d_hdr->fz, p.f_perm, nullptr));
+    TRY(scan_counts<int>(c, s, m, p.fcap, p.bsum, p.stage_off, &c->d_hdr->stage_total));
+    TRY(read_hdr(c, s));
+    const BinHdr fz = c->h_hdr->fz;
+    const long long total = c->h_hdr->stage_total;
+    TRY(ensure(c, c->stage_mem, carve_size({(size_t)total * 4, (size_t)total * vb}), s));
+    Carve sv{(char *)c->stage_mem.ptr};
+    p.stage_col = sv.take<int>(total);
+    p.stage_val = sv.take<char>(total * vb);
+    if (p.fused_dtype == SMASH_F32) TRY(run_fused_bins<float>(c, s, p, fz));
+    else TRY(run_fused_bins<double>(c, s, p, fz));
+    TRY(launch(c, K_FUSED_AUX, s, [&] {
+        k_fused_mark<<<blocks_for(m, 256), 256, 0, s>>>(m, p.fbin, p.fstatus, p.sym_bin, &c->d_hdr->fused_ok);
+    }));
+    return SMASH_OK;
+}
+
+template <typename V>
+smash_status fused_copy(smash_ctx c, hipStream_t s, const Plan &p, const int64_t *crp, int32_t *ccol, V *cval)
+{
+    const int nf = p.hdr.fz.offset[kLdsBins];
+    if (!p.fused || nf == 0) return SMASH_OK;
+    return launch(c, K_FUSED_COPY, s, [&] {
+        k_fused_copy<V><<<blocks_for(nf, 4), 256, 0, s>>>(p.f_perm, nf, p.fstatus, p.stage_off, p.stage_col,
+                                                         (const V *)p.stage_val, (const long long *)crp, ccol, cval);
+    });
+}
+
 smash_status read_hdr(smash_ctx c, hipStream_t s)
 {
     HIP_TRY(c, hipMemcpyAsync(c->h_hdr, c->d_hdr, sizeof(DevHdr), hipMemcpyDeviceToHost, s));
@@ -451,7 +554,8 @@ void smash_destroy(smash_ctx c)
 {
     if (!c) return;
     DeviceGuard g(c->device);
-    for (Arena *a : {&c->plan_mem, &c->heavy_mem, &c->gkeys, &c->gvals})
+    for (Arena *a : {&c->plan_mem, &c->heavy_mem, &c->gkeys, &c->gvals, &c->mlp_mem, &c->pred_mem, &c->fused_mem,
+                     &c->stage_mem})
         if (a->ptr) (void)hipFree(a->ptr);
     if (c->d_hdr) (void)hipFree(c->d_hdr);
     if (c->h_hdr) (void)hipHostFree(c->h_hdr);
@@ -493,14 +597,18 @@ smash_status smash_get_option(smash_ctx c, smash_option opt, int64_t *v)
     return SMASH_OK;
 }
 
-smash_status smash_spgemm_symbolic(smash_ctx c, const smash_csr *A, const smash_csr *B, int64_t *C_row_ptr,
-                                   int64_t *C_nnz, hipStream_t s)
+namespace {
+
+// The symbolic pipeline; with fused_dtype >= 0 it first runs the fused stage
+// for the rows the predictor sizes into LDS (smash_spgemm_fused).
+smash_status symbolic_impl(smash_ctx c, const smash_csr *A, const smash_csr *B, int64_t *C_row_ptr, int64_t *C_nnz,
+                           hipStream_t s, int fused_dtype)
 {
-    if (!c) return SMASH_ERR_INVALID_ARG;
+    const bool fuse = fused_dtype >= 0;
     c->err.clear();
     c->plan.valid = false;
-    TRY(check_csr(c, A, "A", false));
-    TRY(check_csr(c, B, "B", false));
+    TRY(check_csr(c, A, "A", fuse));
+    TRY(check_csr(c, B, "B", fuse));
     if (A->cols != B->rows) return fail(c, SMASH_ERR_INVALID_ARG, "A.cols (%lld) != B.rows (%lld)", (long long)A->cols, (long long)B->rows);
     if (!C_row_ptr || !C_nnz) return fail(c, SMASH_ERR_INVALID_ARG, "C_row_ptr and C_nnz must not be NULL");
     DeviceGuard g(c->device);
@@ -516,6 +624,8 @@ smash_status smash_spgemm_symbolic(smash_ctx c, const smash_csr *A, const smash_
     p.heavy_mode = (int)c->opt[SMASH_OPT_HEAVY_MODE];
     p.lds_row_max = (int)c->opt[SMASH_OPT_LDS_ROW_MAX];
     p.nchunks = (int)std::max<int64_t>(1, (p.n + kChunkCols - 1) / kChunkCols);
+    p.fused = fuse;
+    p.fused_dtype = fuse ? fused_dtype : 0;
     const int64_t m = p.m;
     c->stats = smash_stats();
     c->stats.rows = m;
@@ -530,6 +640,11 @@ smash_status smash_spgemm_symbolic(smash_ctx c, const smash_csr *A, const smash_
             k_validate<<<blocks_for(std::max<int64_t>(B->rows, 1), 4), 256, 0, s>>>(
                 (int)B->rows, (int)B->cols, B->nnz, B->row_ptr, B->col_idx, kErrCsrB, &c->d_hdr->error);
         }));
+    }
+    if (c->opt[SMASH_OPT_VALIDATE] && m > 0) {
+        // no kernel below may dereference an index of an invalid matrix
+        TRY(read_hdr(c, s));
+        TRY(device_errors(c, c->h_hdr->error));
     }
     if (m == 0) {
         HIP_TRY(c, hipMemsetAsync(C_row_ptr, 0, sizeof(int64_t), s));
@@ -577,6 +692,7 @@ smash_status smash_spgemm_symbolic(smash_ctx c, const smash_csr *A, const smash_
         k_analyze<<<blocks_for(m, 4), 256, 0, s>>>((int)m, (int)p.n, p.lds_row_max, A->row_ptr, A->col_idx, B->row_ptr,
                                                    p.ub, p.cap, p.nnzc, p.sym_bin);
     }));
+    if (fuse) TRY(fused_stage(c, s, p));
     TRY(bin_rows(c, s, p, p.sym_bin, p.ub, nullptr, &c->d_hdr->sym, p.sym_perm, global ? p.cap : nullptr));
     TRY(read_hdr(c, s));
     TRY(device_errors(c, c->h_hdr->error));
@@ -663,8 +779,22 @@ smash_status smash_spgemm_symbolic(smash_ctx c, const smash_csr *A, const smash_
     c->stats.nnz_heavy = p.hdr.num.wsum[kBinHeavy];
     c->stats.nnz_dense = global ? 0 : p.hdr.seg.nnz[kSegDense];
     c->stats.global_slots = global ? (int64_t)(p.hdr.gneed[0] + p.hdr.gneed[1]) : 0;
+    if (fuse) {
+        c->stats.fused_rows = p.hdr.fused_ok;
+        c->stats.fused_overflow = p.hdr.fz.offset[kLdsBins] - p.hdr.fused_ok;
+        c->stats.rows_empty -= p.hdr.fused_ok;
+    }
     p.valid = true;
     return SMASH_OK;
+}
+
+}  // namespace
+
+smash_status smash_spgemm_symbolic(smash_ctx c, const smash_csr *A, const smash_csr *B, int64_t *C_row_ptr,
+                                   int64_t *C_nnz, hipStream_t s)
+{
+    if (!c) return SMASH_ERR_INVALID_ARG;
+    return symbolic_impl(c, A, B, C_row_ptr, C_nnz, s, -1);
 }
 
 smash_status smash_spgemm_numeric(smash_ctx c, smash_dtype dtype, const smash_csr *A, const smash_csr *B,
@@ -676,7 +806,7 @@ smash_status smash_spgemm_numeric(smash_ctx c, smash_dtype dtype, const smash_cs
     TRY(check_csr(c, A, "A", true));
     TRY(check_csr(c, B, "B", true));
     const Plan &p = c->plan;
-    if (!p.valid || !same_csr(p.A, *A) || !same_csr(p.B, *B) || p.crp != C_row_ptr)
+    if (!p.valid || p.fused || !same_csr(p.A, *A) || !same_csr(p.B, *B) || p.crp != C_row_ptr)
         return fail(c, SMASH_ERR_NO_PLAN, "no symbolic plan on this context for these A, B and C_row_ptr");
     if (p.hdr.nnz_c > 0 && (!C_col_idx || !C_val))
         return fail(c, SMASH_ERR_INVALID_ARG, "C_col_idx and C_val must not be NULL");
@@ -713,6 +843,239 @@ smash_status smash_spgemm(smash_ctx c, smash_dtype dtype, const smash_csr *A, co
     *C_val = val;
     *C_nnz = nnz;
     return smash_spgemm_numeric(c, dtype, A, B, C_row_ptr, (int32_t *)col, val, s);
+}
+
+smash_status smash_features(smash_ctx c, const smash_csr *A, const smash_csr *B, float *feats, hipStream_t s)
+{
+    if (!c) return SMASH_ERR_INVALID_ARG;
+    c->err.clear();
+    TRY(check_csr(c, A, "A", false));
+    TRY(check_csr(c, B, "B", false));
+    if (A->cols != B->rows) return fail(c, SMASH_ERR_INVALID_ARG, "A.cols != B.rows");
+    if (!feats && A->rows > 0) return fail(c, SMASH_ERR_INVALID_ARG, "feats is NULL");
+    if (A->rows == 0) return SMASH_OK;
+    DeviceGuard g(c->device);
+    TRY(launch(c, K_FEATURES, s, [&] {
+        k_features<<<blocks_for(A->rows, 4), 256, 0, s>>>((int)A->rows, (int)B->cols, A->row_ptr, A->col_idx,
+                                                          B->row_ptr, feats, nullptr, nullptr);
+    }));
+    return SMASH_OK;
+}
+
+smash_status smash_mlp_predict(smash_ctx c, int64_t m, const float *feats, const float *params, const float *ms,
+                               float *yhat, hipStream_t s)
+{
+    if (!c) return SMASH_ERR_INVALID_ARG;
+    c->err.clear();
+    if (m < 0 || m >= INT32_MAX) return fail(c, SMASH_ERR_INVALID_ARG, "bad row count");
+    if (m == 0) return SMASH_OK;
+    if (!feats || !params || !ms || !yhat) return fail(c, SMASH_ERR_INVALID_ARG, "null pointer");
+    DeviceGuard g(c->device);
+    TRY(launch(c, K_MLP_PREDICT, s, [&] {
+        k_mlp_predict<<<blocks_for(m, 256), 256, 0, s>>>((int)m, 0, feats, params, ms, 0.f, nullptr, nullptr, yhat,
+                                                         nullptr);
+    }));
+    return SMASH_OK;
+}
+
+namespace {
+
+struct MlpBufs {
+    float *h1, *h2, *dz2, *dz1, *dy, *grad, *mom, *vel;
+    double *sse;
+};
+
+smash_status mlp_bufs(smash_ctx c, hipStream_t s, int batch, long long sse_slots, MlpBufs &b)
+{
+    const size_t need = carve_size({(size_t)batch * kHid * 4, (size_t)batch * kHid * 4, (size_t)batch * kHid * 4,
+                                    (size_t)batch * kHid * 4, (size_t)batch * 4, (size_t)kParams * 4,
+                                    (size_t)kParams * 4, (size_t)kParams * 4, (size_t)sse_slots * 8});
+    TRY(ensure(c, c->mlp_mem, need, s));
+    Carve cv{(char *)c->mlp_mem.ptr};
+    b.h1 = cv.take<float>((size_t)batch * kHid);
+    b.h2 = cv.take<float>((size_t)batch * kHid);
+    b.dz2 = cv.take<float>((size_t)batch * kHid);
+    b.dz1 = cv.take<float>((size_t)batch * kHid);
+    b.dy = cv.take<float>(batch);
+    b.grad = cv.take<float>(kParams);
+    b.mom = cv.take<float>(kParams);
+    b.vel = cv.take<float>(kParams);
+    b.sse = cv.take<double>(sse_slots);
+    return SMASH_OK;
+}
+
+// Forward and backward of one batch; leaves the gradient in b.grad and the
+// block sums of squared errors in sse[0 .. ceil(n/256)).
+smash_status mlp_step(smash_ctx c, hipStream_t s, const float *feats, const float *targets, const int *idx, int n,
+                      const float *ms, const float *params, MlpBufs &b, double *sse)
+{
+    TRY(launch(c, K_MLP_FWD, s, [&] {
+        k_mlp_fwd<<<blocks_for(n, 256), 256, 0, s>>>(n, idx, feats, targets, ms, params, b.h1, b.h2, b.dy, sse);
+    }));
+    TRY(launch(c, K_MLP_BWD, s, [&] {
+        k_mlp_grad_out<<<kHid + 1, 256, 0, s>>>(n, b.h2, b.dy, params, b.dz2, b.grad);
+    }));
+    TRY(launch(c, K_MLP_BWD, s, [&] { k_mlp_grad_mid<<<kHid, 256, 0, s>>>(n, b.h1, b.dz2, b.grad); }));
+    TRY(launch(c, K_MLP_BWD, s, [&] {
+        k_mlp_back_h1<<<blocks_for((long long)n * kHid, 256), 256, 0, s>>>(n, b.h1, b.dz2, params, b.dz1);
+    }));
+    TRY(launch(c, K_MLP_BWD, s, [&] { k_mlp_grad_in<<<kHid, 256, 0, s>>>(n, idx, feats, ms, b.dz1, b.grad); }));
+    return SMASH_OK;
+}
+
+}  // namespace
+
+smash_status smash_mlp_loss_grad(smash_ctx c, const float *feats, const float *targets, const int32_t *idx, int64_t n,
+                                 const float *ms, const float *params, float *grad, double *loss, hipStream_t s)
+{
+    if (!c) return SMASH_ERR_INVALID_ARG;
+    c->err.clear();
+    if (n <= 0 || n > (1 << 24)) return fail(c, SMASH_ERR_INVALID_ARG, "batch size must be in [1, 2^24]");
+    if (!feats || !targets || !idx || !ms || !params || !grad || !loss)
+        return fail(c, SMASH_ERR_INVALID_ARG, "null pointer");
+    DeviceGuard g(c->device);
+    MlpBufs b;
+    const int nb = (int)blocks_for(n, 256);
+    TRY(mlp_bufs(c, s, (int)n, nb, b));
+    TRY(mlp_step(c, s, feats, targets, idx, (int)n, ms, params, b, b.sse));
+    HIP_TRY(c, hipMemcpyAsync(grad, b.grad, kParams * sizeof(float), hipMemcpyDeviceToDevice, s));
+    std::vector<double> part(nb);
+    HIP_TRY(c, hipMemcpyAsync(part.data(), b.sse, nb * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    collect_times(c);
+    double tot = 0;
+    for (double v : part) tot += v;
+    *loss = tot / (double)n;
+    return SMASH_OK;
+}
+
+smash_status smash_mlp_train(smash_ctx c, const float *feats, const float *targets, int64_t n, const float *ms,
+                             float *params, const int32_t *orders, const smash_train_args *a, double *epoch_loss,
+                             hipStream_t s)
+{
+    if (!c) return SMASH_ERR_INVALID_ARG;
+    c->err.clear();
+    if (!a || a->epochs <= 0 || a->batch <= 0 || a->batch > (1 << 20) || n <= 0 || n >= INT32_MAX)
+        return fail(c, SMASH_ERR_INVALID_ARG, "bad training arguments");
+    if (!feats || !targets || !ms || !params || !orders || !epoch_loss)
+        return fail(c, SMASH_ERR_INVALID_ARG, "null pointer");
+    DeviceGuard g(c->device);
+    const int batch = (int)std::min<int64_t>(a->batch, n);
+    const int steps = (int)((n + batch - 1) / batch);
+    const int nbmax = (int)blocks_for(batch, 256);
+    const long long slots = (long long)a->epochs * steps * nbmax;
+    MlpBufs b;
+    TRY(mlp_bufs(c, s, batch, slots, b));
+    HIP_TRY(c, hipMemsetAsync(b.mom, 0, kParams * sizeof(float), s));
+    HIP_TRY(c, hipMemsetAsync(b.vel, 0, kParams * sizeof(float), s));
+    HIP_TRY(c, hipMemsetAsync(b.sse, 0, slots * sizeof(double), s));
+    int t = 0;
+    for (int e = 0; e < a->epochs; ++e) {
+        for (int st = 0; st < steps; ++st) {
+            const int s0 = st * batch;
+            const int nb = (int)std::min<int64_t>(batch, n - s0);
+            const int *idx = orders + (long long)e * n + s0;
+            TRY(mlp_step(c, s, feats, targets, idx, nb, ms, params, b, b.sse + ((long long)e * steps + st) * nbmax));
+            ++t;
+            TRY(launch(c, K_ADAM, s, [&] {
+                k_adam<<<blocks_for(kParams, 256), 256, 0, s>>>(kParams, params, b.grad, b.mom, b.vel, t, a->lr,
+                                                               a->beta1, a->beta2, a->eps);
+            }));
+        }
+    }
+    std::vector<double> part(slots);
+    HIP_TRY(c, hipMemcpyAsync(part.data(), b.sse, slots * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    collect_times(c);
+    for (int e = 0; e < a->epochs; ++e) {
+        double acc = 0.0;
+        for (int st = 0; st < steps; ++st) {
+            const int nb = (int)std::min<int64_t>(batch, n - (long long)st * batch);
+            double sse = 0.0;
+            for (int q = 0; q < nbmax; ++q) sse += part[((long long)e * steps + st) * nbmax + q];
+            acc += sse / nb;
+        }
+        epoch_loss[e] = acc / steps;
+    }
+    return SMASH_OK;
+}
+
+smash_status smash_predictor_set(smash_ctx c, const float *params, const float *ms, float delta)
+{
+    if (!c) return SMASH_ERR_INVALID_ARG;
+    c->err.clear();
+    if (!params || !ms) return fail(c, SMASH_ERR_INVALID_ARG, "null pointer");
+    for (int f = 0; f < kFeat; ++f)
+        if (!(ms[kFeat + f] > 0.f)) return fail(c, SMASH_ERR_INVALID_ARG, "feature std must be positive");
+    DeviceGuard g(c->device);
+    TRY(ensure(c, c->pred_mem, (kParams + 2 * kFeat) * sizeof(float), nullptr));
+    HIP_TRY(c, hipMemcpy(c->pred_mem.ptr, params, kParams * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy((float *)c->pred_mem.ptr + kParams, ms, 2 * kFeat * sizeof(float), hipMemcpyHostToDevice));
+    c->pred_delta = delta;
+    c->has_predictor = true;
+    return SMASH_OK;
+}
+
+smash_status smash_predictor_load(smash_ctx c, const char *path)
+{
+    if (!c) return SMASH_ERR_INVALID_ARG;
+    c->err.clear();
+    if (!path) return fail(c, SMASH_ERR_INVALID_ARG, "null path");
+    FILE *f = fopen(path, "rb");
+    if (!f) return fail(c, SMASH_ERR_INVALID_ARG, "cannot open %s", path);
+    char magic[8];
+    int32_t ver = 0, np = 0;
+    float delta = 0.f;
+    std::vector<float> ms(2 * kFeat), prm(kParams);
+    const bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, "SMASHMLP", 8) == 0 && fread(&ver, 4, 1, f) == 1 &&
+                    ver == 1 && fread(&np, 4, 1, f) == 1 && np == kParams && fread(&delta, 4, 1, f) == 1 &&
+                    fread(ms.data(), 4, ms.size(), f) == ms.size() && fread(prm.data(), 4, prm.size(), f) == prm.size();
+    fclose(f);
+    if (!ok) return fail(c, SMASH_ERR_INVALID_ARG, "%s is not a version-1 predictor file", path);
+    return smash_predictor_set(c, prm.data(), ms.data(), delta);
+}
+
+smash_status smash_spgemm_fused(smash_ctx c, smash_dtype dtype, const smash_csr *A, const smash_csr *B,
+                                smash_alloc_fn alloc, void *user, int64_t *C_row_ptr, int32_t **C_col_idx,
+                                void **C_val, int64_t *C_nnz, hipStream_t s)
+{
+    if (!c) return SMASH_ERR_INVALID_ARG;
+    if (!alloc || !C_col_idx || !C_val || !C_nnz || !C_row_ptr)
+        return fail(c, SMASH_ERR_INVALID_ARG, "null output argument");
+    if (dtype != SMASH_F32 && dtype != SMASH_F64) return fail(c, SMASH_ERR_INVALID_ARG, "unknown dtype %d", (int)dtype);
+    if (!c->has_predictor) return fail(c, SMASH_ERR_NO_PLAN, "no predictor installed (smash_predictor_set/load)");
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(c, SMASH_ERR_HIP, "hipSetDevice(%d) failed", c->device);
+    int64_t nnz = 0;
+    TRY(symbolic_impl(c, A, B, C_row_ptr, &nnz, s, (int)dtype));
+    Plan &p = c->plan;
+    const size_t vb = dtype == SMASH_F32 ? 4 : 8;
+    void *col = alloc(std::max<size_t>((size_t)nnz * 4, 256), user);
+    void *val = alloc(std::max<size_t>((size_t)nnz * vb, 256), user);
+    if (!col || !val) {
+        p.valid = false;
+        return fail(c, SMASH_ERR_OUT_OF_MEMORY, "allocation callback returned NULL");
+    }
+    *C_col_idx = (int32_t *)col;
+    *C_val = val;
+    *C_nnz = nnz;
+    smash_status st = SMASH_OK;
+    if (p.m > 0 && nnz > 0) {
+        HIP_TRY(c, hipMemsetAsync(&c->d_hdr->error, 0, sizeof(int), s));
+        if (dtype == SMASH_F32) {
+            st = numeric_impl<float>(c, s, p, (const float *)A->val, (const float *)B->val, C_row_ptr, (int32_t *)col,
+                                     (float *)val);
+            if (st == SMASH_OK) st = fused_copy<float>(c, s, p, C_row_ptr, (int32_t *)col, (float *)val);
+        } else {
+            st = numeric_impl<double>(c, s, p, (const double *)A->val, (const double *)B->val, C_row_ptr,
+                                      (int32_t *)col, (double *)val);
+            if (st == SMASH_OK) st = fused_copy<double>(c, s, p, C_row_ptr, (int32_t *)col, (double *)val);
+        }
+        if (st == SMASH_OK) st = read_hdr(c, s);
+        if (st == SMASH_OK) st = device_errors(c, c->h_hdr->error);
+    }
+    p.valid = false;    // the staged values belong to this call only
+    return st;
 }
 
 smash_status smash_get_stats(smash_ctx c, smash_stats *out)

@@ -1,0 +1,196 @@
+// smash_fused.hpp -- the fused single pass for rows the learned predictor
+// sizes into LDS.
+//
+// A row whose predicted capacity fits an LDS table is hashed, counted,
+// sorted and staged in one kernel, with no symbolic pass: the table has
+// next_pow2(2 * capacity) slots, and the row is accepted when its distinct
+// columns fit the capacity.  A row that does not fit (the prediction was
+// too small) is marked and handed to the exact two-phase path, as are rows
+// predicted too large for LDS.  After the row-pointer scan the staged rows
+// are copied to their final offsets.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "smash_kernels.hpp"
+
+namespace smash {
+
+// Fused bin of a row: LDS bin of its predicted capacity when
+// 0 < ub_i and cap_i <= fused_max, else kBinEmpty (not fused).
+__global__ __launch_bounds__(256) void k_fused_bins(int m, const long long *__restrict__ ub,
+                                                    const int *__restrict__ cap_pred, int fused_max,
+                                                    unsigned char *__restrict__ fbin, int *__restrict__ fcap)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const int c = cap_pred[i];
+    const bool fused = ub[i] > 0 && c > 0 && c <= fused_max;
+    fbin[i] = (unsigned char)(fused ? lds_bin(c) : kBinEmpty);
+    fcap[i] = fused ? c : 0;
+}
+
+// Like lds_insert_add, but a row stops inserting once it holds more distinct
+// columns than its capacity (*ndist counts them, *abort is raised): the
+// table then stays at most about half full, so probes stay short even when
+// the prediction was far too small.
+__device__ __forceinline__ void lds_bounded_insert_add(int *keys, double *vals, int logT, int key, double p,
+                                                       int cap, int *ndist, int *abort)
+{
+    if (__hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) return;
+    const unsigned mask = (1u << logT) - 1;
+    unsigned h = slot_of(key, logT);
+    for (unsigned probe = 0; probe <= mask; ++probe) {
+        int cur = __hip_atomic_load(&keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (cur == kEmpty) {
+            const int old = atomicCAS(&keys[h], kEmpty, key);
+            if (old == kEmpty) {
+                atomicAdd(&vals[h], p);
+                if (atomicAdd(ndist, 1) >= cap) atomicExch(abort, 1);
+                return;
+            }
+            cur = old;
+        }
+        if (cur == key) {
+            atomicAdd(&vals[h], p);
+            return;
+        }
+        h = (h + 1) & mask;
+    }
+    atomicExch(abort, 1);    // unreachable while cap <= T / 2
+}
+
+// Fused rows: products merged in an LDS table of 2^LOGT slots; a row whose
+// columns fit its capacity is compacted, sorted and written to the staging
+// area at stage_off[row] (status 1, nnzc = count); otherwise status 0 and
+// the row is left to the two-phase path.
+template <typename V, int LOGT, int WPR, int RPW>
+__global__ __launch_bounds__(kWave *WPR *RPW) void k_fused_rows(
+    const int *__restrict__ Arp, const int *__restrict__ Acol, const V *__restrict__ Aval,
+    const int *__restrict__ Brp, const int *__restrict__ Bcol, const V *__restrict__ Bval,
+    const int *__restrict__ rows, int nrows, const int *__restrict__ fcap, const long long *__restrict__ stage_off,
+    int *__restrict__ scol, V *__restrict__ sval, int *__restrict__ nnzc, unsigned char *__restrict__ status)
+{
+    static_assert(RPW == 1 || WPR == 1, "multi-row blocks use one wave per row");
+    constexpr int T = 1 << LOGT;
+    constexpr int G = WPR * kWave;
+    constexpr int SPT = T / G;
+    __shared__ int s_keys[RPW][T];
+    __shared__ double s_vals[RPW][T];
+    __shared__ EnumScratch<V, G> s_en[RPW];
+    __shared__ int s_scan[RPW][WPR + 1];
+    __shared__ int s_full[RPW];
+    __shared__ int s_ndist[RPW];
+    const int lane = lane_id(), wave = threadIdx.x / kWave;
+    const int g = wave / WPR, wg = wave % WPR;
+    const int gt = threadIdx.x - g * G;
+    const int r = blockIdx.x * RPW + g;
+    const bool active = r < nrows;
+    const int row = active ? rows[r] : 0;
+    int *keys = s_keys[g];
+    double *vals = s_vals[g];
+    for (int t = gt; t < T; t += G) {
+        keys[t] = kEmpty;
+        vals[t] = 0.0;
+    }
+    if (gt == 0) {
+        s_full[g] = 0;
+        s_ndist[g] = 0;
+    }
+    const int cap = active ? fcap[row] : 0;
+    group_sync<WPR>();
+    if (active) {
+        group_products<V, true, G, 4>(
+            Arp[row], Arp[row + 1], gt, s_en[g], Bcol, Bval,
+            [&](int e, int &bs, int &bl, V &a) {
+                const int k = Acol[e];
+                bs = Brp[k];
+                bl = Brp[k + 1] - bs;
+                a = Aval[e];
+            },
+            [&](int j, double p) { lds_bounded_insert_add(keys, vals, LOGT, j, p, cap, &s_ndist[g], &s_full[g]); });
+    }
+    group_sync<WPR>();
+    int kr[SPT];
+    double vr[SPT];
+    int cnt = 0;
+#pragma unroll
+    for (int s = 0; s < SPT; ++s) {
+        kr[s] = keys[gt * SPT + s];
+        vr[s] = vals[gt * SPT + s];
+        cnt += kr[s] != kEmpty;
+    }
+    const int incl = wave_incl_scan(cnt);
+    if (lane == kWave - 1) s_scan[g][wg] = incl;
+    group_sync<WPR>();
+    int wbase = 0, total = 0;
+    for (int w = 0; w < WPR; ++w) {
+        const int t = s_scan[g][w];
+        if (w < wg) wbase += t;
+        total += t;
+    }
+    const bool ok = active && !s_full[g] && total <= cap;
+    int pos = wbase + incl - cnt;
+    group_sync<WPR>();
+#pragma unroll
+    for (int s = 0; s < SPT; ++s) {
+        if (kr[s] != kEmpty) {
+            keys[pos] = kr[s];
+            vals[pos] = vr[s];
+            ++pos;
+        }
+    }
+    const int n2 = total <= 1 ? 1 : (1 << ceil_log2(total));
+    for (int t = total + gt; t < n2; t += G) keys[t] = 0x7fffffff;
+    group_sync<WPR>();
+    if (ok) group_bitonic<double, WPR>(keys, vals, n2, gt);
+    if (active) {
+        if (ok) {
+            const long long o = stage_off[row];
+            for (int t = gt; t < total; t += G) {
+                scol[o + t] = keys[t];
+                sval[o + t] = (V)vals[t];
+            }
+        }
+        if (gt == 0) {
+            status[row] = ok ? 1 : 0;
+            if (ok) nnzc[row] = total;
+        }
+    }
+}
+
+// Rows completed by the fused pass leave the two-phase plan.
+__global__ __launch_bounds__(256) void k_fused_mark(int m, const unsigned char *__restrict__ fbin,
+                                                    const unsigned char *__restrict__ status,
+                                                    unsigned char *__restrict__ sym_bin, int *fused_ok)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool done = i < m && fbin[i] != kBinEmpty && status[i] == 1;
+    if (done) sym_bin[i] = kBinEmpty;
+    const unsigned long long b = __ballot(done);
+    if (lane_id() == 0 && b) atomicAdd(fused_ok, (int)__popcll(b));
+}
+
+// Copies the staged rows of the fused pass to their final offsets in C
+// (one wave per row, coalesced, non-temporal stores).
+template <typename V>
+__global__ __launch_bounds__(256) void k_fused_copy(const int *__restrict__ rows, int nrows,
+                                                    const unsigned char *__restrict__ status,
+                                                    const long long *__restrict__ stage_off,
+                                                    const int *__restrict__ scol, const V *__restrict__ sval,
+                                                    const long long *__restrict__ Crp, int *__restrict__ Ccol,
+                                                    V *__restrict__ Cval)
+{
+    const int r = blockIdx.x * 4 + threadIdx.x / kWave;
+    if (r >= nrows) return;
+    const int row = rows[r];
+    if (status[row] != 1) return;
+    const long long o = stage_off[row], d = Crp[row];
+    const int n = (int)(Crp[row + 1] - d);
+    for (int t = lane_id(); t < n; t += kWave) {
+        store_c(&Ccol[d + t], scol[o + t]);
+        store_c(&Cval[d + t], sval[o + t]);
+    }
+}
+
+}  // namespace smash

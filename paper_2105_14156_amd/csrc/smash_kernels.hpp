@@ -80,10 +80,11 @@ struct DevHdr {
     unsigned long long products;       // sum over rows of products
     unsigned long long gneed[2];       // global-hash slots: [0] symbolic, [1] numeric
     long long nnz_c;
-    BinHdr sym, num;
+    long long stage_total;             // staging entries of the fused pass
+    BinHdr sym, num, fz;
     SegHdr seg;
     int error;
-    int pad;
+    int fused_ok;                      // rows completed by the fused pass
 };
 
 // A column segment of a heavy row: the row, its A entries, the chunk range,
@@ -445,7 +446,8 @@ __global__ __launch_bounds__(256) void k_num_bins(int m, const int *__restrict__
     if (i >= m) return;
     const int b = sym_bin_of[i];
     const int nc = nnzc[i];
-    bin_out[i] = (unsigned char)(b == kBinHeavy ? kBinHeavy : (nc == 0 ? kBinEmpty : lds_bin(nc)));
+    // rows outside the plan (no products, or completed by the fused pass) stay out
+    bin_out[i] = (unsigned char)(b == kBinHeavy ? kBinHeavy : (b == kBinEmpty || nc == 0 ? kBinEmpty : lds_bin(nc)));
 }
 
 // Per-block bin histograms (kBinBlockRows rows per block, no global atomics):

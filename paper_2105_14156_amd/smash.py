@@ -35,13 +35,20 @@ class CsrDesc(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in ("rows", "products", "nnz_c", "rows_empty", "rows_lds",
                                                "rows_heavy", "heavy_segments", "heavy_dense_chunks",
-                                               "global_slots", "nnz_heavy", "nnz_dense")]
+                                               "global_slots", "nnz_heavy", "nnz_dense", "fused_rows",
+                                               "fused_overflow")]
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+MLP_FEATURES, MLP_PARAMS = 6, 4673
+
+
+class TrainArgs(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
 
 _c = ctypes.c_void_p
 _lib.smash_create.argtypes = [ctypes.POINTER(_c), ctypes.c_int]
@@ -63,6 +70,18 @@ _lib.smash_kernel_count.argtypes = []
 _lib.smash_kernel_time.argtypes = [_c, ctypes.c_int, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_int64),
                                    ctypes.POINTER(ctypes.c_double)]
 _lib.smash_kernel_time_reset.argtypes = [_c]
+_lib.smash_features.argtypes = [_c, ctypes.POINTER(CsrDesc), ctypes.POINTER(CsrDesc), _c, _c]
+_lib.smash_mlp_predict.argtypes = [_c, ctypes.c_int64, _c, _c, _c, _c, _c]
+_lib.smash_mlp_loss_grad.argtypes = [_c, _c, _c, _c, ctypes.c_int64, _c, _c, _c, ctypes.POINTER(ctypes.c_double), _c]
+_lib.smash_mlp_train.argtypes = [_c, _c, _c, ctypes.c_int64, _c, _c, _c, ctypes.POINTER(TrainArgs),
+                                 ctypes.POINTER(ctypes.c_double), _c]
+_lib.smash_predictor_set.argtypes = [_c, _c, _c, ctypes.c_float]
+_lib.smash_predictor_load.argtypes = [_c, ctypes.c_char_p]
+_lib.smash_spgemm_fused.argtypes = _lib.smash_spgemm.argtypes
+_lib.smash_spgemm_fused.restype = ctypes.c_int
+for _f in ("smash_features", "smash_mlp_predict", "smash_mlp_loss_grad", "smash_mlp_train", "smash_predictor_set",
+           "smash_predictor_load"):
+    getattr(_lib, _f).restype = ctypes.c_int
 for _f in ("smash_create", "smash_set_option", "smash_get_option", "smash_spgemm_symbolic", "smash_spgemm_numeric",
            "smash_spgemm", "smash_get_stats", "smash_kernel_count", "smash_kernel_time", "smash_kernel_time_reset"):
     getattr(_lib, _f).restype = ctypes.c_int
@@ -166,7 +185,11 @@ class Context:
                                               C_row_ptr.data_ptr(), C_col.data_ptr() if C_col.numel() else 0,
                                               C_val.data_ptr() if C_val.numel() else 0, _stream_ptr(stream)))
 
-    def spgemm(self, A: DeviceCSR, B: DeviceCSR, stream=None, C_row_ptr=None) -> DeviceCSR:
+    def spgemm_fused(self, A: DeviceCSR, B: DeviceCSR, stream=None, C_row_ptr=None) -> DeviceCSR:
+        """C = A * B through smash_spgemm_fused (needs an installed predictor)."""
+        return self.spgemm(A, B, stream, C_row_ptr, _fn=_lib.smash_spgemm_fused)
+
+    def spgemm(self, A: DeviceCSR, B: DeviceCSR, stream=None, C_row_ptr=None, _fn=None) -> DeviceCSR:
         """C = A * B through smash_spgemm; C's arrays come from torch."""
         import torch
         dev = A.row_ptr.device
@@ -182,13 +205,61 @@ class Context:
         cb = ALLOC_FN(_alloc)
         col_p, val_p, nnz = _c(), _c(), ctypes.c_int64()
         da, db = A.desc(), B.desc()
-        self._check(_lib.smash_spgemm(self._h, _dtype_code(A.val), ctypes.byref(da), ctypes.byref(db), cb, None,
+        fn = _fn or _lib.smash_spgemm
+        self._check(fn(self._h, _dtype_code(A.val), ctypes.byref(da), ctypes.byref(db), cb, None,
                                       C_row_ptr.data_ptr(), ctypes.byref(col_p), ctypes.byref(val_p),
                                       ctypes.byref(nnz), _stream_ptr(stream)))
         n = int(nnz.value)
         col = held[0].view(torch.int32)[:n]
         val = held[1].view(A.val.dtype)[:n]
         return DeviceCSR(A.rows, B.cols, C_row_ptr, col, val)
+
+    # ------------------------------------------------------------ predictor
+    def features(self, A: DeviceCSR, B: DeviceCSR, stream=None):
+        import torch
+        out = torch.empty((A.rows, MLP_FEATURES), dtype=torch.float32, device=A.row_ptr.device)
+        da, db = A.desc(), B.desc()
+        self._check(_lib.smash_features(self._h, ctypes.byref(da), ctypes.byref(db), out.data_ptr() if A.rows else 0,
+                                        _stream_ptr(stream)))
+        return out
+
+    def mlp_predict(self, feats, params, mean_std, stream=None):
+        import torch
+        out = torch.empty(feats.shape[0], dtype=torch.float32, device=feats.device)
+        self._check(_lib.smash_mlp_predict(self._h, feats.shape[0], feats.data_ptr(), params.data_ptr(),
+                                           mean_std.data_ptr(), out.data_ptr(), _stream_ptr(stream)))
+        return out
+
+    def mlp_loss_grad(self, feats, targets, idx, mean_std, params, stream=None):
+        import torch
+        grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device=feats.device)
+        loss = ctypes.c_double()
+        self._check(_lib.smash_mlp_loss_grad(self._h, feats.data_ptr(), targets.data_ptr(), idx.data_ptr(),
+                                             idx.numel(), mean_std.data_ptr(), params.data_ptr(), grad.data_ptr(),
+                                             ctypes.byref(loss), _stream_ptr(stream)))
+        return float(loss.value), grad
+
+    def mlp_train(self, feats, targets, mean_std, params, orders, batch, lr=1e-3, beta1=0.9, beta2=0.999,
+                  eps=1e-8, stream=None):
+        """Trains params (device float32, updated in place); orders: device
+        int32 (epochs x n).  Returns the mean batch loss of every epoch."""
+        epochs = orders.shape[0]
+        args = TrainArgs(epochs, batch, lr, beta1, beta2, eps)
+        losses = (ctypes.c_double * epochs)()
+        self._check(_lib.smash_mlp_train(self._h, feats.data_ptr(), targets.data_ptr(), targets.numel(),
+                                         mean_std.data_ptr(), params.data_ptr(), orders.data_ptr(),
+                                         ctypes.byref(args), losses, _stream_ptr(stream)))
+        return np.array(list(losses))
+
+    def predictor_set(self, params, mean_std, delta: float):
+        p = np.ascontiguousarray(params, np.float32)
+        ms = np.ascontiguousarray(mean_std, np.float32)
+        self._check(_lib.smash_predictor_set(self._h, p.ctypes.data, ms.ctypes.data, float(delta)))
+
+    def predictor_load(self, path: str = None):
+        """Installs a predictor file (default: the weights shipped with the package)."""
+        path = path or os.path.join(HERE, "data", "predictor_v1.bin")
+        self._check(_lib.smash_predictor_load(self._h, os.fsencode(path)))
 
     def stats(self) -> dict:
         s = Stats()

@@ -287,3 +287,42 @@ def workload_batch(count: int = 512, dtype=np.float32, seed0: int = 0x5EED0400):
         B = uniform_k_per_row(n, n, 8, s ^ 0xB, dtype)
         out.append(Workload(f"batch{i}_n{n}_ef{ef}", A, B))
     return out
+
+
+# ---------------------------------------------------------------- predictor
+
+MLP_FEATURES = 6
+MLP_HIDDEN = 64
+# packed parameter layout shared by every implementation of the row-size MLP:
+# W1[64][6], b1[64], W2[64][64], b2[64], w3[64], b3
+MLP_LAYOUT = (("W1", (MLP_HIDDEN, MLP_FEATURES)), ("b1", (MLP_HIDDEN,)), ("W2", (MLP_HIDDEN, MLP_HIDDEN)),
+              ("b2", (MLP_HIDDEN,)), ("w3", (MLP_HIDDEN,)), ("b3", (1,)))
+MLP_PARAMS = sum(int(np.prod(s)) for _, s in MLP_LAYOUT)
+
+
+def normal01(seed: int, start: int, count: int) -> np.ndarray:
+    """Standard normal draws by Box-Muller from two SplitMix64 uniforms."""
+    u = uniform01(seed, 2 * start, 2 * count).reshape(count, 2)
+    u1 = np.maximum(u[:, 0], 2.0 ** -53)
+    return np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u[:, 1])
+
+
+def mlp_init(seed: int = 0x11A7) -> np.ndarray:
+    """He initialisation of the packed MLP parameters (float64): weights
+    N(0, 2 / fan_in), biases zero."""
+    out = []
+    pos = 0
+    for name, shape in MLP_LAYOUT:
+        n = int(np.prod(shape))
+        if name.startswith("b"):
+            out.append(np.zeros(n))
+        else:
+            fan_in = shape[-1] if len(shape) == 2 else MLP_HIDDEN
+            out.append(normal01(seed, pos, n) * np.sqrt(2.0 / fan_in))
+        pos += n
+    return np.concatenate(out)
+
+
+def batch_orders(n: int, epochs: int, seed: int = 0x0DE5) -> np.ndarray:
+    """One seeded permutation of range(n) per epoch (int32, epochs x n)."""
+    return np.stack([np.argsort(uniform01(seed + e, 0, n), kind="stable") for e in range(epochs)]).astype(np.int32)
