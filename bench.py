@@ -40,13 +40,16 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="s19", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="s19", choices=sorted(WORKLOADS) + ["batch"])
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--heavy-mode", type=int, default=0)
     ap.add_argument("--path", default="plain", choices=["plain", "fused"],
                     help="plain: symbolic + numeric; fused: learned-capacity single pass for LDS rows")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle time for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the fused-pass and batched-launch comparison beside the main line")
+    ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (counter calibration)")
     return ap.parse_args()
@@ -99,6 +102,81 @@ def cpu_baseline(A, B, target_s):
                       f"{prods / total:.1%}), {t:.1f} s wall"}
 
 
+def products_of(A, B) -> int:
+    """Sum over rows of A of the B-row lengths it selects (host arithmetic)."""
+    return int(np.diff(B.row_ptr).astype(np.int64)[A.col_idx].sum()) if A.nnz else 0
+
+
+def run_batch(count: int, steps: int, warmup: int, plain_loops: int = 2):
+    """The batched workload: `count` products in one captured graph (after
+    autotuning the plan), against a loop of plain smash_spgemm calls over the
+    same problems on the same stream.  Returns a dict of the measurements."""
+    import torch
+    from paper_2105_14156_amd import smash
+    t0 = time.perf_counter()
+    probs = synthetic.workload_batch(count)
+    log(f"batch of {count}: generated in {time.perf_counter() - t0:.1f} s")
+    dA = [smash.to_device(w.A) for w in probs]
+    dB = [smash.to_device(w.B) for w in probs]
+    products = sum(products_of(w.A, w.B) for w in probs)
+    ctx = smash.Context(0)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        plan = smash.BatchPlan(ctx, dA, dB, stream=stream)
+        cfg, tune_ms = plan.autotune(reps=3, stream=stream)
+        log(f"autotuned {cfg} ({tune_ms:.3f} ms per batch)")
+        plan.capture(stream)
+        for _ in range(warmup):
+            plan.launch(stream)
+        nnz_c, _ = plan.result(stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            plan.launch(stream)
+        e1.record(stream)
+        plan.result(stream)
+        graph_ms = e0.elapsed_time(e1) / steps
+        # the same problems one plain call at a time
+        for A, B in zip(dA[:8], dB[:8]):
+            ctx.spgemm(A, B, stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(plain_loops):
+            for A, B in zip(dA, dB):
+                ctx.spgemm(A, B, stream)
+        torch.cuda.synchronize()
+        loop_ms = (time.perf_counter() - t0) / plain_loops * 1e3
+    rows = sum(w.A.rows for w in probs)
+    alg = sum(metrics.algorithmic_bytes(w.A.rows, w.B.rows, w.A.nnz, w.B.nnz, 0, 4) for w in probs) \
+        + nnz_c * 8
+    plan.close()
+    ctx.close()
+    log(f"batch graph {graph_ms:.3f} ms, plain loop {loop_ms:.3f} ms")
+    return {"count": count, "rows": rows, "products": products, "nnz_c": nnz_c, "graph_ms": graph_ms,
+            "plain_loop_ms": loop_ms, "config": cfg, "autotune_ms": tune_ms, "alg_bytes": alg}
+
+
+def main_batch(args):
+    r = run_batch(args.batch_count, args.steps, args.warmup)
+    gflops = metrics.gflops(r["products"], r["graph_ms"] * 1e-3)
+    gbs = r["alg_bytes"] / (r["graph_ms"] * 1e-3) / 1e9
+    out = {
+        "metric": METRIC, "value": round(gflops, 3), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(r["graph_ms"], 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"batch{r['count']}_rmat_x_uniform8", "description":
+                   "512 products A_i*B_i: A_i RMAT n_i log-uniform in [256, 32768], edge factor uniform 4..32; "
+                   "B_i n_i x n_i with 8 uniform columns per row", "path": "batched graph replay (autotuned)",
+                   "rows": r["rows"], "products": r["products"], "nnz_c": r["nnz_c"], "tuned": r["config"]},
+        "hbm_gbs_algorithmic": round(gbs, 2), "path_roofline_frac": round(gbs / HBM_PEAK_GBS, 4),
+        "roofline": {"bound": "hbm", "kernel": "whole batch graph", "achieved": round(gbs, 2),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None},
+        "plain_loop_ms": round(r["plain_loop_ms"], 3),
+        "speedup_vs_plain_loop": round(r["plain_loop_ms"] / r["graph_ms"], 2),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -106,12 +184,15 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
-              f"(the multi-GPU row sharding is described in DESIGN.md, not built)", file=sys.stderr)
+              f"(row sharding across GPUs is a design, not built)", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2105_14156_amd import smash
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.workload == "batch":
+        main_batch(args)
+        return
     name, make, desc = WORKLOADS[args.workload]
     npdt = np.float32 if args.dtype == "f32" else np.float64
     vbytes = 4 if args.dtype == "f32" else 8
@@ -199,6 +280,38 @@ def main():
         "kernel_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in kt.items() if v[0]},
         "stats": st,
     }
+    if not args.no_variants:
+        # the learned fused pass on the same product, and the batched launch
+        other = "fused" if args.path == "plain" else "plain"
+        if other == "fused":
+            ctx.predictor_load()
+        run2 = (lambda: ctx.spgemm_fused(dA, dB, stream)) if other == "fused" else (lambda: ctx.spgemm(dA, dB, stream))
+        for _ in range(max(1, args.warmup)):
+            C = None
+            C = run2()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            C = None
+            C = run2()
+        torch.cuda.synchronize()
+        ms2 = (time.perf_counter() - t0) / args.steps * 1e3
+        st2 = ctx.stats()
+        C = None
+        log(f"{other} path: {ms2:.3f} ms per step")
+        b = run_batch(args.batch_count, args.steps, args.warmup)
+        out["variants"] = {
+            f"{other}_ms_per_step": round(ms2, 4),
+            f"{args.path}_ms_per_step": round(ms_step, 4),
+            "fused_speedup_vs_plain": round((ms2 / ms_step) if other == "plain" else (ms_step / ms2), 4),
+            "fused_rows": st2["fused_rows"] if other == "fused" else st["fused_rows"],
+            "fused_overflow": st2["fused_overflow"] if other == "fused" else st["fused_overflow"],
+            "batch": {"workload": f"batch{b['count']}_rmat_x_uniform8", "graph_ms": round(b["graph_ms"], 4),
+                      "plain_loop_ms": round(b["plain_loop_ms"], 3),
+                      "speedup_vs_plain_loop": round(b["plain_loop_ms"] / b["graph_ms"], 2),
+                      "gflops": round(metrics.gflops(b["products"], b["graph_ms"] * 1e-3), 3),
+                      "tuned": b["config"]},
+        }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(A, B, args.cpu_seconds)

@@ -231,6 +231,107 @@ smash_status smash_spgemm_fused(smash_ctx ctx, smash_dtype dtype, const smash_cs
  * little-endian.  Errors: INVALID_ARG (unreadable or malformed file). */
 smash_status smash_predictor_load(smash_ctx ctx, const char *path);
 
+/* ---------------------------------------------------------------- batches
+ * Many independent products C_p = A_p * B_p (p = 0 .. count-1) computed by
+ * one pipeline over the concatenated rows of all problems, so that uneven
+ * problem sizes share the machine and the whole batch costs one fixed
+ * sequence of kernel launches with no host synchronisation: it can be
+ * captured once as a HIP graph and replayed.  The pipeline is the same as
+ * smash_spgemm's (per-row product bounds, binning, symbolic, row-pointer
+ * scan, numeric: the steps of the SMASH Kernels chapter), with rows above the
+ * LDS limit hashed in per-row global-memory tables (its version 3).  Work is
+ * spread like the paper's tokenised row distribution (SMASH Version 2) and
+ * oversubscribed windows (Window Distribution Phase): persistent workgroups
+ * take row blocks of each bin from device-side counts.
+ *
+ * Output layout: one pool.  Global row g = row0[p] + i is row i of problem
+ * p (row0 = exclusive prefix of the problems' row counts).  C_row_ptr holds
+ * total_rows + 1 int64 offsets into the pool; problem p's C is rows
+ * row0[p] .. row0[p+1]-1 of that CSR (its row pointers are absolute pool
+ * offsets; its column indices are in B_p's column space).
+ */
+typedef struct smash_batch_plan_s *smash_batch_plan;
+
+/* Tunables of the batched launch (the autotuner chooses them):
+ *  lds_row_max   rows with min(products, cols) above this use global tables
+ *                (bin threshold): 32 .. 1024, and at most 2048 >> table_shift;
+ *  table_shift   LDS table slots = next_pow2(bound << table_shift): 1 or 2
+ *                (load factor at most 1/2 or 1/4);
+ *  wide_groups   0: one wavefront per row up to 1024 slots, 4 for 2048;
+ *                1: rows with 512 or more slots use 2, 4, 8 wavefronts;
+ *  blocks_per_cu persistent workgroups per compute unit: 1 .. 32. */
+typedef struct {
+    int32_t lds_row_max;
+    int32_t table_shift;
+    int32_t wide_groups;
+    int32_t blocks_per_cu;
+} smash_batch_config;
+
+/* Creates a plan for the `count` problems A[p] * B[p] (arrays of descriptors,
+ * read during the call only; the matrices they point to must stay alive and
+ * unmoved while the plan is used; values must be non-NULL, of `dtype`).  cfg
+ * NULL takes the defaults {1024, 1, 0, 8}.  Runs the per-row analysis once
+ * (synchronising `stream`) to size the output pool, which it allocates
+ * through `alloc`: C_row_ptr (int64[total_rows + 1]) and col/val pools of
+ * capacity sum over rows of min(products_i, cols_p), an exact upper bound on
+ * the entries of any replay with the same structure.  The caller owns these
+ * buffers (free them after the plan).  Library-owned workspace (per-row
+ * arrays, global tables) is allocated here and freed by destroy.
+ * With SMASH_OPT_VALIDATE set every operand is checked here (once; replays
+ * do not validate).
+ * Errors: INVALID_ARG (count < 0, a NULL pointer, A[p].cols != B[p].rows,
+ * bad cfg), INVALID_CSR, INDEX_OVERFLOW (total rows >= 2^31),
+ * OUT_OF_MEMORY, HIP. */
+smash_status smash_batch_plan_create(smash_ctx ctx, smash_dtype dtype, int32_t count, const smash_csr *A,
+                                     const smash_csr *B, const smash_batch_config *cfg, smash_alloc_fn alloc,
+                                     void *user, smash_batch_plan *out, hipStream_t stream);
+
+/* Changes the tunables of a plan (grows its workspace if needed; drops a
+ * captured graph).  Errors: INVALID_ARG, OUT_OF_MEMORY, HIP. */
+smash_status smash_batch_plan_configure(smash_batch_plan plan, const smash_batch_config *cfg, hipStream_t stream);
+smash_status smash_batch_plan_get_config(smash_batch_plan plan, smash_batch_config *cfg);
+
+/* Output pool of the plan (device pointers owned by the caller), its
+ * capacity in entries, the total row count, and row0 (host, count + 1
+ * entries, valid while the plan lives).  Any pointer argument may be NULL. */
+smash_status smash_batch_plan_outputs(smash_batch_plan plan, int64_t **C_row_ptr, int32_t **C_col_idx,
+                                      void **C_val, int64_t *capacity, int64_t *total_rows, const int64_t **row0);
+
+/* Enqueues the whole batch on `stream` (no host synchronisation, no
+ * allocation).  Results are complete when the stream reaches that point;
+ * errors detected on the device are reported by smash_batch_plan_result. */
+smash_status smash_batch_plan_run(smash_batch_plan plan, hipStream_t stream);
+
+/* Captures smash_batch_plan_run on `stream` into a graph owned by the plan
+ * (replacing a previous one); smash_batch_plan_launch replays it on any
+ * stream of the plan's device.  Errors: HIP (capture failed), NO_PLAN
+ * (launch before capture). */
+smash_status smash_batch_plan_capture(smash_batch_plan plan, hipStream_t stream);
+smash_status smash_batch_plan_launch(smash_batch_plan plan, hipStream_t stream);
+
+/* Synchronises `stream` and reports the last run: total entries, and per
+ * problem entries into nnz_per_problem (host, `count` entries) if non-NULL.
+ * Returns CAPACITY if the entries exceeded the pool (the structure changed
+ * since create; C is then incomplete), HIP on an internal inconsistency. */
+smash_status smash_batch_plan_result(smash_batch_plan plan, hipStream_t stream, int64_t *nnz_total,
+                                     int64_t *nnz_per_problem);
+
+void smash_batch_plan_destroy(smash_batch_plan plan);
+
+/* Autotuner: times smash_batch_plan_run on this plan for each candidate
+ * configuration (bin threshold, table multiplier, workgroup width,
+ * persistent grid), `reps` timed runs each after one warm-up, and
+ * configures the plan with the fastest.  With cache_path non-NULL the
+ * result is looked up first in, and afterwards appended to, a text file of
+ * lines "key lds_row_max table_shift wide_groups blocks_per_cu ms", where
+ * key describes the batch (dtype, count, rows, nnz of A and B, products);
+ * a hit configures the plan without timing.  *best (if non-NULL) receives
+ * the chosen configuration and *best_ms (if non-NULL) its mean time (0 on
+ * a cache hit).  Errors: those of run/configure; an unreadable cache is
+ * ignored, an unwritable one is INVALID_ARG. */
+smash_status smash_batch_autotune(smash_batch_plan plan, hipStream_t stream, int32_t reps, const char *cache_path,
+                                  smash_batch_config *best, double *best_ms);
+
 /* Per-kernel timing (SMASH_OPT_TIMING = 1).  For kernel index `index`
  * (0 .. smash_kernel_count()-1) returns its static name, the number of
  * launches and the summed elapsed milliseconds since the last reset.

@@ -4,7 +4,7 @@ A plain numpy float64 implementation of the MLP 6 -> 64 -> 64 -> 1 with ReLU
 hidden layers, mean-squared-error loss, hand-written backpropagation and the
 Adam update (Kingma and Ba, 2015), on the packed parameter layout of
 synthetic.MLP_LAYOUT.  Also the six per-row features the predictor reads.
-The predictor is this build's addition (the paper's nearest hook is the
+The predictor is an addition to the paper's method (its nearest hook is the
 flop-estimate work distribution of its Future Work section); its target is
 log2(1 + nnz(C_i)).
 """

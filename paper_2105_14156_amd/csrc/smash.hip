@@ -14,6 +14,7 @@
 #include "smash_kernels.hpp"
 #include "smash_mlp.hpp"
 #include "smash_fused.hpp"
+#include "smash_batch.hpp"
 
 #include <algorithm>
 #include <cstdarg>
@@ -1102,6 +1103,527 @@ smash_status smash_kernel_time_reset(smash_ctx c)
     for (int k = 0; k < K_COUNT; ++k) {
         c->launches[k] = 0;
         c->ms[k] = 0.0;
+    }
+    return SMASH_OK;
+}
+
+}  // extern "C"
+
+// ======================================================= batched launch
+
+struct smash_batch_plan_s {
+    smash_ctx c = nullptr;
+    smash_dtype dtype = SMASH_F32;
+    int count = 0;
+    long long M = 0;                     // rows of all problems
+    long long nnz_a = 0, nnz_b = 0;
+    unsigned long long products = 0;
+    smash_batch_config cfg{};
+    int ncu = 256;
+    std::vector<BatchDesc> desc;
+    std::vector<int64_t> row0;           // count + 1
+    // library-owned workspace
+    void *ws = nullptr;
+    BatchDesc *d_desc = nullptr;
+    long long *d_row0 = nullptr, *ub = nullptr, *gsz = nullptr, *goff = nullptr, *bsum = nullptr, *pnnz = nullptr;
+    int *prob = nullptr, *cap = nullptr, *nnzc = nullptr, *sym_perm = nullptr, *num_perm = nullptr, *bcount = nullptr;
+    unsigned char *sym_bin = nullptr, *num_bin = nullptr;
+    unsigned long long *bprod = nullptr;
+    int nblk = 0;
+    BatchHdr *d_hdr = nullptr, *h_hdr = nullptr;
+    int *gkeys = nullptr;
+    void *gvals = nullptr;
+    long long gcap = 0;                  // slots of gkeys / gvals
+    long long cap_total = 0;             // sum of the row bounds (pool capacity)
+    // caller-owned output pool
+    long long *crp = nullptr;
+    int *ccol = nullptr;
+    void *cval = nullptr;
+    long long ccap = 0;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+using BPlan = smash_batch_plan_s;
+
+bool batch_cfg_ok(const smash_batch_config &g)
+{
+    return g.lds_row_max >= 32 && g.lds_row_max <= 1024 && (g.table_shift == 1 || g.table_shift == 2) &&
+           g.lds_row_max <= (2048 >> g.table_shift) && (g.wide_groups == 0 || g.wide_groups == 1) &&
+           g.blocks_per_cu >= 1 && g.blocks_per_cu <= 32;
+}
+
+template <int LOGT, int WIDE>
+struct BShape {
+    static constexpr int WPR = WIDE ? (LOGT <= 8 ? 1 : 1 << (LOGT - 8)) : (LOGT <= 10 ? 1 : 1 << (LOGT - 9));
+    static constexpr int RPW = WPR == 1 ? 4 : 1;
+    static constexpr int THREADS = kWave * WPR * RPW;
+};
+
+unsigned bgrid(const BPlan &p, long long items)
+{
+    const long long g = (long long)p.cfg.blocks_per_cu * p.ncu;
+    return (unsigned)std::max<long long>(1, std::min<long long>(g, items));
+}
+
+template <typename TIn>
+void bscan(const BPlan &p, hipStream_t s, long long n, const TIn *in, long long *out, long long *total)
+{
+    const int nb = (int)blocks_for(std::max<long long>(n, 1), kScanItems);
+    k_scan_reduce<TIn><<<nb, kScanThreads, 0, s>>>(n, in, p.bsum);
+    k_scan_top<<<1, kScanThreads, 0, s>>>(nb, p.bsum, total);
+    k_scan_apply<TIn><<<nb, kScanThreads, 0, s>>>(n, in, p.bsum, total, out);
+}
+
+void bbin(const BPlan &p, hipStream_t s, const unsigned char *bin_of, BinHdr *h, int *perm, bool products)
+{
+    const int m = (int)p.M;
+    k_bin_count<<<p.nblk, 256, 0, s>>>(m, bin_of, products ? p.ub : nullptr, nullptr, p.bcount,
+                                       products ? p.bprod : nullptr, nullptr);
+    k_bin_scan<<<1, 256, 0, s>>>(p.nblk, p.bcount, products ? p.bprod : nullptr, nullptr, h,
+                                 products ? &p.d_hdr->products : nullptr);
+    k_scatter<<<p.nblk, 256, 0, s>>>(m, bin_of, p.bcount, h, perm, nullptr, nullptr);
+}
+
+// clears the header and runs the per-row analysis (graph-safe)
+void batch_analyze(const BPlan &p, hipStream_t s)
+{
+    k_fill_i32<<<1, 256, 0, s>>>((long long)(sizeof(BatchHdr) / sizeof(int)), (int *)p.d_hdr, 0);
+    k_banalyze<<<bgrid(p, blocks_for(p.M, 4)), 256, 0, s>>>(p.M, p.count, p.d_row0, p.d_desc, p.cfg.lds_row_max,
+                                                            p.cfg.table_shift, p.prob, p.ub, p.cap, p.nnzc,
+                                                            p.sym_bin, p.gsz);
+}
+
+template <int LT, int WIDE>
+void bsym_bin(const BPlan &p, hipStream_t s)
+{
+    using S = BShape<LT, WIDE>;
+    k_bsym_rows<LT, S::WPR, S::RPW><<<bgrid(p, blocks_for(p.M, S::RPW)), S::THREADS, 0, s>>>(
+        p.d_desc, p.prob, &p.d_hdr->sym, LT - kMinLogT, p.sym_perm, p.nnzc, &p.d_hdr->error);
+}
+
+template <typename V, int LT, int WIDE>
+void bnum_bin(const BPlan &p, hipStream_t s)
+{
+    using S = BShape<LT, WIDE>;
+    k_bnum_rows<V, LT, S::WPR, S::RPW><<<bgrid(p, blocks_for(p.M, S::RPW)), S::THREADS, 0, s>>>(
+        p.d_desc, p.prob, p.d_hdr, LT - kMinLogT, p.num_perm, p.ccap, p.crp, p.ccol, (V *)p.cval, &p.d_hdr->error);
+}
+
+template <int WIDE>
+void bsym_bins(const BPlan &p, hipStream_t s)
+{
+    bsym_bin<6, WIDE>(p, s);
+    bsym_bin<7, WIDE>(p, s);
+    bsym_bin<8, WIDE>(p, s);
+    bsym_bin<9, WIDE>(p, s);
+    bsym_bin<10, WIDE>(p, s);
+    bsym_bin<11, WIDE>(p, s);
+}
+
+template <typename V, int WIDE>
+void bnum_bins(const BPlan &p, hipStream_t s)
+{
+    bnum_bin<V, 6, WIDE>(p, s);
+    bnum_bin<V, 7, WIDE>(p, s);
+    bnum_bin<V, 8, WIDE>(p, s);
+    bnum_bin<V, 9, WIDE>(p, s);
+    bnum_bin<V, 10, WIDE>(p, s);
+    bnum_bin<V, 11, WIDE>(p, s);
+}
+
+template <typename V>
+void batch_numeric(const BPlan &p, hipStream_t s)
+{
+    if (p.cfg.wide_groups) bnum_bins<V, 1>(p, s);
+    else bnum_bins<V, 0>(p, s);
+    k_bnum_global<V><<<bgrid(p, p.M), kGlobalThreads, kGlobalRankBits / 8, s>>>(
+        p.d_desc, p.prob, p.d_hdr, p.num_perm, p.goff, p.gcap, p.gkeys, (V *)p.gvals, p.ccap, p.crp, p.ccol,
+        (V *)p.cval, &p.d_hdr->error);
+}
+
+// the whole batch: no host synchronisation, no allocation, no memset
+void batch_enqueue(const BPlan &p, hipStream_t s)
+{
+    if (p.M == 0) {     // nothing to compute; keeps a captured graph non-empty
+        k_fill_i32<<<1, 256, 0, s>>>((long long)(sizeof(BatchHdr) / sizeof(int)), (int *)p.d_hdr, 0);
+        return;
+    }
+    batch_analyze(p, s);
+    bbin(p, s, p.sym_bin, &p.d_hdr->sym, p.sym_perm, true);
+    bscan<long long>(p, s, p.M, p.gsz, p.goff, &p.d_hdr->gneed);
+    if (p.cfg.wide_groups) bsym_bins<1>(p, s);
+    else bsym_bins<0>(p, s);
+    k_bsym_global<<<bgrid(p, p.M), kGlobalThreads, 0, s>>>(p.d_desc, p.prob, &p.d_hdr->sym, p.sym_perm, p.cap,
+                                                           p.goff, p.gcap, p.gkeys, p.nnzc, &p.d_hdr->error);
+    bscan<int>(p, s, p.M, p.nnzc, p.crp, &p.d_hdr->nnz_c);
+    k_bcheck<<<1, 64, 0, s>>>(p.d_hdr, p.ccap);
+    k_bnum_bins<<<bgrid(p, blocks_for(p.M, 256)), 256, 0, s>>>(p.M, p.cfg.table_shift, p.nnzc, p.sym_bin,
+                                                               p.num_bin);
+    bbin(p, s, p.num_bin, &p.d_hdr->num, p.num_perm, false);
+    if (p.dtype == SMASH_F32) batch_numeric<float>(p, s);
+    else batch_numeric<double>(p, s);
+}
+
+smash_status batch_sync(BPlan &p, hipStream_t s)
+{
+    HIP_TRY(p.c, hipGetLastError());
+    HIP_TRY(p.c, hipMemcpyAsync(p.h_hdr, p.d_hdr, sizeof(BatchHdr), hipMemcpyDeviceToHost, s));
+    HIP_TRY(p.c, hipStreamSynchronize(s));
+    return SMASH_OK;
+}
+
+// sizes the global tables for the plan's configuration (analysis + scan)
+smash_status batch_size_tables(BPlan &p, hipStream_t s)
+{
+    if (p.M == 0) return SMASH_OK;
+    batch_analyze(p, s);
+    bscan<long long>(p, s, p.M, p.gsz, p.goff, &p.d_hdr->gneed);
+    TRY(batch_sync(p, s));
+    const long long need = std::max<long long>(p.h_hdr->gneed, 1);
+    if (need > p.gcap) {
+        const size_t vb = p.dtype == SMASH_F32 ? 4 : 8;
+        if (p.gkeys) (void)hipFree(p.gkeys);
+        if (p.gvals) (void)hipFree(p.gvals);
+        p.gkeys = nullptr;
+        p.gvals = nullptr;
+        p.gcap = 0;
+        if (hipMalloc((void **)&p.gkeys, (size_t)need * 4) != hipSuccess ||
+            hipMalloc(&p.gvals, (size_t)need * vb) != hipSuccess)
+            return fail(p.c, SMASH_ERR_OUT_OF_MEMORY, "global tables of %lld slots", need);
+        p.gcap = need;
+    }
+    if (p.exec) {
+        (void)hipGraphExecDestroy(p.exec);
+        p.exec = nullptr;
+    }
+    return SMASH_OK;
+}
+
+void batch_free(BPlan *p)
+{
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->ws) (void)hipFree(p->ws);
+    if (p->gkeys) (void)hipFree(p->gkeys);
+    if (p->gvals) (void)hipFree(p->gvals);
+    if (p->h_hdr) (void)hipHostFree(p->h_hdr);
+    delete p;
+}
+
+}  // namespace
+
+extern "C" {
+
+smash_status smash_batch_plan_create(smash_ctx c, smash_dtype dtype, int32_t count, const smash_csr *A,
+                                     const smash_csr *B, const smash_batch_config *cfg, smash_alloc_fn alloc,
+                                     void *user, smash_batch_plan *out, hipStream_t s)
+{
+    if (!c) return SMASH_ERR_INVALID_ARG;
+    c->err.clear();
+    if (!out || !alloc || count < 0 || (count > 0 && (!A || !B)))
+        return fail(c, SMASH_ERR_INVALID_ARG, "NULL argument or negative count");
+    *out = nullptr;
+    if (dtype != SMASH_F32 && dtype != SMASH_F64) return fail(c, SMASH_ERR_INVALID_ARG, "unknown dtype %d", (int)dtype);
+    const smash_batch_config def{1024, 1, 0, 8};
+    const smash_batch_config g = cfg ? *cfg : def;
+    if (!batch_cfg_ok(g)) return fail(c, SMASH_ERR_INVALID_ARG, "batch configuration out of range");
+    for (int q = 0; q < count; ++q) {
+        TRY(check_csr(c, &A[q], "A", true));
+        TRY(check_csr(c, &B[q], "B", true));
+        if (A[q].cols != B[q].rows)
+            return fail(c, SMASH_ERR_INVALID_ARG, "problem %d: A.cols (%lld) != B.rows (%lld)", q,
+                        (long long)A[q].cols, (long long)B[q].rows);
+    }
+    DeviceGuard dg(c->device);
+    if (!dg.ok) return fail(c, SMASH_ERR_HIP, "hipSetDevice(%d) failed", c->device);
+    BPlan *p = new (std::nothrow) BPlan();
+    if (!p) return fail(c, SMASH_ERR_OUT_OF_MEMORY, "plan");
+    p->c = c;
+    p->dtype = dtype;
+    p->count = count;
+    p->cfg = g;
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess && ncu > 0)
+        p->ncu = ncu;
+    p->row0.assign((size_t)count + 1, 0);
+    p->desc.resize((size_t)std::max(count, 1));
+    for (int q = 0; q < count; ++q) {
+        p->row0[q + 1] = p->row0[q] + A[q].rows;
+        p->nnz_a += A[q].nnz;
+        p->nnz_b += B[q].nnz;
+        p->desc[q] = BatchDesc{A[q].row_ptr, A[q].col_idx, A[q].val, B[q].row_ptr, B[q].col_idx, B[q].val,
+                               (int)A[q].rows, (int)B[q].cols, (long long)p->row0[q]};
+    }
+    p->M = p->row0[count];
+    smash_status st = SMASH_OK;
+    auto bail = [&](smash_status e) {
+        batch_free(p);
+        return e;
+    };
+    if (p->M >= (1LL << 31) - 1) return bail(fail(c, SMASH_ERR_INDEX_OVERFLOW, "batch of %lld rows", p->M));
+    const long long M = std::max<long long>(p->M, 1);
+    p->nblk = (int)blocks_for(M, kBinBlockRows);
+    const int nsb = (int)blocks_for(M, kScanItems);
+    const size_t need = carve_size({p->desc.size() * sizeof(BatchDesc), ((size_t)count + 1) * 8, (size_t)M * 4,
+                                    (size_t)M * 8, (size_t)M * 4, (size_t)M * 4, (size_t)M, (size_t)M,
+                                    (size_t)M * 8, (size_t)(M + 1) * 8, (size_t)M * 4, (size_t)M * 4,
+                                    (size_t)p->nblk * kNumBins * 4, (size_t)p->nblk * 8, (size_t)(nsb + 1) * 8,
+                                    (size_t)std::max(count, 1) * 8, sizeof(BatchHdr)});
+    if (hipMalloc(&p->ws, need) != hipSuccess) return bail(fail(c, SMASH_ERR_OUT_OF_MEMORY, "batch workspace"));
+    if (hipHostMalloc((void **)&p->h_hdr, sizeof(BatchHdr), hipHostMallocDefault) != hipSuccess)
+        return bail(fail(c, SMASH_ERR_HIP, "pinned header"));
+    Carve cv{(char *)p->ws};
+    p->d_desc = cv.take<BatchDesc>(p->desc.size());
+    p->d_row0 = cv.take<long long>((size_t)count + 1);
+    p->prob = cv.take<int>(M);
+    p->ub = cv.take<long long>(M);
+    p->cap = cv.take<int>(M);
+    p->nnzc = cv.take<int>(M);
+    p->sym_bin = cv.take<unsigned char>(M);
+    p->num_bin = cv.take<unsigned char>(M);
+    p->gsz = cv.take<long long>(M);
+    p->goff = cv.take<long long>(M + 1);
+    p->sym_perm = cv.take<int>(M);
+    p->num_perm = cv.take<int>(M);
+    p->bcount = cv.take<int>((size_t)p->nblk * kNumBins);
+    p->bprod = cv.take<unsigned long long>(p->nblk);
+    p->bsum = cv.take<long long>(nsb + 1);
+    p->pnnz = cv.take<long long>(std::max(count, 1));
+    p->d_hdr = cv.take<BatchHdr>(1);
+    if (hipMemcpyAsync(p->d_desc, p->desc.data(), p->desc.size() * sizeof(BatchDesc), hipMemcpyHostToDevice, s) !=
+            hipSuccess ||
+        hipMemcpyAsync(p->d_row0, p->row0.data(), ((size_t)count + 1) * 8, hipMemcpyHostToDevice, s) != hipSuccess)
+        return bail(fail(c, SMASH_ERR_HIP, "descriptor upload"));
+    if (c->opt[SMASH_OPT_VALIDATE] && count > 0) {
+        k_fill_i32<<<1, 256, 0, s>>>((long long)(sizeof(BatchHdr) / sizeof(int)), (int *)p->d_hdr, 0);
+        for (int q = 0; q < count; ++q) {
+            if (A[q].rows > 0 || A[q].nnz > 0)
+                k_validate<<<blocks_for(std::max<int64_t>(A[q].rows, 1), 4), 256, 0, s>>>(
+                    (int)A[q].rows, (int)A[q].cols, A[q].nnz, A[q].row_ptr, A[q].col_idx, kErrCsrA, &p->d_hdr->error);
+            if (B[q].rows > 0 || B[q].nnz > 0)
+                k_validate<<<blocks_for(std::max<int64_t>(B[q].rows, 1), 4), 256, 0, s>>>(
+                    (int)B[q].rows, (int)B[q].cols, B[q].nnz, B[q].row_ptr, B[q].col_idx, kErrCsrB, &p->d_hdr->error);
+        }
+        st = batch_sync(*p, s);
+        if (st != SMASH_OK) return bail(st);
+        if (p->h_hdr->error)
+            return bail(fail(c, SMASH_ERR_INVALID_CSR, "an operand of the batch violates the CSR preconditions"));
+    }
+    // output pool: sum over rows of min(ub, cols)
+    if (p->M > 0) {
+        batch_analyze(*p, s);
+        bscan<int>(*p, s, p->M, p->cap, p->goff, &p->d_hdr->nnz_c);
+        st = batch_sync(*p, s);
+        if (st != SMASH_OK) return bail(st);
+        p->cap_total = p->h_hdr->nnz_c;
+    }
+    st = batch_size_tables(*p, s);
+    if (st != SMASH_OK) return bail(st);
+    const size_t vb = dtype == SMASH_F32 ? 4 : 8;
+    p->ccap = p->cap_total;
+    p->crp = (long long *)alloc((size_t)(p->M + 1) * 8, user);
+    p->ccol = (int *)alloc(std::max<size_t>((size_t)p->ccap * 4, 256), user);
+    p->cval = alloc(std::max<size_t>((size_t)p->ccap * vb, 256), user);
+    if (!p->crp || !p->ccol || !p->cval) return bail(fail(c, SMASH_ERR_OUT_OF_MEMORY, "allocation callback failed"));
+    if (p->M == 0 && hipMemsetAsync(p->crp, 0, 8, s) != hipSuccess) return bail(fail(c, SMASH_ERR_HIP, "memset"));
+    // products of the batch
+    if (p->M > 0) {
+        bbin(*p, s, p->sym_bin, &p->d_hdr->sym, p->sym_perm, true);
+        st = batch_sync(*p, s);
+        if (st != SMASH_OK) return bail(st);
+        p->products = p->h_hdr->products;
+    }
+    *out = p;
+    return SMASH_OK;
+}
+
+smash_status smash_batch_plan_configure(smash_batch_plan p, const smash_batch_config *cfg, hipStream_t s)
+{
+    if (!p || !cfg) return SMASH_ERR_INVALID_ARG;
+    if (!batch_cfg_ok(*cfg)) return fail(p->c, SMASH_ERR_INVALID_ARG, "batch configuration out of range");
+    DeviceGuard dg(p->c->device);
+    if (!dg.ok) return fail(p->c, SMASH_ERR_HIP, "hipSetDevice failed");
+    p->cfg = *cfg;
+    return batch_size_tables(*p, s);
+}
+
+smash_status smash_batch_plan_get_config(smash_batch_plan p, smash_batch_config *cfg)
+{
+    if (!p || !cfg) return SMASH_ERR_INVALID_ARG;
+    *cfg = p->cfg;
+    return SMASH_OK;
+}
+
+smash_status smash_batch_plan_outputs(smash_batch_plan p, int64_t **C_row_ptr, int32_t **C_col_idx, void **C_val,
+                                      int64_t *capacity, int64_t *total_rows, const int64_t **row0)
+{
+    if (!p) return SMASH_ERR_INVALID_ARG;
+    if (C_row_ptr) *C_row_ptr = (int64_t *)p->crp;
+    if (C_col_idx) *C_col_idx = p->ccol;
+    if (C_val) *C_val = p->cval;
+    if (capacity) *capacity = p->ccap;
+    if (total_rows) *total_rows = p->M;
+    if (row0) *row0 = p->row0.data();
+    return SMASH_OK;
+}
+
+smash_status smash_batch_plan_run(smash_batch_plan p, hipStream_t s)
+{
+    if (!p) return SMASH_ERR_INVALID_ARG;
+    DeviceGuard dg(p->c->device);
+    if (!dg.ok) return fail(p->c, SMASH_ERR_HIP, "hipSetDevice failed");
+    batch_enqueue(*p, s);
+    HIP_TRY(p->c, hipGetLastError());
+    return SMASH_OK;
+}
+
+smash_status smash_batch_plan_capture(smash_batch_plan p, hipStream_t s)
+{
+    if (!p) return SMASH_ERR_INVALID_ARG;
+    DeviceGuard dg(p->c->device);
+    if (!dg.ok) return fail(p->c, SMASH_ERR_HIP, "hipSetDevice failed");
+    if (p->exec) {
+        (void)hipGraphExecDestroy(p->exec);
+        p->exec = nullptr;
+    }
+    hipGraph_t graph = nullptr;
+    HIP_TRY(p->c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    batch_enqueue(*p, s);
+    const hipError_t launch_err = hipGetLastError();
+    HIP_TRY(p->c, hipStreamEndCapture(s, &graph));
+    if (launch_err != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return fail(p->c, SMASH_ERR_HIP, "launch during capture: %s", hipGetErrorString(launch_err));
+    }
+    const hipError_t e = hipGraphInstantiate(&p->exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        p->exec = nullptr;
+        return fail(p->c, SMASH_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    return SMASH_OK;
+}
+
+smash_status smash_batch_plan_launch(smash_batch_plan p, hipStream_t s)
+{
+    if (!p) return SMASH_ERR_INVALID_ARG;
+    if (!p->exec) return fail(p->c, SMASH_ERR_NO_PLAN, "no captured graph on this plan");
+    DeviceGuard dg(p->c->device);
+    if (!dg.ok) return fail(p->c, SMASH_ERR_HIP, "hipSetDevice failed");
+    HIP_TRY(p->c, hipGraphLaunch(p->exec, s));
+    return SMASH_OK;
+}
+
+smash_status smash_batch_plan_result(smash_batch_plan p, hipStream_t s, int64_t *nnz_total, int64_t *nnz_per_problem)
+{
+    if (!p) return SMASH_ERR_INVALID_ARG;
+    DeviceGuard dg(p->c->device);
+    if (!dg.ok) return fail(p->c, SMASH_ERR_HIP, "hipSetDevice failed");
+    if (p->M == 0) {
+        if (nnz_total) *nnz_total = 0;
+        if (nnz_per_problem)
+            for (int q = 0; q < p->count; ++q) nnz_per_problem[q] = 0;
+        return SMASH_OK;
+    }
+    if (nnz_per_problem && p->count > 0) {
+        k_bproblem_nnz<<<blocks_for(p->count, 256), 256, 0, s>>>(p->count, p->d_row0, p->crp, p->pnnz);
+        HIP_TRY(p->c, hipMemcpyAsync(nnz_per_problem, p->pnnz, (size_t)p->count * 8, hipMemcpyDeviceToHost, s));
+    }
+    TRY(batch_sync(*p, s));
+    const int e = p->h_hdr->error;
+    if (nnz_total) *nnz_total = p->h_hdr->nnz_c;
+    if (e & kErrCapacity)
+        return fail(p->c, SMASH_ERR_CAPACITY, "the batch needs %lld entries (or more global table slots) beyond "
+                    "the plan's pool of %lld", (long long)p->h_hdr->nnz_c, p->ccap);
+    if (e) return fail(p->c, SMASH_ERR_HIP, "internal inconsistency (device error flags 0x%x)", e);
+    return SMASH_OK;
+}
+
+void smash_batch_plan_destroy(smash_batch_plan p)
+{
+    if (!p) return;
+    DeviceGuard dg(p->c->device);
+    batch_free(p);
+}
+
+smash_status smash_batch_autotune(smash_batch_plan p, hipStream_t s, int32_t reps, const char *cache_path,
+                                  smash_batch_config *best, double *best_ms)
+{
+    if (!p || reps < 1) return SMASH_ERR_INVALID_ARG;
+    DeviceGuard dg(p->c->device);
+    if (!dg.ok) return fail(p->c, SMASH_ERR_HIP, "hipSetDevice failed");
+    char key[256];
+    snprintf(key, sizeof key, "%s:%d:%lld:%lld:%lld:%llu", p->dtype == SMASH_F32 ? "f32" : "f64", p->count, p->M,
+             p->nnz_a, p->nnz_b, p->products);
+    if (cache_path) {
+        if (FILE *f = fopen(cache_path, "r")) {
+            char k[256];
+            smash_batch_config g{};
+            double ms = 0;
+            bool hit = false;
+            smash_batch_config found{};
+            while (fscanf(f, "%255s %d %d %d %d %lf", k, &g.lds_row_max, &g.table_shift, &g.wide_groups,
+                          &g.blocks_per_cu, &ms) == 6)
+                if (strcmp(k, key) == 0 && batch_cfg_ok(g)) {
+                    found = g;
+                    hit = true;
+                }
+            fclose(f);
+            if (hit) {
+                TRY(smash_batch_plan_configure(p, &found, s));
+                if (best) *best = found;
+                if (best_ms) *best_ms = 0.0;
+                return SMASH_OK;
+            }
+        }
+    }
+    std::vector<smash_batch_config> cands;
+    for (int lrm : {256, 512, 1024})
+        for (int sh : {1, 2})
+            for (int wide : {0, 1})
+                for (int bpc : {4, 16}) {
+                    const smash_batch_config g{lrm, sh, wide, bpc};
+                    if (batch_cfg_ok(g)) cands.push_back(g);
+                }
+    hipEvent_t e0, e1;
+    HIP_TRY(p->c, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(p->c, SMASH_ERR_HIP, "hipEventCreate");
+    }
+    smash_status st = SMASH_OK;
+    double top = 1e300;
+    smash_batch_config win = p->cfg;
+    for (const smash_batch_config &g : cands) {
+        st = smash_batch_plan_configure(p, &g, s);
+        if (st != SMASH_OK) break;
+        batch_enqueue(*p, s);                      // warm-up
+        (void)hipEventRecord(e0, s);
+        for (int r = 0; r < reps; ++r) batch_enqueue(*p, s);
+        (void)hipEventRecord(e1, s);
+        st = smash_batch_plan_result(p, s, nullptr, nullptr);
+        if (st != SMASH_OK) break;
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        const double per = ms / reps;
+        if (per < top) {
+            top = per;
+            win = g;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != SMASH_OK) return st;
+    TRY(smash_batch_plan_configure(p, &win, s));
+    if (best) *best = win;
+    if (best_ms) *best_ms = top;
+    if (cache_path) {
+        FILE *f = fopen(cache_path, "a");
+        if (!f) return fail(p->c, SMASH_ERR_INVALID_ARG, "cannot append to %s", cache_path);
+        fprintf(f, "%s %d %d %d %d %.6f\n", key, win.lds_row_max, win.table_shift, win.wide_groups,
+                win.blocks_per_cu, top);
+        fclose(f);
     }
     return SMASH_OK;
 }

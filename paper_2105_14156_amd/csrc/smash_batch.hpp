@@ -1,0 +1,241 @@
+// smash_batch.hpp -- kernels of the batched launch: many independent
+// products C_p = A_p * B_p run as one pipeline over the concatenated row
+// space of all problems.
+//
+// Global row g of the batch is row g - row0[p] of problem p.  Every kernel
+// has a fixed grid (sized from the batch's row count or the machine), reads
+// the bin sizes it needs from device memory and loops over its work items,
+// so the whole sequence can be captured once in a graph and replayed with no
+// host synchronisation: analysis, binning, symbolic per bin, one row-pointer
+// scan over the batch (each C_p lands at a device-computed offset of one
+// output pool), numeric per bin.  Rows whose bound exceeds the LDS limit use
+// per-row tables in global memory.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "smash_kernels.hpp"
+
+namespace smash {
+
+struct BatchDesc {
+    const int *Arp, *Acol;
+    const void *Aval;
+    const int *Brp, *Bcol;
+    const void *Bval;
+    int rows, cols;
+    long long row0;             // first global row of the problem
+};
+
+struct BatchHdr {
+    BinHdr sym, num;
+    unsigned long long products;
+    long long nnz_c;            // total entries of all C_p
+    long long gneed;            // global table slots of the heavy rows
+    int error;
+    int pad;
+};
+
+enum : int { kErrCapacity = 16 };
+
+// Table size class of a row bound: 2^LOGT >= bound << shift slots.
+__device__ __forceinline__ int lds_bin_shift(long long bound, int shift)
+{
+    int lt = ceil_log2(bound << shift);
+    return (lt < kMinLogT ? kMinLogT : lt) - kMinLogT;
+}
+
+// Per global row: its problem, products ub, bound cap = min(ub, cols), bin
+// (empty, LDS by cap << shift, or heavy above lds_row_max) and, for heavy
+// rows, its global table size.  One wave per row, grid-stride.
+__global__ __launch_bounds__(256) void k_banalyze(long long M, int count, const long long *__restrict__ row0s,
+                                                  const BatchDesc *__restrict__ desc, int lds_row_max, int shift,
+                                                  int *__restrict__ prob, long long *__restrict__ ub_out,
+                                                  int *__restrict__ cap_out, int *__restrict__ nnzc,
+                                                  unsigned char *__restrict__ bin_out, long long *__restrict__ gsz)
+{
+    const int lane = lane_id();
+    for (long long g = (long long)blockIdx.x * 4 + threadIdx.x / kWave; g < M; g += (long long)gridDim.x * 4) {
+        int lo = 0, hi = count;     // row0s[lo] <= g < row0s[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (row0s[mid] <= g) lo = mid;
+            else hi = mid;
+        }
+        const BatchDesc &d = desc[lo];
+        const int row = (int)(g - d.row0);
+        const int e0 = d.Arp[row], e1 = d.Arp[row + 1];
+        long long ub = 0;
+        for (int e = e0 + lane; e < e1; e += kWave) {
+            const int k = d.Acol[e];
+            ub += d.Brp[k + 1] - d.Brp[k];
+        }
+        ub = wave_sum(ub);
+        if (lane == 0) {
+            const int cap = (int)(ub < d.cols ? ub : d.cols);
+            int b = kBinEmpty;
+            if (ub > 0) {
+                b = cap > lds_row_max ? kBinHeavy : lds_bin_shift(cap, shift);
+                if (b >= kLdsBins) b = kBinHeavy;
+            }
+            prob[g] = lo;
+            ub_out[g] = ub;
+            cap_out[g] = cap;
+            nnzc[g] = 0;
+            bin_out[g] = (unsigned char)b;
+            gsz[g] = b == kBinHeavy ? 1LL << gtable_log2(cap) : 0;
+        }
+    }
+}
+
+// Numeric bins from the exact counts: heavy rows stay heavy, rows without
+// entries drop out, LDS rows take the class of their count.
+__global__ __launch_bounds__(256) void k_bnum_bins(long long M, int shift, const int *__restrict__ nnzc,
+                                                   const unsigned char *__restrict__ sym_bin,
+                                                   unsigned char *__restrict__ num_bin)
+{
+    for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < M;
+         g += (long long)gridDim.x * blockDim.x) {
+        const int b = sym_bin[g], nc = nnzc[g];
+        num_bin[g] = (unsigned char)(b == kBinHeavy ? kBinHeavy
+                                                    : (b == kBinEmpty || nc == 0 ? kBinEmpty : lds_bin_shift(nc, shift)));
+    }
+}
+
+// Symbolic, LDS bin `bin`: RPW rows of WPR waves per work item.
+template <int LOGT, int WPR, int RPW>
+__global__ __launch_bounds__(kWave *WPR *RPW) void k_bsym_rows(const BatchDesc *__restrict__ desc,
+                                                               const int *__restrict__ prob, const BinHdr *h, int bin,
+                                                               const int *__restrict__ perm, int *__restrict__ nnzc,
+                                                               int *err)
+{
+    static_assert(RPW == 1 || WPR == 1, "multi-row blocks use one wave per row");
+    constexpr int G = WPR * kWave;
+    __shared__ int s_keys[RPW][1 << LOGT];
+    __shared__ EnumScratch<float, G> s_en[RPW];
+    __shared__ int s_cnt[RPW];
+    const int cnt = h->count[bin];
+    const int *rows = perm + h->offset[bin];
+    const int g = threadIdx.x / kWave / WPR;
+    const int gt = threadIdx.x - g * G;
+    for (int base = blockIdx.x * RPW; base < cnt; base += gridDim.x * RPW) {
+        const int r = base + g;
+        const bool active = r < cnt;
+        const int grow = active ? rows[r] : 0;
+        const BatchDesc &d = desc[active ? prob[grow] : 0];
+        sym_row<LOGT, WPR>(d.Arp, d.Acol, d.Brp, d.Bcol, (int)(grow - d.row0), active, gt, s_keys[g], s_en[g],
+                           &s_cnt[g], &nnzc[grow], err);
+        group_sync<WPR>();
+    }
+}
+
+// Numeric, LDS bin `bin`.  Does nothing when the output pool is too small
+// (the capacity check has then flagged the batch).
+template <typename V, int LOGT, int WPR, int RPW>
+__global__ __launch_bounds__(kWave *WPR *RPW) void k_bnum_rows(const BatchDesc *__restrict__ desc,
+                                                               const int *__restrict__ prob, const BatchHdr *bh,
+                                                               int bin, const int *__restrict__ perm,
+                                                               long long ccap, const long long *__restrict__ Crp,
+                                                               int *__restrict__ Ccol, V *__restrict__ Cval, int *err)
+{
+    static_assert(RPW == 1 || WPR == 1, "multi-row blocks use one wave per row");
+    constexpr int T = 1 << LOGT;
+    constexpr int G = WPR * kWave;
+    __shared__ int s_keys[RPW][T];
+    __shared__ double s_vals[RPW][T];
+    __shared__ EnumScratch<V, G> s_en[RPW];
+    __shared__ int s_scan[RPW][WPR + 1];
+    if (bh->nnz_c > ccap) return;
+    const int cnt = bh->num.count[bin];
+    const int *rows = perm + bh->num.offset[bin];
+    const int g = threadIdx.x / kWave / WPR;
+    const int gt = threadIdx.x - g * G;
+    for (int base = blockIdx.x * RPW; base < cnt; base += gridDim.x * RPW) {
+        const int r = base + g;
+        const bool active = r < cnt;
+        const int grow = active ? rows[r] : 0;
+        const BatchDesc &d = desc[active ? prob[grow] : 0];
+        num_row<V, LOGT, WPR>(d.Arp, d.Acol, (const V *)d.Aval, d.Brp, d.Bcol, (const V *)d.Bval,
+                              (int)(grow - d.row0), grow, active, gt, s_keys[g], s_vals[g], s_en[g], s_scan[g], Crp,
+                              Ccol, Cval, err);
+        group_sync<WPR>();
+    }
+}
+
+// Symbolic, heavy rows: one block per row, key table at goff[row] in the
+// global pool (cleared here; gcap slots in all).
+__global__ __launch_bounds__(kGlobalThreads) void k_bsym_global(const BatchDesc *__restrict__ desc,
+                                                                const int *__restrict__ prob, const BinHdr *h,
+                                                                const int *__restrict__ perm,
+                                                                const int *__restrict__ cap,
+                                                                const long long *__restrict__ goff, long long gcap,
+                                                                int *gkeys, int *__restrict__ nnzc, int *err)
+{
+    __shared__ EnumScratch<float, kGlobalThreads> S;
+    __shared__ int s_cnt;
+    const int cnt = h->count[kBinHeavy];
+    const int *rows = perm + h->offset[kBinHeavy];
+    for (int r = blockIdx.x; r < cnt; r += gridDim.x) {
+        const int grow = rows[r];
+        const long long off = goff[grow];
+        const int T = 1 << gtable_log2(cap[grow]);
+        if (off + T > gcap) {
+            if (threadIdx.x == 0) atomicOr(err, kErrCapacity);
+            continue;
+        }
+        int *keys = gkeys + off;
+        for (int t = threadIdx.x; t < T; t += kGlobalThreads) keys[t] = kEmpty;
+        __threadfence();
+        __syncthreads();
+        const BatchDesc &d = desc[prob[grow]];
+        sym_global_row(d.Arp, d.Acol, d.Brp, d.Bcol, (int)(grow - d.row0), cap[grow], keys, S, &s_cnt, &nnzc[grow],
+                       err);
+        __syncthreads();
+    }
+}
+
+// Numeric, heavy rows: one block per row (dynamic LDS: the rank bitmap).
+template <typename V>
+__global__ __launch_bounds__(kGlobalThreads) void k_bnum_global(const BatchDesc *__restrict__ desc,
+                                                                const int *__restrict__ prob, const BatchHdr *bh,
+                                                                const int *__restrict__ perm,
+                                                                const long long *__restrict__ goff, long long gcap,
+                                                                int *gkeys, V *gvals, long long ccap,
+                                                                const long long *__restrict__ Crp,
+                                                                int *__restrict__ Ccol, V *__restrict__ Cval, int *err)
+{
+    extern __shared__ unsigned s_bm[];
+    __shared__ GlobalNumLds<V> L;
+    if (bh->nnz_c > ccap) return;
+    const int cnt = bh->num.count[kBinHeavy];
+    const int *rows = perm + bh->num.offset[kBinHeavy];
+    for (int r = blockIdx.x; r < cnt; r += gridDim.x) {
+        const int grow = rows[r];
+        const long long off = goff[grow];
+        const int nc = (int)(Crp[grow + 1] - Crp[grow]);
+        if (off + (1LL << gtable_log2(nc)) > gcap) {
+            if (threadIdx.x == 0) atomicOr(err, kErrCapacity);
+            continue;
+        }
+        const BatchDesc &d = desc[prob[grow]];
+        num_global_row<V>(d.Arp, d.Acol, (const V *)d.Aval, d.Brp, d.Bcol, (const V *)d.Bval, (int)(grow - d.row0),
+                          grow, d.cols, gkeys + off, gvals + off, L, s_bm, Crp, Ccol, Cval, err);
+        __syncthreads();
+    }
+}
+
+// Flags a batch whose entries exceed the output pool.
+__global__ void k_bcheck(BatchHdr *bh, long long ccap)
+{
+    if (threadIdx.x == 0 && bh->nnz_c > ccap) atomicOr(&bh->error, kErrCapacity);
+}
+
+// Entries of each problem: nnz[p] = Crp[row0[p + 1]] - Crp[row0[p]].
+__global__ __launch_bounds__(256) void k_bproblem_nnz(int count, const long long *__restrict__ row0s,
+                                                      const long long *__restrict__ Crp, long long *__restrict__ nnz)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < count) nnz[p] = Crp[row0s[p + 1]] - Crp[row0s[p]];
+}
+
+}  // namespace smash

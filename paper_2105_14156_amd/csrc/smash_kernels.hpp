@@ -561,35 +561,25 @@ __global__ __launch_bounds__(256) void k_scatter(int m, const unsigned char *__r
 
 // ------------------------------------------------------- symbolic, LDS hash
 
-// Light rows: one row per group of WPR waves (RPW groups per block; RPW > 1
-// only with WPR = 1).  Counts the distinct columns of each row with an LDS
-// key table of 2^LOGT slots (step a3).
-template <int LOGT, int WPR, int RPW>
-__global__ __launch_bounds__(kWave *WPR *RPW) void k_sym_rows(const int *__restrict__ Arp, const int *__restrict__ Acol,
-                                                              const int *__restrict__ Brp, const int *__restrict__ Bcol,
-                                                              const int *__restrict__ rows, int nrows,
-                                                              int *__restrict__ nnzc, int *err)
+// Symbolic count of one light row by a group of WPR waves (gt: thread index
+// in the group; every thread of the group calls it): the distinct columns of
+// A row `arow` times B, counted in an LDS key table of 2^LOGT slots (step
+// a3), are stored to *out by the group's first thread.
+template <int LOGT, int WPR>
+__device__ __forceinline__ void sym_row(const int *__restrict__ Arp, const int *__restrict__ Acol,
+                                        const int *__restrict__ Brp, const int *__restrict__ Bcol, int arow,
+                                        bool active, int gt, int *keys, EnumScratch<float, WPR * kWave> &en,
+                                        int *s_cnt, int *out, int *err)
 {
-    static_assert(RPW == 1 || WPR == 1, "multi-row blocks use one wave per row");
     constexpr int T = 1 << LOGT;
     constexpr int G = WPR * kWave;
-    __shared__ int s_keys[RPW][T];
-    __shared__ EnumScratch<float, G> s_en[RPW];
-    __shared__ int s_cnt[RPW];
-    const int lane = lane_id(), wave = threadIdx.x / kWave;
-    const int g = wave / WPR;
-    const int gt = threadIdx.x - g * G;
-    const int r = blockIdx.x * RPW + g;
-    const bool active = r < nrows;
-    const int row = active ? rows[r] : 0;
-    int *keys = s_keys[g];
     for (int t = gt; t < T; t += G) keys[t] = kEmpty;
-    if (gt == 0) s_cnt[g] = 0;
+    if (gt == 0) *s_cnt = 0;
     group_sync<WPR>();
     int mine = 0;
     if (active) {
         group_products<float, false, G, 4>(
-            Arp[row], Arp[row + 1], gt, s_en[g], Bcol, (const float *)nullptr,
+            Arp[arow], Arp[arow + 1], gt, en, Bcol, (const float *)nullptr,
             [&](int e, int &bs, int &bl, float &) {
                 const int k = Acol[e];
                 bs = Brp[k];
@@ -598,9 +588,30 @@ __global__ __launch_bounds__(kWave *WPR *RPW) void k_sym_rows(const int *__restr
             [&](int j) { mine += lds_insert_key(keys, LOGT, j, err); });
     }
     mine = wave_sum(mine);
-    if (lane == 0 && mine) atomicAdd(&s_cnt[g], mine);
+    if (lane_id() == 0 && mine) atomicAdd(s_cnt, mine);
     group_sync<WPR>();
-    if (active && gt == 0) nnzc[row] = s_cnt[g];
+    if (active && gt == 0) *out = *s_cnt;
+}
+
+// Light rows: one row per group of WPR waves (RPW groups per block; RPW > 1
+// only with WPR = 1).
+template <int LOGT, int WPR, int RPW>
+__global__ __launch_bounds__(kWave *WPR *RPW) void k_sym_rows(const int *__restrict__ Arp, const int *__restrict__ Acol,
+                                                              const int *__restrict__ Brp, const int *__restrict__ Bcol,
+                                                              const int *__restrict__ rows, int nrows,
+                                                              int *__restrict__ nnzc, int *err)
+{
+    static_assert(RPW == 1 || WPR == 1, "multi-row blocks use one wave per row");
+    constexpr int G = WPR * kWave;
+    __shared__ int s_keys[RPW][1 << LOGT];
+    __shared__ EnumScratch<float, G> s_en[RPW];
+    __shared__ int s_cnt[RPW];
+    const int g = threadIdx.x / kWave / WPR;
+    const int gt = threadIdx.x - g * G;
+    const int r = blockIdx.x * RPW + g;
+    const bool active = r < nrows;
+    const int row = active ? rows[r] : 0;
+    sym_row<LOGT, WPR>(Arp, Acol, Brp, Bcol, row, active, gt, s_keys[g], s_en[g], &s_cnt[g], &nnzc[row], err);
 }
 
 // -------------------------------------------------------- numeric, LDS hash
@@ -631,33 +642,23 @@ __device__ __forceinline__ void group_bitonic(int *keys, V *vals, int n2, int gt
     }
 }
 
-// Light rows (steps a5 and a7): products merged in an LDS tag/value table of
-// 2^LOGT slots, then the occupied slots compacted, sorted by column and
-// written at the row's offset in C.
-template <typename V, int LOGT, int WPR, int RPW>
-__global__ __launch_bounds__(kWave *WPR *RPW) void k_num_rows(
-    const int *__restrict__ Arp, const int *__restrict__ Acol, const V *__restrict__ Aval,
-    const int *__restrict__ Brp, const int *__restrict__ Bcol, const V *__restrict__ Bval,
-    const int *__restrict__ rows, int nrows, const long long *__restrict__ Crp, int *__restrict__ Ccol,
-    V *__restrict__ Cval, int *err)
+// Numeric pass of one light row by a group of WPR waves (steps a5 and a7):
+// the products of A row `arow` times B merged in an LDS tag/value table of
+// 2^LOGT slots, the occupied slots compacted, sorted by column and written
+// at C's row `crow`.
+template <typename V, int LOGT, int WPR>
+__device__ __forceinline__ void num_row(const int *__restrict__ Arp, const int *__restrict__ Acol,
+                                        const V *__restrict__ Aval, const int *__restrict__ Brp,
+                                        const int *__restrict__ Bcol, const V *__restrict__ Bval, int arow,
+                                        long long crow, bool active, int gt, int *keys, double *vals,
+                                        EnumScratch<V, WPR * kWave> &en, int *s_scan, const long long *__restrict__ Crp,
+                                        int *__restrict__ Ccol, V *__restrict__ Cval, int *err)
 {
-    static_assert(RPW == 1 || WPR == 1, "multi-row blocks use one wave per row");
     constexpr int T = 1 << LOGT;
     constexpr int G = WPR * kWave;
     constexpr int SPT = T / G;          // slots per thread in the compaction
     static_assert(SPT >= 1, "table smaller than its group");
-    __shared__ int s_keys[RPW][T];
-    __shared__ double s_vals[RPW][T];
-    __shared__ EnumScratch<V, G> s_en[RPW];
-    __shared__ int s_scan[RPW][WPR + 1];
-    const int lane = lane_id(), wave = threadIdx.x / kWave;
-    const int g = wave / WPR, wg = wave % WPR;
-    const int gt = threadIdx.x - g * G;
-    const int r = blockIdx.x * RPW + g;
-    const bool active = r < nrows;
-    const int row = active ? rows[r] : 0;
-    int *keys = s_keys[g];
-    double *vals = s_vals[g];
+    const int lane = lane_id(), wg = gt / kWave;
     for (int t = gt; t < T; t += G) {
         keys[t] = kEmpty;
         vals[t] = 0.0;
@@ -665,7 +666,7 @@ __global__ __launch_bounds__(kWave *WPR *RPW) void k_num_rows(
     group_sync<WPR>();
     if (active) {
         group_products<V, true, G, 4>(
-            Arp[row], Arp[row + 1], gt, s_en[g], Bcol, Bval,
+            Arp[arow], Arp[arow + 1], gt, en, Bcol, Bval,
             [&](int e, int &bs, int &bl, V &a) {
                 const int k = Acol[e];
                 bs = Brp[k];
@@ -686,11 +687,11 @@ __global__ __launch_bounds__(kWave *WPR *RPW) void k_num_rows(
         cnt += kr[s] != kEmpty;
     }
     const int incl = wave_incl_scan(cnt);
-    if (lane == kWave - 1) s_scan[g][wg] = incl;
+    if (lane == kWave - 1) s_scan[wg] = incl;
     group_sync<WPR>();
     int wbase = 0, total = 0;
     for (int w = 0; w < WPR; ++w) {
-        const int t = s_scan[g][w];
+        const int t = s_scan[w];
         if (w < wg) wbase += t;
         total += t;
     }
@@ -709,8 +710,8 @@ __global__ __launch_bounds__(kWave *WPR *RPW) void k_num_rows(
     group_sync<WPR>();
     group_bitonic<double, WPR>(keys, vals, n2, gt);
     if (active) {
-        const long long rb = Crp[row];
-        const int nc = (int)(Crp[row + 1] - rb);
+        const long long rb = Crp[crow];
+        const int nc = (int)(Crp[crow + 1] - rb);
         if (gt == 0 && nc != total) atomicOr(err, kErrCount);
         const int nw = total < nc ? total : nc;
         for (int t = gt; t < nw; t += G) {
@@ -718,6 +719,30 @@ __global__ __launch_bounds__(kWave *WPR *RPW) void k_num_rows(
             store_c(&Cval[rb + t], (V)vals[t]);
         }
     }
+}
+
+// Light rows: one row per group of WPR waves (RPW groups per block).
+template <typename V, int LOGT, int WPR, int RPW>
+__global__ __launch_bounds__(kWave *WPR *RPW) void k_num_rows(
+    const int *__restrict__ Arp, const int *__restrict__ Acol, const V *__restrict__ Aval,
+    const int *__restrict__ Brp, const int *__restrict__ Bcol, const V *__restrict__ Bval,
+    const int *__restrict__ rows, int nrows, const long long *__restrict__ Crp, int *__restrict__ Ccol,
+    V *__restrict__ Cval, int *err)
+{
+    static_assert(RPW == 1 || WPR == 1, "multi-row blocks use one wave per row");
+    constexpr int T = 1 << LOGT;
+    constexpr int G = WPR * kWave;
+    __shared__ int s_keys[RPW][T];
+    __shared__ double s_vals[RPW][T];
+    __shared__ EnumScratch<V, G> s_en[RPW];
+    __shared__ int s_scan[RPW][WPR + 1];
+    const int g = threadIdx.x / kWave / WPR;
+    const int gt = threadIdx.x - g * G;
+    const int r = blockIdx.x * RPW + g;
+    const bool active = r < nrows;
+    const int row = active ? rows[r] : 0;
+    num_row<V, LOGT, WPR>(Arp, Acol, Aval, Brp, Bcol, Bval, row, row, active, gt, s_keys[g], s_vals[g], s_en[g],
+                          s_scan[g], Crp, Ccol, Cval, err);
 }
 
 // ---------------------------------------------------------------- row scan
@@ -1202,24 +1227,20 @@ __global__ __launch_bounds__(256) void k_fill_i32(long long n, int *__restrict__
 
 constexpr int kGlobalThreads = 1024;
 
-// Symbolic phase of heavy rows in global mode: one block per row inserts the
-// row's columns in its global key table (device-scope CAS) and counts them.
-__global__ __launch_bounds__(kGlobalThreads) void k_sym_global(
-    const int *__restrict__ Arp, const int *__restrict__ Acol, const int *__restrict__ Brp,
-    const int *__restrict__ Bcol, const int *__restrict__ rows, const int *__restrict__ cap,
-    const long long *__restrict__ goff, int *gkeys, int *__restrict__ nnzc, int *err)
+// Symbolic count of one heavy row in global mode by a whole block: the row's
+// columns are inserted in its global key table of next_pow2(2 cap) slots
+// (device-scope CAS; the table must hold kEmpty) and counted into *out.
+__device__ __forceinline__ void sym_global_row(const int *__restrict__ Arp, const int *__restrict__ Acol,
+                                               const int *__restrict__ Brp, const int *__restrict__ Bcol, int arow,
+                                               int cap, int *keys, EnumScratch<float, kGlobalThreads> &S, int *s_cnt,
+                                               int *out, int *err)
 {
-    __shared__ EnumScratch<float, kGlobalThreads> S;
-    __shared__ int s_cnt;
-    const int lane = lane_id();
-    const int row = rows[blockIdx.x];
-    const int logT = gtable_log2(cap[row]);
+    const int logT = gtable_log2(cap);
     const unsigned mask = (1u << logT) - 1;
-    int *keys = gkeys + goff[blockIdx.x];
-    if (threadIdx.x == 0) s_cnt = 0;
+    if (threadIdx.x == 0) *s_cnt = 0;
     int mine = 0;
     group_products<float, false, kGlobalThreads, 2>(
-        Arp[row], Arp[row + 1], threadIdx.x, S, Bcol, (const float *)nullptr,
+        Arp[arow], Arp[arow + 1], threadIdx.x, S, Bcol, (const float *)nullptr,
         [&](int e, int &bs, int &bl, float &) {
             const int k = Acol[e];
             bs = Brp[k];
@@ -1241,38 +1262,52 @@ __global__ __launch_bounds__(kGlobalThreads) void k_sym_global(
         });
     __syncthreads();
     mine = wave_sum(mine);
-    if (lane == 0 && mine) atomicAdd(&s_cnt, mine);
+    if (lane_id() == 0 && mine) atomicAdd(s_cnt, mine);
     __syncthreads();
-    if (threadIdx.x == 0) nnzc[row] = s_cnt;
+    if (threadIdx.x == 0) *out = *s_cnt;
 }
 
-// Numeric phase of heavy rows in global mode: one block per row clears its
-// global tag/value table, merges the row's products into it with
+// Symbolic phase of heavy rows in global mode: one block per row.
+__global__ __launch_bounds__(kGlobalThreads) void k_sym_global(
+    const int *__restrict__ Arp, const int *__restrict__ Acol, const int *__restrict__ Brp,
+    const int *__restrict__ Bcol, const int *__restrict__ rows, const int *__restrict__ cap,
+    const long long *__restrict__ goff, int *gkeys, int *__restrict__ nnzc, int *err)
+{
+    __shared__ EnumScratch<float, kGlobalThreads> S;
+    __shared__ int s_cnt;
+    const int row = rows[blockIdx.x];
+    sym_global_row(Arp, Acol, Brp, Bcol, row, cap[row], gkeys + goff[blockIdx.x], S, &s_cnt, &nnzc[row], err);
+}
+
+// Numeric pass of one heavy row in global mode by a whole block: clears the
+// row's global tag/value table, merges the row's products into it with
 // device-scope CAS and atomic add, then writes the entries in column order
-// (rank from an LDS bitmap over column windows of kGlobalRankBits).
+// at C's row `crow` (rank from an LDS bitmap over column windows of
+// kGlobalRankBits; s_bm is the block's dynamic LDS).
 constexpr int kGlobalRankBits = 1 << 19;
 
 template <typename V>
-__global__ __launch_bounds__(kGlobalThreads) void k_num_global(
-    const int *__restrict__ Arp, const int *__restrict__ Acol, const V *__restrict__ Aval,
-    const int *__restrict__ Brp, const int *__restrict__ Bcol, const V *__restrict__ Bval,
-    const int *__restrict__ rows, int ncols, const long long *__restrict__ goff, int *gkeys, V *gvals,
-    const long long *__restrict__ Crp, int *__restrict__ Ccol, V *__restrict__ Cval, int *err)
+struct GlobalNumLds {
+    EnumScratch<V, kGlobalThreads> S;
+    long long tmp[kGlobalThreads / kWave + 1];
+    int base[kGlobalThreads];
+};
+
+template <typename V>
+__device__ __forceinline__ void num_global_row(const int *__restrict__ Arp, const int *__restrict__ Acol,
+                                               const V *__restrict__ Aval, const int *__restrict__ Brp,
+                                               const int *__restrict__ Bcol, const V *__restrict__ Bval, int arow,
+                                               long long crow, int ncols, int *keys, V *vals, GlobalNumLds<V> &L,
+                                               unsigned *s_bm, const long long *__restrict__ Crp,
+                                               int *__restrict__ Ccol, V *__restrict__ Cval, int *err)
 {
     constexpr int WORDS = kGlobalRankBits / 32;
     constexpr int WPT = WORDS / kGlobalThreads;
-    extern __shared__ unsigned s_bm[];                     // [WORDS]
-    __shared__ EnumScratch<V, kGlobalThreads> S;
-    __shared__ long long s_tmp[kGlobalThreads / kWave + 1];
-    __shared__ int s_base[kGlobalThreads];
-    const int row = rows[blockIdx.x];
-    const long long rb = Crp[row];
-    const int nc = (int)(Crp[row + 1] - rb);
+    const long long rb = Crp[crow];
+    const int nc = (int)(Crp[crow + 1] - rb);
     const int logT = gtable_log2(nc);
     const int T = 1 << logT;
     const unsigned mask = (unsigned)T - 1;
-    int *keys = gkeys + goff[blockIdx.x];
-    V *vals = gvals + goff[blockIdx.x];
     for (int t = threadIdx.x; t < T; t += kGlobalThreads) {
         keys[t] = kEmpty;
         vals[t] = V(0);
@@ -1280,7 +1315,7 @@ __global__ __launch_bounds__(kGlobalThreads) void k_num_global(
     __threadfence();
     __syncthreads();
     group_products<V, true, kGlobalThreads, 2>(
-        Arp[row], Arp[row + 1], threadIdx.x, S, Bcol, Bval,
+        Arp[arow], Arp[arow + 1], threadIdx.x, L.S, Bcol, Bval,
         [&](int e, int &bs, int &bl, V &a) {
             const int k = Acol[e];
             bs = Brp[k];
@@ -1319,14 +1354,14 @@ __global__ __launch_bounds__(kGlobalThreads) void k_num_global(
         int pc = 0;
         for (int q = 0; q < WPT; ++q) pc += __popc(s_bm[threadIdx.x * WPT + q]);
         long long tot;
-        const long long ex = block_excl_scan<long long, kGlobalThreads>((long long)pc, s_tmp, tot);
-        s_base[threadIdx.x] = (int)ex;
+        const long long ex = block_excl_scan<long long, kGlobalThreads>((long long)pc, L.tmp, tot);
+        L.base[threadIdx.x] = (int)ex;
         __syncthreads();
         for (int t = threadIdx.x; t < T; t += kGlobalThreads) {
             const int j = gload(&keys[t]);
             if (j == kEmpty || j < lo || j >= hi) continue;
             const int jl = j - lo, wd = jl >> 5, owner = wd / WPT;
-            int rank = s_base[owner];
+            int rank = L.base[owner];
             for (int q = owner * WPT; q < wd; ++q) rank += __popc(s_bm[q]);
             rank += __popc(s_bm[wd] & ((1u << (jl & 31)) - 1u));
             const long long pos = done + rank;
@@ -1339,6 +1374,21 @@ __global__ __launch_bounds__(kGlobalThreads) void k_num_global(
         __syncthreads();
     }
     if (threadIdx.x == 0 && done != nc) atomicOr(err, kErrCount);
+}
+
+// Numeric phase of heavy rows in global mode: one block per row.
+template <typename V>
+__global__ __launch_bounds__(kGlobalThreads) void k_num_global(
+    const int *__restrict__ Arp, const int *__restrict__ Acol, const V *__restrict__ Aval,
+    const int *__restrict__ Brp, const int *__restrict__ Bcol, const V *__restrict__ Bval,
+    const int *__restrict__ rows, int ncols, const long long *__restrict__ goff, int *gkeys, V *gvals,
+    const long long *__restrict__ Crp, int *__restrict__ Ccol, V *__restrict__ Cval, int *err)
+{
+    extern __shared__ unsigned s_bm[];                     // [kGlobalRankBits / 32]
+    __shared__ GlobalNumLds<V> L;
+    const int row = rows[blockIdx.x];
+    num_global_row<V>(Arp, Acol, Aval, Brp, Bcol, Bval, row, row, ncols, gkeys + goff[blockIdx.x],
+                      gvals + goff[blockIdx.x], L, s_bm, Crp, Ccol, Cval, err);
 }
 
 }  // namespace smash

@@ -87,6 +87,36 @@ for _f in ("smash_create", "smash_set_option", "smash_get_option", "smash_spgemm
     getattr(_lib, _f).restype = ctypes.c_int
 
 
+class BatchConfig(ctypes.Structure):
+    _fields_ = [("lds_row_max", ctypes.c_int32), ("table_shift", ctypes.c_int32), ("wide_groups", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {n: int(getattr(self, n)) for n, _ in self._fields_}
+
+
+_lib.smash_batch_plan_create.argtypes = [_c, ctypes.c_int, ctypes.c_int32, ctypes.POINTER(CsrDesc),
+                                         ctypes.POINTER(CsrDesc), ctypes.POINTER(BatchConfig), ALLOC_FN, _c,
+                                         ctypes.POINTER(_c), _c]
+_lib.smash_batch_plan_configure.argtypes = [_c, ctypes.POINTER(BatchConfig), _c]
+_lib.smash_batch_plan_get_config.argtypes = [_c, ctypes.POINTER(BatchConfig)]
+_lib.smash_batch_plan_outputs.argtypes = [_c, ctypes.POINTER(_c), ctypes.POINTER(_c), ctypes.POINTER(_c),
+                                          ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                          ctypes.POINTER(ctypes.POINTER(ctypes.c_int64))]
+_lib.smash_batch_plan_run.argtypes = [_c, _c]
+_lib.smash_batch_plan_capture.argtypes = [_c, _c]
+_lib.smash_batch_plan_launch.argtypes = [_c, _c]
+_lib.smash_batch_plan_result.argtypes = [_c, _c, ctypes.POINTER(ctypes.c_int64), _c]
+_lib.smash_batch_plan_destroy.argtypes = [_c]
+_lib.smash_batch_plan_destroy.restype = None
+_lib.smash_batch_autotune.argtypes = [_c, _c, ctypes.c_int32, ctypes.c_char_p, ctypes.POINTER(BatchConfig),
+                                      ctypes.POINTER(ctypes.c_double)]
+for _f in ("smash_batch_plan_create", "smash_batch_plan_configure", "smash_batch_plan_get_config",
+           "smash_batch_plan_outputs", "smash_batch_plan_run", "smash_batch_plan_capture", "smash_batch_plan_launch",
+           "smash_batch_plan_result", "smash_batch_autotune"):
+    getattr(_lib, _f).restype = ctypes.c_int
+
+
 class SmashError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"{STATUS.get(status, status)}: {message}")
@@ -277,6 +307,101 @@ class Context:
 
     def reset_kernel_times(self):
         self._check(_lib.smash_kernel_time_reset(self._h))
+
+
+class BatchPlan:
+    """A batch of products C_p = A_p * B_p run as one pipeline
+    (smash_batch_plan_*).  The output pool (row pointers over all problems'
+    rows, column and value pools) is allocated by torch at creation and held
+    here; ``problem(p)`` returns C_p as tensor views of it."""
+
+    def __init__(self, ctx: "Context", As, Bs, config: dict = None, stream=None):
+        import torch
+        assert len(As) == len(Bs)
+        self.ctx = ctx
+        self.count = len(As)
+        self._inputs = (list(As), list(Bs))         # keep the operands alive
+        dt = As[0].val.dtype if As else torch.float32
+        self.dtype = dt
+        self.dev = As[0].row_ptr.device if As else torch.device("cuda")
+        da = (CsrDesc * max(1, self.count))(*[a.desc() for a in As])
+        db = (CsrDesc * max(1, self.count))(*[b.desc() for b in Bs])
+        self._held = []
+
+        def _alloc(nbytes, _user):
+            t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.dev)
+            self._held.append(t)
+            return t.data_ptr()
+
+        self._cb = ALLOC_FN(_alloc)
+        cfg = ctypes.byref(BatchConfig(**config)) if config else None
+        h = _c()
+        ctx._check(_lib.smash_batch_plan_create(ctx._h, F32 if dt == torch.float32 else F64, self.count, da, db, cfg,
+                                                self._cb, None, ctypes.byref(h), _stream_ptr(stream)))
+        self._h = h
+        cap, rows = ctypes.c_int64(), ctypes.c_int64()
+        r0 = ctypes.POINTER(ctypes.c_int64)()
+        ctx._check(_lib.smash_batch_plan_outputs(self._h, None, None, None, ctypes.byref(cap), ctypes.byref(rows),
+                                                 ctypes.byref(r0)))
+        self.capacity, self.total_rows = int(cap.value), int(rows.value)
+        self.row0 = np.array([r0[i] for i in range(self.count + 1)], dtype=np.int64)
+        self.C_row_ptr = self._held[0].view(torch.int64)[:self.total_rows + 1]
+        self.C_col = self._held[1].view(torch.int32)[:self.capacity]
+        self.C_val = self._held[2].view(dt)[:self.capacity]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.smash_batch_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def configure(self, config: dict, stream=None):
+        self.ctx._check(_lib.smash_batch_plan_configure(self._h, ctypes.byref(BatchConfig(**config)),
+                                                        _stream_ptr(stream)))
+
+    def config(self) -> dict:
+        g = BatchConfig()
+        self.ctx._check(_lib.smash_batch_plan_get_config(self._h, ctypes.byref(g)))
+        return g.as_dict()
+
+    def run(self, stream=None):
+        self.ctx._check(_lib.smash_batch_plan_run(self._h, _stream_ptr(stream)))
+
+    def capture(self, stream):
+        self.ctx._check(_lib.smash_batch_plan_capture(self._h, _stream_ptr(stream)))
+
+    def launch(self, stream=None):
+        self.ctx._check(_lib.smash_batch_plan_launch(self._h, _stream_ptr(stream)))
+
+    def result(self, stream=None):
+        """(total entries, per-problem entries); synchronises the stream."""
+        tot = ctypes.c_int64()
+        per = np.zeros(max(1, self.count), dtype=np.int64)
+        self.ctx._check(_lib.smash_batch_plan_result(self._h, _stream_ptr(stream), ctypes.byref(tot),
+                                                     per.ctypes.data))
+        return int(tot.value), per[:self.count]
+
+    def autotune(self, reps=3, cache_path=None, stream=None):
+        """Returns (chosen configuration, its mean ms or 0 on a cache hit)."""
+        g, ms = BatchConfig(), ctypes.c_double()
+        self.ctx._check(_lib.smash_batch_autotune(self._h, _stream_ptr(stream), reps,
+                                                  os.fsencode(cache_path) if cache_path else None,
+                                                  ctypes.byref(g), ctypes.byref(ms)))
+        return g.as_dict(), float(ms.value)
+
+    def problem(self, p: int) -> DeviceCSR:
+        """C_p as views of the pool (row pointers rebased to its first entry)."""
+        r0, r1 = int(self.row0[p]), int(self.row0[p + 1])
+        rp = self.C_row_ptr[r0:r1 + 1]
+        base = int(rp[0].item())
+        n = int(rp[-1].item()) - base
+        return DeviceCSR(r1 - r0, int(self._inputs[1][p].cols), rp - base, self.C_col[base:base + n],
+                         self.C_val[base:base + n])
 
 
 def status_string(code: int) -> str:

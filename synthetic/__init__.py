@@ -21,6 +21,7 @@ per stored entry in CSR order, as ``2u - 1`` with ``u`` a 53-bit uniform in
 from __future__ import annotations
 
 import dataclasses
+import os
 import math
 
 import numpy as np
@@ -280,13 +281,19 @@ def workload_batch(count: int = 512, dtype=np.float32, seed0: int = 0x5EED0400):
     """The batched workload: C_i = A_i . B_i, A_i an n_i x n_i RMAT matrix
     (rejection at scale ceil(log2 n_i)), B_i n_i x n_i with 8 distinct
     uniform columns per row; problem i uses seed ``seed0 + i``."""
-    out = []
-    for i, (n, ef) in enumerate(batch_shapes(count, seed0)):
+    from concurrent.futures import ThreadPoolExecutor
+    shapes = batch_shapes(count, seed0)
+
+    def one(i):
+        n, ef = shapes[i]
         s = seed0 + i
         A = rmat_rect(n, ef, s, dtype)
         B = uniform_k_per_row(n, n, 8, s ^ 0xB, dtype)
-        out.append(Workload(f"batch{i}_n{n}_ef{ef}", A, B))
-    return out
+        return Workload(f"batch{i}_n{n}_ef{ef}", A, B)
+
+    # problems are independent; numpy releases the GIL in the bulk of the work
+    with ThreadPoolExecutor(max(1, min(8, os.cpu_count() or 1))) as ex:
+        return list(ex.map(one, range(count)))
 
 
 # ---------------------------------------------------------------- predictor
