@@ -71,6 +71,22 @@ def copy_calibration(mib: int, reps: int = 3):
     print(json.dumps({"copy_bytes_per_launch": n, "launches": reps, "gbs": round(2 * n / dt / 1e9, 1)}), flush=True)
 
 
+def committed_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary of
+    this workload (profiles/traffic_<workload>.json), or None when there is
+    none or the HIP sources changed since the counters were taken."""
+    from paper_2105_14156_amd import profiling
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("source_sha256") != profiling.source_hash():
+        return None
+    k = d.get("kernels", {}).get(kernel)
+    return int(k["hbm_bytes_scaled"]) if k else None
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -274,7 +290,8 @@ def main():
         "hbm_gbs_algorithmic": round(path_gbs, 2),
         "path_roofline_frac": round(path_gbs / HBM_PEAK_GBS, 4),
         "roofline": {"bound": "hbm", "kernel": dname, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": committed_traffic(name, dname) if args.path == "plain" and args.dtype == "f32" else None,
                      "launches_per_step": launches_per_step, "avg_launch_ms": round(avg_ms, 4),
                      "alg_bytes_per_launch": int(per_launch_bytes), "c_entry_share": round(share, 4)},
         "kernel_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in kt.items() if v[0]},

@@ -353,7 +353,7 @@ smash_status launch_seg_bin(smash_ctx c, hipStream_t s, const Plan &p, int bin, 
     const int *hrows = p.sym_perm + p.hdr.sym.offset[kBinHeavy];
     const Seg *segs = p.segs + p.hdr.seg.offset[bin];
     return launch(c, K_NUM_SEG, s, [&] {
-        k_num_seg<V, LOGT, THREADS><<<cnt, THREADS, 0, s>>>(p.A.row_ptr, p.A.col_idx, Aval, p.B.col_idx, Bval, p.bsplit,
+        k_num_seg<V, LOGT, THREADS><<<cnt, THREADS, 0, s>>>(p.A.row_ptr, p.A.col_idx, Aval, p.B.col_idx, Bval, p.bsplit, (long long)(p.nchunks + 1),
                                                      hrows, segs, p.nchunks, p.woff, (const long long *)crp, ccol,
                                                      cval, &c->d_hdr->error);
     });
@@ -378,7 +378,7 @@ smash_status numeric_impl(smash_ctx c, hipStream_t s, const Plan &p, const V *Av
             const Seg *segs = p.segs + p.hdr.seg.offset[kSegDense];
             TRY(launch(c, K_NUM_DENSE, s, [&] {
                 k_num_dense<V><<<nd, kDenseThreads, lds, s>>>(p.A.row_ptr, p.A.col_idx, Aval, p.B.col_idx, Bval,
-                                                             p.bsplit, hrows, segs, p.nchunks, p.woff,
+                                                             p.bsplit, (long long)(p.nchunks + 1), hrows, segs, p.nchunks, p.woff,
                                                              (const long long *)crp, ccol, cval, &c->d_hdr->error);
             }));
         }
@@ -725,7 +725,7 @@ smash_status symbolic_impl(smash_ctx c, const smash_csr *A, const smash_csr *B, 
         const int nwin = (p.nchunks + kSymWinChunks - 1) / kSymWinChunks;
         TRY(launch(c, K_SYM_HEAVY, s, [&] {
             k_sym_heavy<<<(unsigned)((long long)H * nwin), kSymHeavyThreads, 0, s>>>(
-                A->row_ptr, A->col_idx, B->col_idx, p.bsplit, heavy_rows, H, p.nchunks, p.wcnt, p.nnzc);
+                A->row_ptr, A->col_idx, B->col_idx, p.bsplit, (long long)(p.nchunks + 1), heavy_rows, H, p.nchunks, p.wcnt, p.nnzc);
         }));
     } else if (H > 0) {
         TRY(read_hdr(c, s));
@@ -1135,6 +1135,8 @@ struct smash_batch_plan_s {
     void *gvals = nullptr;
     long long gcap = 0;                  // slots of gkeys / gvals
     long long cap_total = 0;             // sum of the row bounds (pool capacity)
+    int wide_words = 1;                  // LDS bitmap words of the widest problem up to kWideMaxCols
+    bool any_global = false;             // a problem wider than kWideMaxCols (global tables)
     // caller-owned output pool
     long long *crp = nullptr;
     int *ccol = nullptr;
@@ -1238,7 +1240,10 @@ void batch_numeric(const BPlan &p, hipStream_t s)
 {
     if (p.cfg.wide_groups) bnum_bins<V, 1>(p, s);
     else bnum_bins<V, 0>(p, s);
-    k_bnum_global<V><<<bgrid(p, p.M), kGlobalThreads, kGlobalRankBits / 8, s>>>(
+    k_bnum_wide<V><<<bgrid(p, p.M), kWideThreads, kWideWin * sizeof(double), s>>>(
+        p.d_desc, p.prob, p.d_hdr, p.num_perm, p.ccap, p.crp, p.ccol, (V *)p.cval, &p.d_hdr->error);
+    if (p.any_global)
+        k_bnum_global<V><<<bgrid(p, p.M), kGlobalThreads, kGlobalRankBits / 8, s>>>(
         p.d_desc, p.prob, p.d_hdr, p.num_perm, p.goff, p.gcap, p.gkeys, (V *)p.gvals, p.ccap, p.crp, p.ccol,
         (V *)p.cval, &p.d_hdr->error);
 }
@@ -1255,7 +1260,10 @@ void batch_enqueue(const BPlan &p, hipStream_t s)
     bscan<long long>(p, s, p.M, p.gsz, p.goff, &p.d_hdr->gneed);
     if (p.cfg.wide_groups) bsym_bins<1>(p, s);
     else bsym_bins<0>(p, s);
-    k_bsym_global<<<bgrid(p, p.M), kGlobalThreads, 0, s>>>(p.d_desc, p.prob, &p.d_hdr->sym, p.sym_perm, p.cap,
+    k_bsym_wide<<<bgrid(p, p.M), kWideThreads, p.wide_words * sizeof(unsigned), s>>>(
+        p.d_desc, p.prob, &p.d_hdr->sym, p.sym_perm, p.nnzc);
+    if (p.any_global)
+        k_bsym_global<<<bgrid(p, p.M), kGlobalThreads, 0, s>>>(p.d_desc, p.prob, &p.d_hdr->sym, p.sym_perm, p.cap,
                                                            p.goff, p.gcap, p.gkeys, p.nnzc, &p.d_hdr->error);
     bscan<int>(p, s, p.M, p.nnzc, p.crp, &p.d_hdr->nnz_c);
     k_bcheck<<<1, 64, 0, s>>>(p.d_hdr, p.ccap);
@@ -1356,6 +1364,10 @@ smash_status smash_batch_plan_create(smash_ctx c, smash_dtype dtype, int32_t cou
                                (int)A[q].rows, (int)B[q].cols, (long long)p->row0[q]};
     }
     p->M = p->row0[count];
+    for (int q = 0; q < count; ++q) {
+        if (B[q].cols <= kWideMaxCols) p->wide_words = std::max(p->wide_words, (int)((B[q].cols + 31) / 32));
+        else p->any_global = true;
+    }
     smash_status st = SMASH_OK;
     auto bail = [&](smash_status e) {
         batch_free(p);
@@ -1373,6 +1385,17 @@ smash_status smash_batch_plan_create(smash_ctx c, smash_dtype dtype, int32_t cou
     if (hipMalloc(&p->ws, need) != hipSuccess) return bail(fail(c, SMASH_ERR_OUT_OF_MEMORY, "batch workspace"));
     if (hipHostMalloc((void **)&p->h_hdr, sizeof(BatchHdr), hipHostMallocDefault) != hipSuccess)
         return bail(fail(c, SMASH_ERR_HIP, "pinned header"));
+    if (hipFuncSetAttribute((const void *)k_bsym_wide, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(p->wide_words * sizeof(unsigned))) != hipSuccess ||
+        hipFuncSetAttribute((const void *)k_bnum_global<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            kGlobalRankBits / 8) != hipSuccess ||
+        hipFuncSetAttribute((const void *)k_bnum_global<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            kGlobalRankBits / 8) != hipSuccess ||
+        hipFuncSetAttribute((const void *)k_bnum_wide<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(kWideWin * sizeof(double))) != hipSuccess ||
+        hipFuncSetAttribute((const void *)k_bnum_wide<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(kWideWin * sizeof(double))) != hipSuccess)
+        return bail(fail(c, SMASH_ERR_HIP, "hipFuncSetAttribute"));
     Carve cv{(char *)p->ws};
     p->d_desc = cv.take<BatchDesc>(p->desc.size());
     p->d_row0 = cv.take<long long>((size_t)count + 1);

@@ -8,8 +8,10 @@
 // so the whole sequence can be captured once in a graph and replayed with no
 // host synchronisation: analysis, binning, symbolic per bin, one row-pointer
 // scan over the batch (each C_p lands at a device-computed offset of one
-// output pool), numeric per bin.  Rows whose bound exceeds the LDS limit use
-// per-row tables in global memory.
+// output pool), numeric per bin.  Rows whose bound exceeds the LDS hash
+// limit are counted in an LDS bitmap over B's columns and accumulated in LDS
+// windows of columns (per-row global tables only for problems wider than
+// kWideMaxCols columns).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -37,6 +39,13 @@ struct BatchHdr {
 };
 
 enum : int { kErrCapacity = 16 };
+
+// Heavy rows of problems with at most kWideMaxCols columns are counted with
+// an LDS bitmap over all columns and accumulated in LDS windows of
+// kWideWin columns; wider problems use per-row global tables.
+constexpr int kWideMaxCols = 1 << 20;
+constexpr int kWideWin = 8192;
+constexpr int kWideThreads = 512;
 
 // Table size class of a row bound: 2^LOGT >= bound << shift slots.
 __device__ __forceinline__ int lds_bin_shift(long long bound, int shift)
@@ -83,7 +92,7 @@ __global__ __launch_bounds__(256) void k_banalyze(long long M, int count, const 
             cap_out[g] = cap;
             nnzc[g] = 0;
             bin_out[g] = (unsigned char)b;
-            gsz[g] = b == kBinHeavy ? 1LL << gtable_log2(cap) : 0;
+            gsz[g] = b == kBinHeavy && d.cols > kWideMaxCols ? 1LL << gtable_log2(cap) : 0;
         }
     }
 }
@@ -177,6 +186,8 @@ __global__ __launch_bounds__(kGlobalThreads) void k_bsym_global(const BatchDesc 
     const int *rows = perm + h->offset[kBinHeavy];
     for (int r = blockIdx.x; r < cnt; r += gridDim.x) {
         const int grow = rows[r];
+        const BatchDesc &d = desc[prob[grow]];
+        if (d.cols <= kWideMaxCols) continue;
         const long long off = goff[grow];
         const int T = 1 << gtable_log2(cap[grow]);
         if (off + T > gcap) {
@@ -187,7 +198,6 @@ __global__ __launch_bounds__(kGlobalThreads) void k_bsym_global(const BatchDesc 
         for (int t = threadIdx.x; t < T; t += kGlobalThreads) keys[t] = kEmpty;
         __threadfence();
         __syncthreads();
-        const BatchDesc &d = desc[prob[grow]];
         sym_global_row(d.Arp, d.Acol, d.Brp, d.Bcol, (int)(grow - d.row0), cap[grow], keys, S, &s_cnt, &nnzc[grow],
                        err);
         __syncthreads();
@@ -211,16 +221,149 @@ __global__ __launch_bounds__(kGlobalThreads) void k_bnum_global(const BatchDesc 
     const int *rows = perm + bh->num.offset[kBinHeavy];
     for (int r = blockIdx.x; r < cnt; r += gridDim.x) {
         const int grow = rows[r];
+        const BatchDesc &d = desc[prob[grow]];
+        if (d.cols <= kWideMaxCols) continue;
         const long long off = goff[grow];
         const int nc = (int)(Crp[grow + 1] - Crp[grow]);
         if (off + (1LL << gtable_log2(nc)) > gcap) {
             if (threadIdx.x == 0) atomicOr(err, kErrCapacity);
             continue;
         }
-        const BatchDesc &d = desc[prob[grow]];
         num_global_row<V>(d.Arp, d.Acol, (const V *)d.Aval, d.Brp, d.Bcol, (const V *)d.Bval, (int)(grow - d.row0),
                           grow, d.cols, gkeys + off, gvals + off, L, s_bm, Crp, Ccol, Cval, err);
         __syncthreads();
+    }
+}
+
+// Symbolic, heavy rows of problems with at most kWideMaxCols columns: one
+// block per row sets one bit per column of the row in an LDS bitmap over all
+// of B's columns (dynamic LDS, ceil(cols / 32) words) and counts the bits.
+__global__ __launch_bounds__(kWideThreads) void k_bsym_wide(const BatchDesc *__restrict__ desc,
+                                                            const int *__restrict__ prob, const BinHdr *h,
+                                                            const int *__restrict__ perm, int *__restrict__ nnzc)
+{
+    extern __shared__ unsigned s_bmw[];
+    __shared__ EnumScratch<float, kWideThreads> S;
+    __shared__ int s_cnt;
+    const int cnt = h->count[kBinHeavy];
+    const int *rows = perm + h->offset[kBinHeavy];
+    const int gt = threadIdx.x;
+    for (int r = blockIdx.x; r < cnt; r += gridDim.x) {
+        const int grow = rows[r];
+        const BatchDesc &d = desc[prob[grow]];
+        if (d.cols > kWideMaxCols) continue;
+        const int nw = (d.cols + 31) >> 5;
+        const int *Acol = d.Acol, *Brp = d.Brp;
+        const int arow = (int)(grow - d.row0);
+        for (int t = gt; t < nw; t += kWideThreads) s_bmw[t] = 0u;
+        if (gt == 0) s_cnt = 0;
+        __syncthreads();
+        group_products<float, false, kWideThreads, 4>(
+            d.Arp[arow], d.Arp[arow + 1], gt, S, d.Bcol, (const float *)nullptr,
+            [&](int e, int &bs, int &bl, float &) {
+                const int k = Acol[e];
+                bs = Brp[k];
+                bl = Brp[k + 1] - bs;
+            },
+            [&](int j) {
+                const unsigned bit = 1u << (j & 31);
+                if (!(s_bmw[j >> 5] & bit)) atomicOr(&s_bmw[j >> 5], bit);
+            });
+        __syncthreads();
+        int c = 0;
+        for (int t = gt; t < nw; t += kWideThreads) c += __popc(s_bmw[t]);
+        c = wave_sum(c);
+        if (lane_id() == 0 && c) atomicAdd(&s_cnt, c);
+        __syncthreads();
+        if (gt == 0) nnzc[grow] = s_cnt;
+    }
+}
+
+// Numeric, heavy rows of problems with at most kWideMaxCols columns: one
+// block per row takes B's columns in windows of kWideWin; in each window the
+// row's products with columns inside it are added into an LDS array of
+// doubles indexed by column (occupancy marked by the -0.0 start value, as in
+// the dense chunks of single products), and each wave ranks its share of the
+// window with ballots and writes its entries in column order (dynamic LDS:
+// the kWideWin doubles).
+template <typename V>
+__global__ __launch_bounds__(kWideThreads) void k_bnum_wide(const BatchDesc *__restrict__ desc,
+                                                            const int *__restrict__ prob, const BatchHdr *bh,
+                                                            const int *__restrict__ perm, long long ccap,
+                                                            const long long *__restrict__ Crp, int *__restrict__ Ccol,
+                                                            V *__restrict__ Cval, int *err)
+{
+    constexpr int NW = kWideThreads / kWave;
+    constexpr int CPW = kWideWin / NW;                  // columns ranked by each wave
+    constexpr int ROUNDS = CPW / kWave;
+    extern __shared__ unsigned char s_raw[];
+    double *acc = (double *)s_raw;                      // [kWideWin]
+    __shared__ EnumScratch<V, kWideThreads> S;
+    __shared__ int s_wt[NW];
+    if (bh->nnz_c > ccap) return;
+    const int cnt = bh->num.count[kBinHeavy];
+    const int *rows = perm + bh->num.offset[kBinHeavy];
+    const int gt = threadIdx.x, lane = lane_id(), wg = gt / kWave;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (int r = blockIdx.x; r < cnt; r += gridDim.x) {
+        const int grow = rows[r];
+        const BatchDesc &d = desc[prob[grow]];
+        if (d.cols > kWideMaxCols) continue;
+        const int *Acol = d.Acol, *Brp = d.Brp;
+        const V *Aval = (const V *)d.Aval;
+        const int arow = (int)(grow - d.row0);
+        const long long rb = Crp[grow];
+        const int nc = (int)(Crp[grow + 1] - rb);
+        int done = 0;
+        for (int lo = 0; lo < d.cols; lo += kWideWin) {
+            for (int t = gt; t < kWideWin; t += kWideThreads) acc[t] = -0.0;
+            __syncthreads();
+            group_products<V, true, kWideThreads, 4>(
+                d.Arp[arow], d.Arp[arow + 1], gt, S, d.Bcol, (const V *)d.Bval,
+                [&](int e, int &bs, int &bl, V &a) {
+                    const int k = Acol[e];
+                    bs = Brp[k];
+                    bl = Brp[k + 1] - bs;
+                    a = Aval[e];
+                },
+                [&](int j, double p) {
+                    const unsigned jl = (unsigned)(j - lo);
+                    if (jl < (unsigned)kWideWin) atomicAdd(&acc[jl], p + 0.0);
+                });
+            __syncthreads();
+            double vr[ROUNDS];
+            unsigned long long msk[ROUNDS];
+            int wcount = 0;
+#pragma unroll
+            for (int q = 0; q < ROUNDS; ++q) {
+                const int jl = wg * CPW + q * kWave + lane;
+                vr[q] = acc[jl];
+                msk[q] = __ballot(__double_as_longlong(vr[q]) != kNegZeroBits);
+                wcount += __popcll(msk[q]);
+            }
+            if (lane == 0) s_wt[wg] = wcount;
+            __syncthreads();
+            int run = done, tot = 0;
+            for (int w = 0; w < NW; ++w) {
+                const int t = s_wt[w];
+                if (w < wg) run += t;
+                tot += t;
+            }
+#pragma unroll
+            for (int q = 0; q < ROUNDS; ++q) {
+                if ((msk[q] >> lane) & 1ull) {
+                    const int pos = run + __popcll(msk[q] & below);
+                    if (pos < nc) {
+                        store_c(&Ccol[rb + pos], lo + wg * CPW + q * kWave + lane);
+                        store_c(&Cval[rb + pos], (V)vr[q]);
+                    }
+                }
+                run += __popcll(msk[q]);
+            }
+            done += tot;
+            __syncthreads();
+        }
+        if (gt == 0 && done != nc) atomicOr(err, kErrCount);
     }
 }
 

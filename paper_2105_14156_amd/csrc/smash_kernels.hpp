@@ -214,8 +214,9 @@ struct EnumScratch {
 // entry with one search that all its lanes share, and every lane loads one
 // product per piece (coalesced, no per-lane search).  Shorter ranges, which
 // carry few of the products, are enumerated flat: thread gt takes products
-// q = gt, gt + G, ... and finds its A entry by binary search.  U products per
-// thread are located and loaded before any is merged.
+// q = gt, gt + G, ... and finds its A entry by binary search (consecutive
+// lanes then read consecutive B entries where a range continues).  U products
+// per thread are located and loaded before any is merged.
 template <typename V, bool WITH_VAL, int G, int U, typename Get, typename Sink>
 __device__ __forceinline__ void group_products(int e0, int e1, int gt, EnumScratch<V, G> &S,
                                                const int *__restrict__ Bcol, const V *__restrict__ Bval,
@@ -852,7 +853,7 @@ constexpr int kSymHeavyThreads = 256;
 
 __global__ __launch_bounds__(kSymHeavyThreads) void k_sym_heavy(
     const int *__restrict__ Arp, const int *__restrict__ Acol, const int *__restrict__ Bcol,
-    const int *__restrict__ Bsplit, const int *__restrict__ rows, int nheavy, int nchunks,
+    const int *__restrict__ Bsplit, long long per, const int *__restrict__ rows, int nheavy, int nchunks,
     int *__restrict__ wcnt, int *__restrict__ nnzc)
 {
     constexpr int G = kSymHeavyThreads;
@@ -867,15 +868,16 @@ __global__ __launch_bounds__(kSymHeavyThreads) void k_sym_heavy(
     const int c0 = w * kSymWinChunks;
     const int c1 = c0 + kSymWinChunks < nchunks ? c0 + kSymWinChunks : nchunks;
     const int lo = c0 * kChunkCols;
-    const long long per = nchunks + 1;
+    const int *__restrict__ split0 = Bsplit + c0;
+    const int *__restrict__ split1 = Bsplit + c1;
     for (int t = gt; t < WORDS; t += G) bm[t] = 0u;
     __syncthreads();
     group_products<float, false, G, 4>(
         Arp[row], Arp[row + 1], gt, S, Bcol, (const float *)nullptr,
         [&](int e, int &bs, int &bl, float &) {
-            const long long k = Acol[e];
-            bs = Bsplit[k * per + c0];
-            bl = Bsplit[k * per + c1] - bs;
+            const int k = Acol[e];
+            bs = split0[k * per];
+            bl = split1[k * per] - bs;
         },
         [&](int j) {
             const int jl = j - lo;
@@ -1042,7 +1044,7 @@ constexpr int kSegPrefGroup = 8;        // bitmap words per prefix entry
 template <typename V, int LOGT, int THREADS>
 __global__ __launch_bounds__(THREADS) void k_num_seg(
     const int *__restrict__ Arp, const int *__restrict__ Acol, const V *__restrict__ Aval,
-    const int *__restrict__ Bcol, const V *__restrict__ Bval, const int *__restrict__ Bsplit,
+    const int *__restrict__ Bcol, const V *__restrict__ Bval, const int *__restrict__ Bsplit, long long per,
     const int *__restrict__ heavy_rows, const Seg *__restrict__ segs, int nchunks,
     const int *__restrict__ woff, const long long *__restrict__ Crp, int *__restrict__ Ccol,
     V *__restrict__ Cval, int *err)
@@ -1060,7 +1062,8 @@ __global__ __launch_bounds__(THREADS) void k_num_seg(
     const int gt = threadIdx.x;
     const int lo = sg.c0 * kChunkCols;
     const int words = (sg.c1 - sg.c0) * kChunkWords;
-    const long long per = nchunks + 1;
+    const int *__restrict__ split0 = Bsplit + sg.c0;
+    const int *__restrict__ split1 = Bsplit + sg.c1;
     for (int t = gt; t < T; t += THREADS) {
         keys[t] = kEmpty;
         vals[t] = 0.0;
@@ -1070,9 +1073,9 @@ __global__ __launch_bounds__(THREADS) void k_num_seg(
     group_products<V, true, THREADS, 4>(
         sg.e0, sg.e1, gt, S, Bcol, Bval,
         [&](int e, int &bs, int &bl, V &a) {
-            const long long k = Acol[e];
-            bs = Bsplit[k * per + sg.c0];
-            bl = Bsplit[k * per + sg.c1] - bs;
+            const int k = Acol[e];
+            bs = split0[k * per];
+            bl = split1[k * per] - bs;
             a = Aval[e];
         },
         [&](int j, double p) { lds_insert_add(keys, vals, LOGT, j, p, err); });
@@ -1128,16 +1131,20 @@ __global__ __launch_bounds__(THREADS) void k_num_seg(
 }
 
 // Dense chunk of a heavy row: products whose columns lie in chunk c0 added
-// directly into an LDS array of doubles indexed by column, with an occupancy
-// bitmap; each wave then ranks its own 512 columns with ballots and writes its
-// entries straight to C in column order (consecutive lanes, consecutive
-// addresses).
+// directly into an LDS array of doubles indexed by column; each wave then
+// ranks its own 1024 columns with ballots and writes its entries straight to
+// C in column order (consecutive lanes, consecutive addresses).  Occupancy
+// needs no bitmap: the array starts at -0.0 and every product is added as
+// p + 0.0, which is never -0.0, so a column was reached exactly when its sum
+// is no longer the bit pattern of -0.0 (a sum of terms that are not -0.0 is
+// never -0.0 under round-to-nearest, even when they cancel).
 constexpr int kDenseThreads = 512;
+constexpr long long kNegZeroBits = (long long)0x8000000000000000ULL;
 
 template <typename V>
 __global__ __launch_bounds__(kDenseThreads) void k_num_dense(
     const int *__restrict__ Arp, const int *__restrict__ Acol, const V *__restrict__ Aval,
-    const int *__restrict__ Bcol, const V *__restrict__ Bval, const int *__restrict__ Bsplit,
+    const int *__restrict__ Bcol, const V *__restrict__ Bval, const int *__restrict__ Bsplit, long long per,
     const int *__restrict__ heavy_rows, const Seg *__restrict__ segs, int nchunks,
     const int *__restrict__ woff, const long long *__restrict__ Crp, int *__restrict__ Ccol,
     V *__restrict__ Cval, int *err)
@@ -1147,29 +1154,24 @@ __global__ __launch_bounds__(kDenseThreads) void k_num_dense(
     constexpr int ROUNDS = CPW / kWave;
     extern __shared__ unsigned char s_raw[];
     double *acc = (double *)s_raw;                      // [kChunkCols]
-    __shared__ unsigned bm[kChunkWords];
     __shared__ EnumScratch<V, kDenseThreads> S;
     __shared__ int s_wt[NW];
     const Seg sg = segs[blockIdx.x];
     const int gt = threadIdx.x, lane = lane_id(), wg = gt / kWave;
     const int lo = sg.c0 * kChunkCols;
-    const long long per = nchunks + 1;
-    for (int t = gt; t < kChunkCols; t += kDenseThreads) acc[t] = 0.0;
-    for (int t = gt; t < kChunkWords; t += kDenseThreads) bm[t] = 0u;
+    const int *__restrict__ split0 = Bsplit + sg.c0;
+    const int *__restrict__ split1 = split0 + 1;
+    for (int t = gt; t < kChunkCols; t += kDenseThreads) acc[t] = -0.0;
     __syncthreads();
     group_products<V, true, kDenseThreads, 4>(
         sg.e0, sg.e1, gt, S, Bcol, Bval,
         [&](int e, int &bs, int &bl, V &a) {
-            const long long k = Acol[e];
-            bs = Bsplit[k * per + sg.c0];
-            bl = Bsplit[k * per + sg.c0 + 1] - bs;
+            const int k = Acol[e];
+            bs = split0[k * per];
+            bl = split1[k * per] - bs;
             a = Aval[e];
         },
-        [&](int j, double p) {
-            const int jl = j - lo;
-            atomicAdd(&acc[jl], p);
-            atomicOr(&bm[jl >> 5], 1u << (jl & 31));
-        });
+        [&](int j, double p) { atomicAdd(&acc[j - lo], p + 0.0); });
     __syncthreads();
     double vr[ROUNDS];
     unsigned long long msk[ROUNDS];
@@ -1178,7 +1180,7 @@ __global__ __launch_bounds__(kDenseThreads) void k_num_dense(
     for (int r = 0; r < ROUNDS; ++r) {
         const int jl = wg * CPW + r * kWave + lane;
         vr[r] = acc[jl];
-        msk[r] = __ballot((bm[jl >> 5] >> (jl & 31)) & 1u);
+        msk[r] = __ballot(__double_as_longlong(vr[r]) != kNegZeroBits);
         wcount += __popcll(msk[r]);
     }
     if (lane == 0) s_wt[wg] = wcount;

@@ -167,6 +167,15 @@ def uniform_k_per_row(rows: int, cols: int, k: int, seed: int, dtype=np.float32)
     the next block of the stream until every row is duplicate-free."""
     if k > cols:
         raise ValueError("k > cols")
+    if k * k > 8 * cols:
+        # redraws would almost never succeed: take, per row, the k columns
+        # with the smallest of cols uniform keys
+        out = np.empty((rows, k), dtype=np.int64)
+        for r in range(rows):
+            u = uniform01(seed ^ SALT_STRUCT, r * cols, cols)
+            out[r] = np.sort(np.argpartition(u, k - 1)[:k])
+        rr = np.repeat(np.arange(rows, dtype=np.int64), k)
+        return csr_from_coo(rows, cols, rr, out.reshape(-1), seed, dtype)
     out = np.empty((rows, k), dtype=np.int64)
     todo = np.arange(rows, dtype=np.int64)
     rnd = 0

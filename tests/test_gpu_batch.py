@@ -98,12 +98,23 @@ def test_batch_degenerate(env, oracle_mod):
         (syn.dense_rows(8, 3000, [1, 5], 5, f32), syn.random_sparse(3000, 5000, 0.004, 6, f32)),
         (syn.identity(100, f32), syn.random_sparse(100, 9, 0.5, 7, f32)),
         (syn.random_sparse(1, 1, 1.0, 8, f32), syn.random_sparse(1, 1, 1.0, 9, f32)),
+        # wider than the LDS bitmap limit: heavy rows use global tables
+        (syn.random_sparse(30, 200, 0.3, 10, f32), syn.uniform_k_per_row(200, (1 << 20) + 3000, 40, 11, f32)),
+        # products that are all +-0.0, in the LDS windows of heavy rows
+        _zero_case(),
     ]
     refs = [oracle_mod.spgemm(A, B) for A, B in probs]
     plan = _make_plan(smash, ctx, probs, dict(lds_row_max=64, table_shift=1, wide_groups=0, blocks_per_cu=2))
     plan.run()
     _check_plan(plan, probs, refs, oracle_mod, "degenerate")
     plan.close()
+
+
+def _zero_case():
+    B = syn.uniform_k_per_row(8, 8192, 3000, 0x2E0, np.float32)
+    A = syn.CSR(3, 8, np.array([0, 2, 4, 6], np.int32), np.arange(6, dtype=np.int32),
+                np.array([0.0, -0.0, -0.0, -0.0, 0.5, -0.0], np.float32))
+    return A, B
 
 
 def test_batch_without_rows(env):

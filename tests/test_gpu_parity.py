@@ -140,6 +140,29 @@ def test_cancellation_keeps_structural_zero(sm, ctx, oracle_mod):
     assert val.tolist() == [0.0, 8.0, -2.0, 10.0]
 
 
+def _zero_product_case():
+    """Rows whose products are all exactly +-0.0 (explicit zero and negative
+    zero values in A), landing in dense chunks: 3 rows of A, each reaching
+    two B rows of 3000 columns within one 8192-column chunk."""
+    B = syn.uniform_k_per_row(8, 8192, 3000, 0x2E0, np.float64)
+    rp = np.array([0, 2, 4, 6], np.int32)
+    ci = np.array([0, 1, 2, 3, 4, 5], np.int32)
+    va = np.array([0.0, -0.0, -0.0, -0.0, 0.5, -0.0])      # row 2 mixes a nonzero in
+    A = syn.CSR(3, 8, rp, ci, va)
+    return A, B
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_zero_products_keep_structure(sm, ctx, oracle_mod, dtype):
+    A, B = _zero_product_case()
+    ctx.set_option(sm.OPT_LDS_ROW_MAX, 64)
+    rp, col, val = run(sm, ctx, A.astype(dtype), B.astype(dtype), dtype)
+    assert ctx.stats()["heavy_dense_chunks"] > 0
+    ref = oracle_mod.spgemm(A.astype(dtype), B.astype(dtype))
+    check_rows(rp, col, val, ref, dtype, "zero products")
+    assert np.all(val[: rp[2]] == 0.0)
+
+
 def test_repeat_numeric_and_determinism(sm, ctx, oracle_mod, torch_mod):
     torch = torch_mod
     A = syn.rmat(14, 8, 0x99, np.float32)
