@@ -85,7 +85,11 @@ typedef enum {
     /* 1 = record HIP events around every kernel launch and accumulate the
      * elapsed time per kernel (smash_kernel_time).  Default 0. */
     SMASH_OPT_TIMING = 3,
-    SMASH_OPT_COUNT = 4
+    /* Row capacities of smash_spgemm_fused: 0 = the installed predictor
+     * (default); 1 = the exact upper bound min(products, cols), without the
+     * network (the baseline that shows what the network gains). */
+    SMASH_OPT_FUSED_SIZING = 4,
+    SMASH_OPT_COUNT = 5
 } smash_option;
 
 /* Counters of the last symbolic/numeric call (smash_get_stats). */
@@ -103,6 +107,7 @@ typedef struct {
     int64_t nnz_dense;          /* entries of C in dense chunks of heavy rows */
     int64_t fused_rows;         /* rows completed by the fused pass (smash_spgemm_fused) */
     int64_t fused_overflow;     /* rows the fused pass handed back (prediction too small) */
+    int64_t fused_capacity;     /* sum of the capacities the fused pass reserved (staging slots) */
 } smash_stats;
 
 /* Allocation callback of smash_spgemm: return device memory of at least
@@ -221,7 +226,7 @@ smash_status smash_predictor_set(smash_ctx ctx, const float *params, const float
  * is never lost to a bad prediction; only time is).  Staged rows are copied
  * to their final offsets after the row-pointer scan.  The result is the same
  * canonical C as smash_spgemm.  Errors: NO_PLAN if no predictor is
- * installed, and those of smash_spgemm. */
+ * installed while SMASH_OPT_FUSED_SIZING is 0, and those of smash_spgemm. */
 smash_status smash_spgemm_fused(smash_ctx ctx, smash_dtype dtype, const smash_csr *A, const smash_csr *B,
                                 smash_alloc_fn alloc, void *user, int64_t *C_row_ptr,
                                 int32_t **C_col_idx, void **C_val, int64_t *C_nnz, hipStream_t stream);

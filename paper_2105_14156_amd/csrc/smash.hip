@@ -104,7 +104,7 @@ struct Pending {
 struct smash_ctx_s {
     int device = 0;
     std::string err;
-    int64_t opt[5] = {1, 1024, 0, 0, 0};
+    int64_t opt[SMASH_OPT_COUNT] = {1, 1024, 0, 0, 0};
     DevHdr *h_hdr = nullptr;   // pinned host mirror
     DevHdr *d_hdr = nullptr;
     Arena plan_mem, heavy_mem, gkeys, gvals, mlp_mem, pred_mem, fused_mem, stage_mem;
@@ -448,16 +448,20 @@ smash_status fused_stage(smash_ctx c, hipStream_t s, Plan &p)
     p.fstatus = cv.take<unsigned char>(m);
     p.stage_off = cv.take<long long>(m + 1);
     const float *prm = (const float *)c->pred_mem.ptr;
-    TRY(launch(c, K_FEATURES, s, [&] {
-        k_features<<<blocks_for(m, 4), 256, 0, s>>>(m, (int)p.n, p.A.row_ptr, p.A.col_idx, p.B.row_ptr, p.feats,
-                                                    nullptr, p.maxb);
-    }));
-    TRY(launch(c, K_MLP_PREDICT, s, [&] {
-        k_mlp_predict<<<blocks_for(m, 256), 256, 0, s>>>(m, (int)p.n, p.feats, prm, prm + kParams, c->pred_delta,
-                                                         p.ub, p.maxb, nullptr, p.cap_pred);
-    }));
+    const bool learned = c->opt[SMASH_OPT_FUSED_SIZING] == 0;
+    if (learned) {
+        TRY(launch(c, K_FEATURES, s, [&] {
+            k_features<<<blocks_for(m, 4), 256, 0, s>>>(m, (int)p.n, p.A.row_ptr, p.A.col_idx, p.B.row_ptr, p.feats,
+                                                        nullptr, p.maxb);
+        }));
+        TRY(launch(c, K_MLP_PREDICT, s, [&] {
+            k_mlp_predict<<<blocks_for(m, 256), 256, 0, s>>>(m, (int)p.n, p.feats, prm, prm + kParams,
+                                                             c->pred_delta, p.ub, p.maxb, nullptr, p.cap_pred);
+        }));
+    }
     TRY(launch(c, K_FUSED_AUX, s, [&] {
-        k_fused_bins<<<blocks_for(m, 256), 256, 0, s>>>(m, p.ub, p.cap_pred, p.lds_row_max, p.fbin, p.fcap);
+        k_fused_bins<<<blocks_for(m, 256), 256, 0, s>>>(m, p.ub, learned ? p.cap_pred : p.cap, p.lds_row_max,
+                                                        p.fbin, p.fcap);
     }));
     TRY(bin_rows(c, s, p, p.fbin, nullptr, nullptr, &c->d_hdr->fz, p.f_perm, nullptr));
     TRY(scan_counts<int>(c, s, m, p.fcap, p.bsum, p.stage_off, &c->d_hdr->stage_total));
@@ -576,6 +580,7 @@ smash_status smash_set_option(smash_ctx c, smash_option opt, int64_t v)
     switch (opt) {
     case SMASH_OPT_VALIDATE:
     case SMASH_OPT_TIMING:
+    case SMASH_OPT_FUSED_SIZING:
         if (v != 0 && v != 1) return fail(c, SMASH_ERR_INVALID_ARG, "option %d takes 0 or 1", (int)opt);
         break;
     case SMASH_OPT_LDS_ROW_MAX:
@@ -783,6 +788,7 @@ smash_status symbolic_impl(smash_ctx c, const smash_csr *A, const smash_csr *B, 
     if (fuse) {
         c->stats.fused_rows = p.hdr.fused_ok;
         c->stats.fused_overflow = p.hdr.fz.offset[kLdsBins] - p.hdr.fused_ok;
+        c->stats.fused_capacity = p.hdr.stage_total;
         c->stats.rows_empty -= p.hdr.fused_ok;
     }
     p.valid = true;
@@ -1044,7 +1050,8 @@ smash_status smash_spgemm_fused(smash_ctx c, smash_dtype dtype, const smash_csr 
     if (!alloc || !C_col_idx || !C_val || !C_nnz || !C_row_ptr)
         return fail(c, SMASH_ERR_INVALID_ARG, "null output argument");
     if (dtype != SMASH_F32 && dtype != SMASH_F64) return fail(c, SMASH_ERR_INVALID_ARG, "unknown dtype %d", (int)dtype);
-    if (!c->has_predictor) return fail(c, SMASH_ERR_NO_PLAN, "no predictor installed (smash_predictor_set/load)");
+    if (!c->has_predictor && c->opt[SMASH_OPT_FUSED_SIZING] == 0)
+        return fail(c, SMASH_ERR_NO_PLAN, "no predictor installed (smash_predictor_set/load)");
     DeviceGuard g(c->device);
     if (!g.ok) return fail(c, SMASH_ERR_HIP, "hipSetDevice(%d) failed", c->device);
     int64_t nnz = 0;

@@ -205,6 +205,35 @@ struct EnumScratch {
     int wsum[2 * (G / kWave)];
 };
 
+// Hands U loaded products of one thread to the sink: one call per product
+// (sink(j, a * b), or sink(j) without values), or with ARRAY_SINK one call
+// with all U (sink(j[U], p[U], ok[U]), or sink(j[U], ok[U])), so that the
+// sink can overlap their LDS round trips.
+template <bool WITH_VAL, int U, bool ARRAY_SINK, typename Sink>
+__device__ __forceinline__ void emit_products(Sink &sink, const int (&pos)[U], const int (&j)[U],
+                                              const double (&av)[U], const double (&bv)[U])
+{
+    if constexpr (ARRAY_SINK) {
+        bool ok[U];
+        double p[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            ok[u] = pos[u] >= 0;
+            p[u] = av[u] * bv[u];
+        }
+        if constexpr (WITH_VAL) sink(j, p, ok);
+        else sink(j, ok);
+    } else {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (pos[u] >= 0) {
+                if constexpr (WITH_VAL) sink(j[u], av[u] * bv[u]);
+                else sink(j[u]);
+            }
+        }
+    }
+}
+
 // Calls sink(j, a * b) -- the product formed in double -- (or sink(j)
 // without values) for every product of the A entries [e0, e1) of one row,
 // each restricted to the B range returned by get(e, &bstart, &blen, &a).  The
@@ -217,7 +246,7 @@ struct EnumScratch {
 // q = gt, gt + G, ... and finds its A entry by binary search (consecutive
 // lanes then read consecutive B entries where a range continues).  U products
 // per thread are located and loaded before any is merged.
-template <typename V, bool WITH_VAL, int G, int U, typename Get, typename Sink>
+template <typename V, bool WITH_VAL, int G, int U, typename Get, typename Sink, bool ARRAY_SINK = false>
 __device__ __forceinline__ void group_products(int e0, int e1, int gt, EnumScratch<V, G> &S,
                                                const int *__restrict__ Bcol, const V *__restrict__ Bval,
                                                Get get, Sink sink)
@@ -287,13 +316,7 @@ __device__ __forceinline__ void group_products(int e0, int e1, int gt, EnumScrat
                     if constexpr (WITH_VAL) bv[u] = (double)Bval[pos[u]];
                 }
             }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                if (pos[u] >= 0) {
-                    if constexpr (WITH_VAL) sink(j[u], av[u] * bv[u]);
-                    else sink(j[u]);
-                }
-            }
+            emit_products<WITH_VAL, U, ARRAY_SINK>(sink, pos, j, av, bv);
         }
         // short ranges, flat
         for (int q0 = 0; q0 < stot; q0 += G * U) {
@@ -325,13 +348,7 @@ __device__ __forceinline__ void group_products(int e0, int e1, int gt, EnumScrat
                     if constexpr (WITH_VAL) bv[u] = (double)Bval[pos[u]];
                 }
             }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                if (pos[u] >= 0) {
-                    if constexpr (WITH_VAL) sink(j[u], av[u] * bv[u]);
-                    else sink(j[u]);
-                }
-            }
+            emit_products<WITH_VAL, U, ARRAY_SINK>(sink, pos, j, av, bv);
         }
         group_sync<WG>();
     }
@@ -339,11 +356,11 @@ __device__ __forceinline__ void group_products(int e0, int e1, int gt, EnumScrat
 
 // ------------------------------------------------------------ LDS hashing
 
-// Claims the slot of `key` in an LDS key table; returns 1 if the key was new.
-__device__ __forceinline__ int lds_insert_key(int *keys, int logT, int key, int *err)
+// Claims the slot of `key` in an LDS key table, probing from slot h; returns
+// 1 if the key was new.
+__device__ __forceinline__ int lds_insert_key_at(int *keys, int logT, int key, unsigned h, int *err)
 {
     const unsigned mask = (1u << logT) - 1;
-    unsigned h = slot_of(key, logT);
     for (unsigned probe = 0; probe <= mask; ++probe) {
         int cur = __hip_atomic_load(&keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (cur == key) return 0;
@@ -358,12 +375,18 @@ __device__ __forceinline__ int lds_insert_key(int *keys, int logT, int key, int 
     return 0;
 }
 
-// Claims or finds the slot of `key` and adds `p` to its value (values are
-// accumulated in double: the LDS FP64 atomic add is the fast one on gfx950).
-__device__ __forceinline__ void lds_insert_add(int *keys, double *vals, int logT, int key, double p, int *err)
+__device__ __forceinline__ int lds_insert_key(int *keys, int logT, int key, int *err)
+{
+    return lds_insert_key_at(keys, logT, key, slot_of(key, logT), err);
+}
+
+// Claims or finds the slot of `key`, probing from slot h, and adds `p` to its
+// value (values are accumulated in double: the LDS FP64 atomic add is the
+// fast one on gfx950).
+__device__ __forceinline__ void lds_insert_add_at(int *keys, double *vals, int logT, int key, double p, unsigned h,
+                                                  int *err)
 {
     const unsigned mask = (1u << logT) - 1;
-    unsigned h = slot_of(key, logT);
     for (unsigned probe = 0; probe <= mask; ++probe) {
         int cur = __hip_atomic_load(&keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (cur == kEmpty) {
@@ -377,6 +400,70 @@ __device__ __forceinline__ void lds_insert_add(int *keys, double *vals, int logT
         h = (h + 1) & mask;
     }
     atomicOr(err, kErrProbe);
+}
+
+__device__ __forceinline__ void lds_insert_add(int *keys, double *vals, int logT, int key, double p, int *err)
+{
+    lds_insert_add_at(keys, vals, logT, key, p, slot_of(key, logT), err);
+}
+
+// U products of one thread at once: the first probe of every product is
+// issued before any result is used (one LDS round trip for all U, and one
+// for their claims of empty slots), so the common case -- the column is in
+// its home slot or claims it -- costs two round trips for U products
+// instead of two per product.  Products that meet another column continue
+// with linear probing one by one.  Two products of the same column in one
+// thread are safe: the second claim fails on the first one's key.
+template <int U>
+__device__ __forceinline__ void lds_insert_add_u(int *keys, double *vals, int logT, const int (&j)[U],
+                                                 const double (&p)[U], const bool (&ok)[U], int *err)
+{
+    const unsigned mask = (1u << logT) - 1;
+    unsigned h[U];
+    int cur[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        h[u] = slot_of(j[u], logT);
+        cur[u] = ok[u] ? __hip_atomic_load(&keys[h[u]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        if (ok[u] && cur[u] == kEmpty) {
+            const int old = atomicCAS(&keys[h[u]], kEmpty, j[u]);
+            cur[u] = old == kEmpty ? j[u] : old;
+        }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        if (!ok[u]) continue;
+        if (cur[u] == j[u]) atomicAdd(&vals[h[u]], p[u]);
+        else lds_insert_add_at(keys, vals, logT, j[u], p[u], (h[u] + 1) & mask, err);
+    }
+}
+
+// Key-only variant: returns how many of the U columns were new.
+template <int U>
+__device__ __forceinline__ int lds_insert_key_u(int *keys, int logT, const int (&j)[U], const bool (&ok)[U], int *err)
+{
+    const unsigned mask = (1u << logT) - 1;
+    unsigned h[U];
+    int cur[U];
+    int added = 0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        h[u] = slot_of(j[u], logT);
+        cur[u] = ok[u] ? __hip_atomic_load(&keys[h[u]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        if (ok[u] && cur[u] == kEmpty) {
+            const int old = atomicCAS(&keys[h[u]], kEmpty, j[u]);
+            if (old == kEmpty) ++added;
+            cur[u] = old == kEmpty ? j[u] : old;
+        }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        if (ok[u] && cur[u] != j[u]) added += lds_insert_key_at(keys, logT, j[u], (h[u] + 1) & mask, err);
+    return added;
 }
 
 // --------------------------------------------------------------- validation
@@ -579,14 +666,14 @@ __device__ __forceinline__ void sym_row(const int *__restrict__ Arp, const int *
     group_sync<WPR>();
     int mine = 0;
     if (active) {
-        group_products<float, false, G, 4>(
-            Arp[arow], Arp[arow + 1], gt, en, Bcol, (const float *)nullptr,
-            [&](int e, int &bs, int &bl, float &) {
-                const int k = Acol[e];
-                bs = Brp[k];
-                bl = Brp[k + 1] - bs;
-            },
-            [&](int j) { mine += lds_insert_key(keys, LOGT, j, err); });
+        auto get = [&](int e, int &bs, int &bl, float &) {
+            const int k = Acol[e];
+            bs = Brp[k];
+            bl = Brp[k + 1] - bs;
+        };
+        auto sink = [&](const int (&j)[4], const bool (&ok)[4]) { mine += lds_insert_key_u<4>(keys, LOGT, j, ok, err); };
+        group_products<float, false, G, 4, decltype(get), decltype(sink), true>(
+            Arp[arow], Arp[arow + 1], gt, en, Bcol, (const float *)nullptr, get, sink);
     }
     mine = wave_sum(mine);
     if (lane_id() == 0 && mine) atomicAdd(s_cnt, mine);
@@ -666,15 +753,17 @@ __device__ __forceinline__ void num_row(const int *__restrict__ Arp, const int *
     }
     group_sync<WPR>();
     if (active) {
-        group_products<V, true, G, 4>(
-            Arp[arow], Arp[arow + 1], gt, en, Bcol, Bval,
-            [&](int e, int &bs, int &bl, V &a) {
-                const int k = Acol[e];
-                bs = Brp[k];
-                bl = Brp[k + 1] - bs;
-                a = Aval[e];
-            },
-            [&](int j, double p) { lds_insert_add(keys, vals, LOGT, j, p, err); });
+        auto get = [&](int e, int &bs, int &bl, V &a) {
+            const int k = Acol[e];
+            bs = Brp[k];
+            bl = Brp[k + 1] - bs;
+            a = Aval[e];
+        };
+        auto sink = [&](const int (&j)[4], const double (&p)[4], const bool (&ok)[4]) {
+            lds_insert_add_u<4>(keys, vals, LOGT, j, p, ok, err);
+        };
+        group_products<V, true, G, 4, decltype(get), decltype(sink), true>(Arp[arow], Arp[arow + 1], gt, en, Bcol,
+                                                                            Bval, get, sink);
     }
     group_sync<WPR>();
     // compaction of the occupied slots to the front of the table
@@ -1070,15 +1159,17 @@ __global__ __launch_bounds__(THREADS) void k_num_seg(
     }
     for (int t = gt; t < words; t += THREADS) bm[t] = 0u;
     __syncthreads();
-    group_products<V, true, THREADS, 4>(
-        sg.e0, sg.e1, gt, S, Bcol, Bval,
-        [&](int e, int &bs, int &bl, V &a) {
-            const int k = Acol[e];
-            bs = split0[k * per];
-            bl = split1[k * per] - bs;
-            a = Aval[e];
-        },
-        [&](int j, double p) { lds_insert_add(keys, vals, LOGT, j, p, err); });
+    auto get = [&](int e, int &bs, int &bl, V &a) {
+        const int k = Acol[e];
+        bs = split0[k * per];
+        bl = split1[k * per] - bs;
+        a = Aval[e];
+    };
+    auto sink = [&](const int (&j)[4], const double (&p)[4], const bool (&ok)[4]) {
+        lds_insert_add_u<4>(keys, vals, LOGT, j, p, ok, err);
+    };
+    group_products<V, true, THREADS, 4, decltype(get), decltype(sink), true>(sg.e0, sg.e1, gt, S, Bcol, Bval, get,
+                                                                            sink);
     __syncthreads();
     int kr[SPT];
     double vr[SPT];
