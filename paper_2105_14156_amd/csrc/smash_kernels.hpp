@@ -205,6 +205,28 @@ struct EnumScratch {
     int wsum[2 * (G / kWave)];
 };
 
+// Loads the U products of one thread (column, and value in double) with no
+// branch between the loads, so all of them are in flight before the first is
+// used.  A product with pos < 0 is absent; it loads entry 0 of B, which
+// exists whenever the caller enumerates any product.
+template <typename V, bool WITH_VAL, int U>
+__device__ __forceinline__ void load_products(const int *__restrict__ Bcol, const V *__restrict__ Bval,
+                                              const int (&pos)[U], int (&j)[U], double (&bv)[U])
+{
+    V raw[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int q = pos[u] >= 0 ? pos[u] : 0;
+        j[u] = Bcol[q];
+        if constexpr (WITH_VAL) raw[u] = Bval[q];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        if constexpr (WITH_VAL) bv[u] = (double)raw[u];
+        else bv[u] = 0.0;
+    }
+}
+
 // Hands U loaded products of one thread to the sink: one call per product
 // (sink(j, a * b), or sink(j) without values), or with ARRAY_SINK one call
 // with all U (sink(j[U], p[U], ok[U]), or sink(j[U], ok[U])), so that the
@@ -307,15 +329,7 @@ __device__ __forceinline__ void group_products(int e0, int e1, int gt, EnumScrat
             }
             int j[U];
             double bv[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                j[u] = 0;
-                bv[u] = 0.0;
-                if (pos[u] >= 0) {
-                    j[u] = Bcol[pos[u]];
-                    if constexpr (WITH_VAL) bv[u] = (double)Bval[pos[u]];
-                }
-            }
+            load_products<V, WITH_VAL, U>(Bcol, Bval, pos, j, bv);
             emit_products<WITH_VAL, U, ARRAY_SINK>(sink, pos, j, av, bv);
         }
         // short ranges, flat
@@ -339,15 +353,7 @@ __device__ __forceinline__ void group_products(int e0, int e1, int gt, EnumScrat
             }
             int j[U];
             double bv[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                j[u] = 0;
-                bv[u] = 0.0;
-                if (pos[u] >= 0) {
-                    j[u] = Bcol[pos[u]];
-                    if constexpr (WITH_VAL) bv[u] = (double)Bval[pos[u]];
-                }
-            }
+            load_products<V, WITH_VAL, U>(Bcol, Bval, pos, j, bv);
             emit_products<WITH_VAL, U, ARRAY_SINK>(sink, pos, j, av, bv);
         }
         group_sync<WG>();
@@ -407,35 +413,28 @@ __device__ __forceinline__ void lds_insert_add(int *keys, double *vals, int logT
     lds_insert_add_at(keys, vals, logT, key, p, slot_of(key, logT), err);
 }
 
-// U products of one thread at once: the first probe of every product is
-// issued before any result is used (one LDS round trip for all U, and one
-// for their claims of empty slots), so the common case -- the column is in
-// its home slot or claims it -- costs two round trips for U products
-// instead of two per product.  Products that meet another column continue
-// with linear probing one by one.  Two products of the same column in one
-// thread are safe: the second claim fails on the first one's key.
+// U products of one thread at once, each starting with a compare-and-swap
+// of its home slot (empty -> column), all U issued before any result is
+// used: the CAS returns the slot's previous key, so one LDS round trip tells
+// whether the column was claimed (empty), is already there (its key), or
+// met another column (probing continues one product at a time from the next
+// slot).  Two products of the same column in one thread are safe: the
+// second CAS returns the first one's key.
 template <int U>
 __device__ __forceinline__ void lds_insert_add_u(int *keys, double *vals, int logT, const int (&j)[U],
                                                  const double (&p)[U], const bool (&ok)[U], int *err)
 {
     const unsigned mask = (1u << logT) - 1;
     unsigned h[U];
-    int cur[U];
+    int old[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-        h[u] = slot_of(j[u], logT);
-        cur[u] = ok[u] ? __hip_atomic_load(&keys[h[u]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : 0;
-    }
+    for (int u = 0; u < U; ++u) h[u] = slot_of(j[u], logT);
 #pragma unroll
-    for (int u = 0; u < U; ++u)
-        if (ok[u] && cur[u] == kEmpty) {
-            const int old = atomicCAS(&keys[h[u]], kEmpty, j[u]);
-            cur[u] = old == kEmpty ? j[u] : old;
-        }
+    for (int u = 0; u < U; ++u) old[u] = ok[u] ? atomicCAS(&keys[h[u]], kEmpty, j[u]) : j[u];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         if (!ok[u]) continue;
-        if (cur[u] == j[u]) atomicAdd(&vals[h[u]], p[u]);
+        if (old[u] == kEmpty || old[u] == j[u]) atomicAdd(&vals[h[u]], p[u]);
         else lds_insert_add_at(keys, vals, logT, j[u], p[u], (h[u] + 1) & mask, err);
     }
 }
@@ -446,23 +445,18 @@ __device__ __forceinline__ int lds_insert_key_u(int *keys, int logT, const int (
 {
     const unsigned mask = (1u << logT) - 1;
     unsigned h[U];
-    int cur[U];
+    int old[U];
     int added = 0;
 #pragma unroll
+    for (int u = 0; u < U; ++u) h[u] = slot_of(j[u], logT);
+#pragma unroll
+    for (int u = 0; u < U; ++u) old[u] = ok[u] ? atomicCAS(&keys[h[u]], kEmpty, j[u]) : j[u];
+#pragma unroll
     for (int u = 0; u < U; ++u) {
-        h[u] = slot_of(j[u], logT);
-        cur[u] = ok[u] ? __hip_atomic_load(&keys[h[u]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : 0;
+        if (!ok[u]) continue;
+        if (old[u] == kEmpty) ++added;
+        else if (old[u] != j[u]) added += lds_insert_key_at(keys, logT, j[u], (h[u] + 1) & mask, err);
     }
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-        if (ok[u] && cur[u] == kEmpty) {
-            const int old = atomicCAS(&keys[h[u]], kEmpty, j[u]);
-            if (old == kEmpty) ++added;
-            cur[u] = old == kEmpty ? j[u] : old;
-        }
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-        if (ok[u] && cur[u] != j[u]) added += lds_insert_key_at(keys, logT, j[u], (h[u] + 1) & mask, err);
     return added;
 }
 
@@ -961,7 +955,7 @@ __global__ __launch_bounds__(kSymHeavyThreads) void k_sym_heavy(
     const int *__restrict__ split1 = Bsplit + c1;
     for (int t = gt; t < WORDS; t += G) bm[t] = 0u;
     __syncthreads();
-    group_products<float, false, G, 4>(
+    group_products<float, false, G, 8>(
         Arp[row], Arp[row + 1], gt, S, Bcol, (const float *)nullptr,
         [&](int e, int &bs, int &bl, float &) {
             const int k = Acol[e];
@@ -1165,10 +1159,10 @@ __global__ __launch_bounds__(THREADS) void k_num_seg(
         bl = split1[k * per] - bs;
         a = Aval[e];
     };
-    auto sink = [&](const int (&j)[4], const double (&p)[4], const bool (&ok)[4]) {
-        lds_insert_add_u<4>(keys, vals, LOGT, j, p, ok, err);
+    auto sink = [&](const int (&j)[2], const double (&p)[2], const bool (&ok)[2]) {
+        lds_insert_add_u<2>(keys, vals, LOGT, j, p, ok, err);
     };
-    group_products<V, true, THREADS, 4, decltype(get), decltype(sink), true>(sg.e0, sg.e1, gt, S, Bcol, Bval, get,
+    group_products<V, true, THREADS, 2, decltype(get), decltype(sink), true>(sg.e0, sg.e1, gt, S, Bcol, Bval, get,
                                                                             sink);
     __syncthreads();
     int kr[SPT];
@@ -1254,7 +1248,7 @@ __global__ __launch_bounds__(kDenseThreads) void k_num_dense(
     const int *__restrict__ split1 = split0 + 1;
     for (int t = gt; t < kChunkCols; t += kDenseThreads) acc[t] = -0.0;
     __syncthreads();
-    group_products<V, true, kDenseThreads, 4>(
+    group_products<V, true, kDenseThreads, 2>(
         sg.e0, sg.e1, gt, S, Bcol, Bval,
         [&](int e, int &bs, int &bl, V &a) {
             const int k = Acol[e];
