@@ -268,7 +268,8 @@ __device__ __forceinline__ void emit_products(Sink &sink, const int (&pos)[U], c
 // q = gt, gt + G, ... and finds its A entry by binary search (consecutive
 // lanes then read consecutive B entries where a range continues).  U products
 // per thread are located and loaded before any is merged.
-template <typename V, bool WITH_VAL, int G, int U, typename Get, typename Sink, bool ARRAY_SINK = false>
+template <typename V, bool WITH_VAL, int G, int U, typename Get, typename Sink, bool ARRAY_SINK = false,
+          bool PIPELINE = false>
 __device__ __forceinline__ void group_products(int e0, int e1, int gt, EnumScratch<V, G> &S,
                                                const int *__restrict__ Bcol, const V *__restrict__ Bval,
                                                Get get, Sink sink)
@@ -304,14 +305,14 @@ __device__ __forceinline__ void group_products(int e0, int e1, int gt, EnumScrat
         if constexpr (WITH_VAL) S.a[gt] = a;
         group_sync<WG>();
         const int ptot = S.pincl[G - 1], stot = S.sincl[G - 1];
-        // long ranges, piece by piece
-        for (int pc0 = wg * U; pc0 < ptot; pc0 += WG * U) {
+        // long ranges, piece by piece: wave wg takes U consecutive pieces per
+        // round; with PIPELINE the pieces of the next round are located (LDS
+        // searches) while the loads of this round are in flight
+        auto locate_pieces = [&](int pc0, int (&pos)[U], double (&av)[U]) {
             int src = 0;
 #pragma unroll
             for (int step = G / 2; step > 0; step >>= 1)
                 if (S.pincl[src + step - 1] <= pc0) src += step;
-            int pos[U];
-            double av[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int pc = pc0 + u;
@@ -327,15 +328,36 @@ __device__ __forceinline__ void group_products(int e0, int e1, int gt, EnumScrat
                     }
                 }
             }
-            int j[U];
-            double bv[U];
-            load_products<V, WITH_VAL, U>(Bcol, Bval, pos, j, bv);
-            emit_products<WITH_VAL, U, ARRAY_SINK>(sink, pos, j, av, bv);
-        }
-        // short ranges, flat
-        for (int q0 = 0; q0 < stot; q0 += G * U) {
+        };
+        {
             int pos[U];
             double av[U];
+            int pc0 = wg * U;
+            if constexpr (PIPELINE)
+                if (pc0 < ptot) locate_pieces(pc0, pos, av);
+            for (; pc0 < ptot; pc0 += WG * U) {
+                int j[U];
+                double bv[U];
+                if constexpr (!PIPELINE) locate_pieces(pc0, pos, av);
+                load_products<V, WITH_VAL, U>(Bcol, Bval, pos, j, bv);
+                int posn[U];
+                double avn[U];
+                if constexpr (PIPELINE)
+                    if (pc0 + WG * U < ptot) locate_pieces(pc0 + WG * U, posn, avn);
+                emit_products<WITH_VAL, U, ARRAY_SINK>(sink, pos, j, av, bv);
+                if constexpr (!PIPELINE) continue;
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    pos[u] = posn[u];
+                    av[u] = avn[u];
+                }
+            }
+        }
+        // short ranges, flat: thread gt takes products q = q0 + u * G + gt
+        // and finds its A entry by binary search (consecutive lanes then read
+        // consecutive B entries where a range continues); with PIPELINE the
+        // next round is located while this round's loads are in flight
+        auto locate_flat = [&](int q0, int (&pos)[U], double (&av)[U]) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int q = q0 + u * G + gt;
@@ -351,10 +373,29 @@ __device__ __forceinline__ void group_products(int e0, int e1, int gt, EnumScrat
                     if constexpr (WITH_VAL) av[u] = (double)S.a[src];
                 }
             }
-            int j[U];
-            double bv[U];
-            load_products<V, WITH_VAL, U>(Bcol, Bval, pos, j, bv);
-            emit_products<WITH_VAL, U, ARRAY_SINK>(sink, pos, j, av, bv);
+        };
+        {
+            int pos[U];
+            double av[U];
+            if constexpr (PIPELINE)
+                if (stot > 0) locate_flat(0, pos, av);
+            for (int q0 = 0; q0 < stot; q0 += G * U) {
+                int j[U];
+                double bv[U];
+                if constexpr (!PIPELINE) locate_flat(q0, pos, av);
+                load_products<V, WITH_VAL, U>(Bcol, Bval, pos, j, bv);
+                int posn[U];
+                double avn[U];
+                if constexpr (PIPELINE)
+                    if (q0 + G * U < stot) locate_flat(q0 + G * U, posn, avn);
+                emit_products<WITH_VAL, U, ARRAY_SINK>(sink, pos, j, av, bv);
+                if constexpr (!PIPELINE) continue;
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    pos[u] = posn[u];
+                    av[u] = avn[u];
+                }
+            }
         }
         group_sync<WG>();
     }
@@ -1248,15 +1289,15 @@ __global__ __launch_bounds__(kDenseThreads) void k_num_dense(
     const int *__restrict__ split1 = split0 + 1;
     for (int t = gt; t < kChunkCols; t += kDenseThreads) acc[t] = -0.0;
     __syncthreads();
-    group_products<V, true, kDenseThreads, 2>(
-        sg.e0, sg.e1, gt, S, Bcol, Bval,
-        [&](int e, int &bs, int &bl, V &a) {
-            const int k = Acol[e];
-            bs = split0[k * per];
-            bl = split1[k * per] - bs;
-            a = Aval[e];
-        },
-        [&](int j, double p) { atomicAdd(&acc[j - lo], p + 0.0); });
+    auto get = [&](int e, int &bs, int &bl, V &a) {
+        const int k = Acol[e];
+        bs = split0[k * per];
+        bl = split1[k * per] - bs;
+        a = Aval[e];
+    };
+    auto sink = [&](int j, double p) { atomicAdd(&acc[j - lo], p + 0.0); };
+    group_products<V, true, kDenseThreads, 2, decltype(get), decltype(sink), false, true>(sg.e0, sg.e1, gt, S, Bcol,
+                                                                                          Bval, get, sink);
     __syncthreads();
     double vr[ROUNDS];
     unsigned long long msk[ROUNDS];
