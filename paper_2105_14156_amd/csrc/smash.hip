@@ -282,7 +282,7 @@ smash_status launch_num_bin(smash_ctx c, hipStream_t s, const Plan &p, int cnt, 
     return launch(c, K_NUM_ROWS, s, [&] {
         k_num_rows<V, LOGT, S::WPR, S::RPW><<<blocks_for(cnt, S::RPW), S::THREADS, 0, s>>>(
             p.A.row_ptr, p.A.col_idx, Aval, p.B.row_ptr, p.B.col_idx, Bval, rows, cnt, (const long long *)crp, ccol,
-            cval, &c->d_hdr->error);
+            cval, (int)p.n, &c->d_hdr->error);
     });
 }
 

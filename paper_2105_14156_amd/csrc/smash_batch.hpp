@@ -166,7 +166,7 @@ __global__ __launch_bounds__(kWave *WPR *RPW) void k_bnum_rows(const BatchDesc *
         const BatchDesc &d = desc[active ? prob[grow] : 0];
         num_row<V, LOGT, WPR>(d.Arp, d.Acol, (const V *)d.Aval, d.Brp, d.Bcol, (const V *)d.Bval,
                               (int)(grow - d.row0), grow, active, gt, s_keys[g], s_vals[g], s_en[g], s_scan[g], Crp,
-                              Ccol, Cval, err);
+                              Ccol, Cval, d.cols, err);
         group_sync<WPR>();
     }
 }

@@ -767,15 +767,18 @@ __device__ __forceinline__ void group_bitonic(int *keys, V *vals, int n2, int gt
 
 // Numeric pass of one light row by a group of WPR waves (steps a5 and a7):
 // the products of A row `arow` times B merged in an LDS tag/value table of
-// 2^LOGT slots, the occupied slots compacted, sorted by column and written
-// at C's row `crow`.
+// 2^LOGT slots, then written in column order at C's row `crow`.  When B has
+// at most 64 * 2^LOGT columns the order comes from ranks in an occupancy
+// bitmap over all of B's columns, built in the table's own LDS once its
+// entries are in registers (no sort); otherwise the occupied slots are
+// compacted and sorted (bitonic).
 template <typename V, int LOGT, int WPR>
 __device__ __forceinline__ void num_row(const int *__restrict__ Arp, const int *__restrict__ Acol,
                                         const V *__restrict__ Aval, const int *__restrict__ Brp,
                                         const int *__restrict__ Bcol, const V *__restrict__ Bval, int arow,
                                         long long crow, bool active, int gt, int *keys, double *vals,
                                         EnumScratch<V, WPR * kWave> &en, int *s_scan, const long long *__restrict__ Crp,
-                                        int *__restrict__ Ccol, V *__restrict__ Cval, int *err)
+                                        int *__restrict__ Ccol, V *__restrict__ Cval, int ncols, int *err)
 {
     constexpr int T = 1 << LOGT;
     constexpr int G = WPR * kWave;
@@ -820,20 +823,75 @@ __device__ __forceinline__ void num_row(const int *__restrict__ Arp, const int *
         if (w < wg) wbase += t;
         total += t;
     }
-    int pos = wbase + incl - cnt;
     group_sync<WPR>();
+    if (ncols <= 64 * T) {
+        // bitmap over B's columns in the value area (2T words), prefix of its
+        // popcounts per group of 8 words in the key area; then every entry's
+        // rank, and the entries staged in rank order for coalesced stores
+        unsigned *bm = reinterpret_cast<unsigned *>(vals);
+        int *pref = keys;
+        const int W = (ncols + 31) >> 5;
+        const int NGR = (W + 7) >> 3;
+        for (int t = gt; t < NGR * 8; t += G) bm[t] = 0u;
+        group_sync<WPR>();
 #pragma unroll
-    for (int s = 0; s < SPT; ++s) {
-        if (kr[s] != kEmpty) {
-            keys[pos] = kr[s];
-            vals[pos] = vr[s];
-            ++pos;
+        for (int s = 0; s < SPT; ++s)
+            if (kr[s] != kEmpty) atomicOr(&bm[kr[s] >> 5], 1u << (kr[s] & 31));
+        group_sync<WPR>();
+        int run = 0;
+        for (int g0 = 0; g0 < NGR; g0 += G) {
+            const int gi = g0 + gt;
+            int pc = 0;
+            if (gi < NGR)
+#pragma unroll
+                for (int q = 0; q < 8; ++q) pc += __popc(bm[gi * 8 + q]);
+            const int inc = wave_incl_scan(pc);
+            if (lane == kWave - 1) s_scan[wg] = inc;
+            group_sync<WPR>();
+            int wb = 0, tot = 0;
+            for (int w = 0; w < WPR; ++w) {
+                const int t = s_scan[w];
+                if (w < wg) wb += t;
+                tot += t;
+            }
+            if (gi < NGR) pref[gi] = run + wb + inc - pc;
+            run += tot;
+            group_sync<WPR>();
         }
+        int rk[SPT];
+#pragma unroll
+        for (int s = 0; s < SPT; ++s) {
+            rk[s] = -1;
+            if (kr[s] != kEmpty) {
+                const int j = kr[s], w = j >> 5;
+                int r = pref[w >> 3];
+                for (int q = w & ~7; q < w; ++q) r += __popc(bm[q]);
+                rk[s] = r + __popc(bm[w] & ((1u << (j & 31)) - 1u));
+            }
+        }
+        group_sync<WPR>();
+#pragma unroll
+        for (int s = 0; s < SPT; ++s)
+            if (rk[s] >= 0 && rk[s] < T) {
+                keys[rk[s]] = kr[s];
+                vals[rk[s]] = vr[s];
+            }
+    } else {
+        int pos = wbase + incl - cnt;
+#pragma unroll
+        for (int s = 0; s < SPT; ++s) {
+            if (kr[s] != kEmpty) {
+                keys[pos] = kr[s];
+                vals[pos] = vr[s];
+                ++pos;
+            }
+        }
+        const int n2 = total <= 1 ? 1 : (1 << ceil_log2(total));
+        for (int t = total + gt; t < n2; t += G) keys[t] = 0x7fffffff;
+        group_sync<WPR>();
+        group_bitonic<double, WPR>(keys, vals, n2, gt);
     }
-    const int n2 = total <= 1 ? 1 : (1 << ceil_log2(total));
-    for (int t = total + gt; t < n2; t += G) keys[t] = 0x7fffffff;
     group_sync<WPR>();
-    group_bitonic<double, WPR>(keys, vals, n2, gt);
     if (active) {
         const long long rb = Crp[crow];
         const int nc = (int)(Crp[crow + 1] - rb);
@@ -852,7 +910,7 @@ __global__ __launch_bounds__(kWave *WPR *RPW) void k_num_rows(
     const int *__restrict__ Arp, const int *__restrict__ Acol, const V *__restrict__ Aval,
     const int *__restrict__ Brp, const int *__restrict__ Bcol, const V *__restrict__ Bval,
     const int *__restrict__ rows, int nrows, const long long *__restrict__ Crp, int *__restrict__ Ccol,
-    V *__restrict__ Cval, int *err)
+    V *__restrict__ Cval, int ncols, int *err)
 {
     static_assert(RPW == 1 || WPR == 1, "multi-row blocks use one wave per row");
     constexpr int T = 1 << LOGT;
@@ -867,7 +925,7 @@ __global__ __launch_bounds__(kWave *WPR *RPW) void k_num_rows(
     const bool active = r < nrows;
     const int row = active ? rows[r] : 0;
     num_row<V, LOGT, WPR>(Arp, Acol, Aval, Brp, Bcol, Bval, row, row, active, gt, s_keys[g], s_vals[g], s_en[g],
-                          s_scan[g], Crp, Ccol, Cval, err);
+                          s_scan[g], Crp, Ccol, Cval, ncols, err);
 }
 
 // ---------------------------------------------------------------- row scan
