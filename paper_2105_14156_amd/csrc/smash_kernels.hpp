@@ -1063,7 +1063,8 @@ __global__ __launch_bounds__(kSymHeavyThreads) void k_sym_heavy(
         },
         [&](int j) {
             const int jl = j - lo;
-            atomicOr(&bm[jl >> 5], 1u << (jl & 31));
+            const unsigned bit = 1u << (jl & 31);
+            if (!(bm[jl >> 5] & bit)) atomicOr(&bm[jl >> 5], bit);     // most repeats skip the atomic
         });
     __syncthreads();
     // per-chunk counts: one wave per chunk
