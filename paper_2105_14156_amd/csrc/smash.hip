@@ -406,7 +406,7 @@ smash_status launch_fused_bin(smash_ctx c, hipStream_t s, const Plan &p, int cnt
     return launch(c, K_FUSED_ROWS, s, [&] {
         k_fused_rows<V, LOGT, S::WPR, S::RPW><<<blocks_for(cnt, S::RPW), S::THREADS, 0, s>>>(
             p.A.row_ptr, p.A.col_idx, (const V *)p.A.val, p.B.row_ptr, p.B.col_idx, (const V *)p.B.val, rows, cnt,
-            p.fcap, p.stage_off, p.stage_col, (V *)p.stage_val, p.nnzc, p.fstatus);
+            p.fcap, p.stage_off, p.stage_col, (V *)p.stage_val, p.nnzc, p.fstatus, (int)p.n);
     });
 }
 
@@ -431,10 +431,9 @@ smash_status read_hdr(smash_ctx c, hipStream_t s);
 // The fused stage of smash_spgemm_fused: features, predicted capacities,
 // fused bins, staging offsets, the fused kernels, and removal of the rows
 // they completed from the two-phase plan.
-smash_status fused_stage(smash_ctx c, hipStream_t s, Plan &p)
+smash_status fused_alloc(smash_ctx c, hipStream_t s, Plan &p)
 {
     const int m = (int)p.m;
-    const size_t vb = p.fused_dtype == SMASH_F32 ? 4 : 8;
     const size_t need = carve_size({(size_t)m * kFeat * 4, (size_t)m * 4, (size_t)m * 4, (size_t)m * 4,
                                     (size_t)m * 4, (size_t)m, (size_t)m, (size_t)(m + 1) * 8});
     TRY(ensure(c, c->fused_mem, need, s));
@@ -447,13 +446,16 @@ smash_status fused_stage(smash_ctx c, hipStream_t s, Plan &p)
     p.fbin = cv.take<unsigned char>(m);
     p.fstatus = cv.take<unsigned char>(m);
     p.stage_off = cv.take<long long>(m + 1);
+    return SMASH_OK;
+}
+
+smash_status fused_stage(smash_ctx c, hipStream_t s, Plan &p)
+{
+    const int m = (int)p.m;
+    const size_t vb = p.fused_dtype == SMASH_F32 ? 4 : 8;
     const float *prm = (const float *)c->pred_mem.ptr;
     const bool learned = c->opt[SMASH_OPT_FUSED_SIZING] == 0;
-    if (learned) {
-        TRY(launch(c, K_FEATURES, s, [&] {
-            k_features<<<blocks_for(m, 4), 256, 0, s>>>(m, (int)p.n, p.A.row_ptr, p.A.col_idx, p.B.row_ptr, p.feats,
-                                                        nullptr, p.maxb);
-        }));
+    if (learned) {      // the features came with the analysis
         TRY(launch(c, K_MLP_PREDICT, s, [&] {
             k_mlp_predict<<<blocks_for(m, 256), 256, 0, s>>>(m, (int)p.n, p.feats, prm, prm + kParams,
                                                              c->pred_delta, p.ub, p.maxb, nullptr, p.cap_pred);
@@ -693,10 +695,14 @@ smash_status symbolic_impl(smash_ctx c, const smash_csr *A, const smash_csr *B, 
         }
     }
 
-    // a1/a2: products per row, bins, rows grouped by bin
+    // a1/a2: products per row (and the predictor's features for the fused
+    // pass), bins, rows grouped by bin
+    const bool learned = fuse && c->opt[SMASH_OPT_FUSED_SIZING] == 0;
+    if (fuse) TRY(fused_alloc(c, s, p));
     TRY(launch(c, K_ANALYZE, s, [&] {
         k_analyze<<<blocks_for(m, 4), 256, 0, s>>>((int)m, (int)p.n, p.lds_row_max, A->row_ptr, A->col_idx, B->row_ptr,
-                                                   p.ub, p.cap, p.nnzc, p.sym_bin);
+                                                   p.ub, p.cap, p.nnzc, p.sym_bin, learned ? p.feats : nullptr,
+                                                   learned ? p.maxb : nullptr);
     }));
     if (fuse) TRY(fused_stage(c, s, p));
     TRY(bin_rows(c, s, p, p.sym_bin, p.ub, nullptr, &c->d_hdr->sym, p.sym_perm, global ? p.cap : nullptr));

@@ -30,46 +30,60 @@ __global__ __launch_bounds__(256) void k_fused_bins(int m, const long long *__re
     fcap[i] = fused ? c : 0;
 }
 
-// Like lds_insert_add, but a row stops inserting once it holds more distinct
-// columns than its capacity (*ndist counts them, *abort is raised): the
-// table then stays at most about half full, so probes stay short even when
-// the prediction was far too small.
-__device__ __forceinline__ void lds_bounded_insert_add(int *keys, double *vals, int logT, int key, double p,
-                                                       int cap, int *ndist, int *abort)
+// Like lds_insert_add_u, but a row stops inserting once it holds more
+// distinct columns than its capacity (*ndist counts them, *abort is
+// raised): the table then stays at most about half full, so probes stay
+// short however wrong the prediction was.
+template <int U>
+__device__ __forceinline__ void lds_bounded_insert_add_u(int *keys, double *vals, int logT, const int (&j)[U],
+                                                         const double (&p)[U], const bool (&okin)[U], int cap,
+                                                         int *ndist, int *abort)
 {
     if (__hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) return;
     const unsigned mask = (1u << logT) - 1;
-    unsigned h = slot_of(key, logT);
-    for (unsigned probe = 0; probe <= mask; ++probe) {
-        int cur = __hip_atomic_load(&keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (cur == kEmpty) {
-            const int old = atomicCAS(&keys[h], kEmpty, key);
-            if (old == kEmpty) {
-                atomicAdd(&vals[h], p);
+    unsigned h[U];
+    int old[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) h[u] = slot_of(j[u], logT);
+#pragma unroll
+    for (int u = 0; u < U; ++u) old[u] = okin[u] ? atomicCAS(&keys[h[u]], kEmpty, j[u]) : j[u];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        if (!okin[u]) continue;
+        unsigned hh = h[u];
+        int cur = old[u];
+        for (unsigned probe = 0;; ++probe) {
+            if (cur == kEmpty) {                    // claimed a new slot
+                atomicAdd(&vals[hh], p[u]);
                 if (atomicAdd(ndist, 1) >= cap) atomicExch(abort, 1);
-                return;
+                break;
             }
-            cur = old;
+            if (cur == j[u]) {
+                atomicAdd(&vals[hh], p[u]);
+                break;
+            }
+            if (probe >= mask) {                    // unreachable while cap <= T / 2
+                atomicExch(abort, 1);
+                break;
+            }
+            hh = (hh + 1) & mask;
+            cur = atomicCAS(&keys[hh], kEmpty, j[u]);
         }
-        if (cur == key) {
-            atomicAdd(&vals[h], p);
-            return;
-        }
-        h = (h + 1) & mask;
     }
-    atomicExch(abort, 1);    // unreachable while cap <= T / 2
 }
 
 // Fused rows: products merged in an LDS table of 2^LOGT slots; a row whose
-// columns fit its capacity is compacted, sorted and written to the staging
-// area at stage_off[row] (status 1, nnzc = count); otherwise status 0 and
-// the row is left to the two-phase path.
+// columns fit its capacity is put in column order (bitmap ranks or sort, as
+// for the rows of the two-phase path) and written to the staging area at
+// stage_off[row] (status 1, nnzc = count); otherwise status 0 and the row is
+// left to the two-phase path.
 template <typename V, int LOGT, int WPR, int RPW>
 __global__ __launch_bounds__(kWave *WPR *RPW) void k_fused_rows(
     const int *__restrict__ Arp, const int *__restrict__ Acol, const V *__restrict__ Aval,
     const int *__restrict__ Brp, const int *__restrict__ Bcol, const V *__restrict__ Bval,
     const int *__restrict__ rows, int nrows, const int *__restrict__ fcap, const long long *__restrict__ stage_off,
-    int *__restrict__ scol, V *__restrict__ sval, int *__restrict__ nnzc, unsigned char *__restrict__ status)
+    int *__restrict__ scol, V *__restrict__ sval, int *__restrict__ nnzc, unsigned char *__restrict__ status,
+    int ncols)
 {
     static_assert(RPW == 1 || WPR == 1, "multi-row blocks use one wave per row");
     constexpr int T = 1 << LOGT;
@@ -100,15 +114,17 @@ __global__ __launch_bounds__(kWave *WPR *RPW) void k_fused_rows(
     const int cap = active ? fcap[row] : 0;
     group_sync<WPR>();
     if (active) {
-        group_products<V, true, G, 4>(
-            Arp[row], Arp[row + 1], gt, s_en[g], Bcol, Bval,
-            [&](int e, int &bs, int &bl, V &a) {
-                const int k = Acol[e];
-                bs = Brp[k];
-                bl = Brp[k + 1] - bs;
-                a = Aval[e];
-            },
-            [&](int j, double p) { lds_bounded_insert_add(keys, vals, LOGT, j, p, cap, &s_ndist[g], &s_full[g]); });
+        auto get = [&](int e, int &bs, int &bl, V &a) {
+            const int k = Acol[e];
+            bs = Brp[k];
+            bl = Brp[k + 1] - bs;
+            a = Aval[e];
+        };
+        auto sink = [&](const int (&j)[4], const double (&p)[4], const bool (&ok)[4]) {
+            lds_bounded_insert_add_u<4>(keys, vals, LOGT, j, p, ok, cap, &s_ndist[g], &s_full[g]);
+        };
+        group_products<V, true, G, 4, decltype(get), decltype(sink), true>(Arp[row], Arp[row + 1], gt, s_en[g], Bcol,
+                                                                            Bval, get, sink);
     }
     group_sync<WPR>();
     int kr[SPT];
@@ -130,20 +146,7 @@ __global__ __launch_bounds__(kWave *WPR *RPW) void k_fused_rows(
         total += t;
     }
     const bool ok = active && !s_full[g] && total <= cap;
-    int pos = wbase + incl - cnt;
-    group_sync<WPR>();
-#pragma unroll
-    for (int s = 0; s < SPT; ++s) {
-        if (kr[s] != kEmpty) {
-            keys[pos] = kr[s];
-            vals[pos] = vr[s];
-            ++pos;
-        }
-    }
-    const int n2 = total <= 1 ? 1 : (1 << ceil_log2(total));
-    for (int t = total + gt; t < n2; t += G) keys[t] = 0x7fffffff;
-    group_sync<WPR>();
-    if (ok) group_bitonic<double, WPR>(keys, vals, n2, gt);
+    order_row_entries<T, WPR, SPT>(kr, vr, keys, vals, s_scan[g], total, wbase, incl, cnt, ncols, gt);
     if (active) {
         if (ok) {
             const long long o = stage_off[row];
@@ -159,16 +162,22 @@ __global__ __launch_bounds__(kWave *WPR *RPW) void k_fused_rows(
     }
 }
 
-// Rows completed by the fused pass leave the two-phase plan.
+// Rows completed by the fused pass leave the two-phase plan (one global
+// atomic per block for their count).
 __global__ __launch_bounds__(256) void k_fused_mark(int m, const unsigned char *__restrict__ fbin,
                                                     const unsigned char *__restrict__ status,
                                                     unsigned char *__restrict__ sym_bin, int *fused_ok)
 {
+    __shared__ int s_ok;
+    if (threadIdx.x == 0) s_ok = 0;
+    __syncthreads();
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const bool done = i < m && fbin[i] != kBinEmpty && status[i] == 1;
     if (done) sym_bin[i] = kBinEmpty;
     const unsigned long long b = __ballot(done);
-    if (lane_id() == 0 && b) atomicAdd(fused_ok, (int)__popcll(b));
+    if (lane_id() == 0 && b) atomicAdd(&s_ok, (int)__popcll(b));
+    __syncthreads();
+    if (threadIdx.x == 0 && s_ok) atomicAdd(fused_ok, s_ok);
 }
 
 // Copies the staged rows of the fused pass to their final offsets in C

@@ -530,23 +530,59 @@ __global__ __launch_bounds__(256) void k_validate(int rows, int cols, long long 
 
 // Row analysis (step a1): products ub_i = sum_k nnz(B_k) over row i of A, the
 // output bound cap_i = min(ub_i, cols) and the row's symbolic bin.  One wave
-// per row, four rows per block.
+// per row, four rows per block.  With feats non-NULL it also writes the
+// learned predictor's six features and max_k nnz(B_k) (maxb_out).
 __global__ __launch_bounds__(256) void k_analyze(int m, int ncols, int lds_row_max,
                                                  const int *__restrict__ Arp, const int *__restrict__ Acol,
                                                  const int *__restrict__ Brp, long long *__restrict__ ub_out,
                                                  int *__restrict__ cap_out, int *__restrict__ nnzc,
-                                                 unsigned char *__restrict__ bin_out)
+                                                 unsigned char *__restrict__ bin_out, float *__restrict__ feats,
+                                                 int *__restrict__ maxb_out)
 {
     const int lane = lane_id();
     const int row = blockIdx.x * 4 + threadIdx.x / kWave;
     if (row >= m) return;
     const int e0 = Arp[row], e1 = Arp[row + 1];
     long long ub = 0;
+    double sq = 0.0;
+    int mx = 0, mn = 0x7fffffff;
     for (int e = e0 + lane; e < e1; e += kWave) {
         const int k = Acol[e];
-        ub += Brp[k + 1] - Brp[k];
+        const int len = Brp[k + 1] - Brp[k];
+        ub += len;
+        if (feats) {
+            sq += (double)len * (double)len;
+            mx = len > mx ? len : mx;
+            mn = len < mn ? len : mn;
+        }
     }
     ub = wave_sum(ub);
+    if (feats) {
+        // the predictor's six features (the same arithmetic as k_features)
+        sq = wave_sum(sq);
+#pragma unroll
+        for (int d = kWave / 2; d > 0; d >>= 1) {
+            const int a = __shfl_xor(mx, d, kWave), b = __shfl_xor(mn, d, kWave);
+            mx = a > mx ? a : mx;
+            mn = b < mn ? b : mn;
+        }
+        if (lane == 0) {
+            const int na = e1 - e0;
+            float *f = feats + (long long)row * 6;
+            if (na == 0) {
+                for (int t = 0; t < 6; ++t) f[t] = 0.f;
+            } else {
+                const double capd = ub < ncols ? (double)ub : (double)ncols;
+                f[0] = log2f(1.f + (float)na);
+                f[1] = (float)log2(1.0 + (double)ub);
+                f[2] = log2f(1.f + (float)mx);
+                f[3] = log2f(1.f + (float)mn);
+                f[4] = (float)log2(1.0 + capd);
+                f[5] = (float)log2(1.0 + (ub > 0 ? sq / (double)ub : 0.0));
+            }
+            maxb_out[row] = na ? mx : 0;
+        }
+    }
     if (lane == 0) {
         const int cap = (int)(ub < ncols ? ub : ncols);
         int b;
@@ -765,64 +801,20 @@ __device__ __forceinline__ void group_bitonic(int *keys, V *vals, int n2, int gt
     }
 }
 
-// Numeric pass of one light row by a group of WPR waves (steps a5 and a7):
-// the products of A row `arow` times B merged in an LDS tag/value table of
-// 2^LOGT slots, then written in column order at C's row `crow`.  When B has
-// at most 64 * 2^LOGT columns the order comes from ranks in an occupancy
-// bitmap over all of B's columns, built in the table's own LDS once its
-// entries are in registers (no sort); otherwise the occupied slots are
-// compacted and sorted (bitonic).
-template <typename V, int LOGT, int WPR>
-__device__ __forceinline__ void num_row(const int *__restrict__ Arp, const int *__restrict__ Acol,
-                                        const V *__restrict__ Aval, const int *__restrict__ Brp,
-                                        const int *__restrict__ Bcol, const V *__restrict__ Bval, int arow,
-                                        long long crow, bool active, int gt, int *keys, double *vals,
-                                        EnumScratch<V, WPR * kWave> &en, int *s_scan, const long long *__restrict__ Crp,
-                                        int *__restrict__ Ccol, V *__restrict__ Cval, int ncols, int *err)
+// Puts the entries of a row's table in column order at the front of the
+// table (keys[0 .. total), vals[0 .. total)).  kr/vr hold each thread's SPT
+// slots of the table (kEmpty where free), cnt/incl/wbase their count, its
+// inclusive wave prefix and the wave's offset in the group; every thread of
+// the group calls it.  With B at most 64 T columns wide the order comes from
+// ranks in an occupancy bitmap over B's columns built in the table's own LDS;
+// otherwise the entries are compacted and sorted (bitonic).
+template <int T, int WPR, int SPT>
+__device__ __forceinline__ void order_row_entries(const int (&kr)[SPT], const double (&vr)[SPT], int *keys,
+                                                  double *vals, int *s_scan, int total, int wbase, int incl, int cnt,
+                                                  int ncols, int gt)
 {
-    constexpr int T = 1 << LOGT;
     constexpr int G = WPR * kWave;
-    constexpr int SPT = T / G;          // slots per thread in the compaction
-    static_assert(SPT >= 1, "table smaller than its group");
     const int lane = lane_id(), wg = gt / kWave;
-    for (int t = gt; t < T; t += G) {
-        keys[t] = kEmpty;
-        vals[t] = 0.0;
-    }
-    group_sync<WPR>();
-    if (active) {
-        auto get = [&](int e, int &bs, int &bl, V &a) {
-            const int k = Acol[e];
-            bs = Brp[k];
-            bl = Brp[k + 1] - bs;
-            a = Aval[e];
-        };
-        auto sink = [&](const int (&j)[4], const double (&p)[4], const bool (&ok)[4]) {
-            lds_insert_add_u<4>(keys, vals, LOGT, j, p, ok, err);
-        };
-        group_products<V, true, G, 4, decltype(get), decltype(sink), true>(Arp[arow], Arp[arow + 1], gt, en, Bcol,
-                                                                            Bval, get, sink);
-    }
-    group_sync<WPR>();
-    // compaction of the occupied slots to the front of the table
-    int kr[SPT];
-    double vr[SPT];
-    int cnt = 0;
-#pragma unroll
-    for (int s = 0; s < SPT; ++s) {
-        kr[s] = keys[gt * SPT + s];
-        vr[s] = vals[gt * SPT + s];
-        cnt += kr[s] != kEmpty;
-    }
-    const int incl = wave_incl_scan(cnt);
-    if (lane == kWave - 1) s_scan[wg] = incl;
-    group_sync<WPR>();
-    int wbase = 0, total = 0;
-    for (int w = 0; w < WPR; ++w) {
-        const int t = s_scan[w];
-        if (w < wg) wbase += t;
-        total += t;
-    }
     group_sync<WPR>();
     if (ncols <= 64 * T) {
         // bitmap over B's columns in the value area (2T words), prefix of its
@@ -892,6 +884,67 @@ __device__ __forceinline__ void num_row(const int *__restrict__ Arp, const int *
         group_bitonic<double, WPR>(keys, vals, n2, gt);
     }
     group_sync<WPR>();
+}
+
+// Numeric pass of one light row by a group of WPR waves (steps a5 and a7):
+// the products of A row `arow` times B merged in an LDS tag/value table of
+// 2^LOGT slots, then written in column order at C's row `crow`.  When B has
+// at most 64 * 2^LOGT columns the order comes from ranks in an occupancy
+// bitmap over all of B's columns, built in the table's own LDS once its
+// entries are in registers (no sort); otherwise the occupied slots are
+// compacted and sorted (bitonic).
+template <typename V, int LOGT, int WPR>
+__device__ __forceinline__ void num_row(const int *__restrict__ Arp, const int *__restrict__ Acol,
+                                        const V *__restrict__ Aval, const int *__restrict__ Brp,
+                                        const int *__restrict__ Bcol, const V *__restrict__ Bval, int arow,
+                                        long long crow, bool active, int gt, int *keys, double *vals,
+                                        EnumScratch<V, WPR * kWave> &en, int *s_scan, const long long *__restrict__ Crp,
+                                        int *__restrict__ Ccol, V *__restrict__ Cval, int ncols, int *err)
+{
+    constexpr int T = 1 << LOGT;
+    constexpr int G = WPR * kWave;
+    constexpr int SPT = T / G;          // slots per thread in the compaction
+    static_assert(SPT >= 1, "table smaller than its group");
+    const int lane = lane_id(), wg = gt / kWave;
+    for (int t = gt; t < T; t += G) {
+        keys[t] = kEmpty;
+        vals[t] = 0.0;
+    }
+    group_sync<WPR>();
+    if (active) {
+        auto get = [&](int e, int &bs, int &bl, V &a) {
+            const int k = Acol[e];
+            bs = Brp[k];
+            bl = Brp[k + 1] - bs;
+            a = Aval[e];
+        };
+        auto sink = [&](const int (&j)[4], const double (&p)[4], const bool (&ok)[4]) {
+            lds_insert_add_u<4>(keys, vals, LOGT, j, p, ok, err);
+        };
+        group_products<V, true, G, 4, decltype(get), decltype(sink), true>(Arp[arow], Arp[arow + 1], gt, en, Bcol,
+                                                                            Bval, get, sink);
+    }
+    group_sync<WPR>();
+    // compaction of the occupied slots to the front of the table
+    int kr[SPT];
+    double vr[SPT];
+    int cnt = 0;
+#pragma unroll
+    for (int s = 0; s < SPT; ++s) {
+        kr[s] = keys[gt * SPT + s];
+        vr[s] = vals[gt * SPT + s];
+        cnt += kr[s] != kEmpty;
+    }
+    const int incl = wave_incl_scan(cnt);
+    if (lane == kWave - 1) s_scan[wg] = incl;
+    group_sync<WPR>();
+    int wbase = 0, total = 0;
+    for (int w = 0; w < WPR; ++w) {
+        const int t = s_scan[w];
+        if (w < wg) wbase += t;
+        total += t;
+    }
+    order_row_entries<T, WPR, SPT>(kr, vr, keys, vals, s_scan, total, wbase, incl, cnt, ncols, gt);
     if (active) {
         const long long rb = Crp[crow];
         const int nc = (int)(Crp[crow + 1] - rb);
