@@ -805,13 +805,14 @@ __device__ __forceinline__ void group_bitonic(int *keys, V *vals, int n2, int gt
 // table (keys[0 .. total), vals[0 .. total)).  kr/vr hold each thread's SPT
 // slots of the table (kEmpty where free), cnt/incl/wbase their count, its
 // inclusive wave prefix and the wave's offset in the group; every thread of
-// the group calls it.  With B at most 64 T columns wide the order comes from
-// ranks in an occupancy bitmap over B's columns built in the table's own LDS;
-// otherwise the entries are compacted and sorted (bitonic).
+// the group calls it.  The columns lie in [lo, lo + ncols).  With ncols at
+// most 64 T the order comes from ranks in an occupancy bitmap over that
+// range built in the table's own LDS; otherwise the entries are compacted
+// and sorted (bitonic).
 template <int T, int WPR, int SPT>
 __device__ __forceinline__ void order_row_entries(const int (&kr)[SPT], const double (&vr)[SPT], int *keys,
                                                   double *vals, int *s_scan, int total, int wbase, int incl, int cnt,
-                                                  int ncols, int gt)
+                                                  int ncols, int gt, int lo = 0)
 {
     constexpr int G = WPR * kWave;
     const int lane = lane_id(), wg = gt / kWave;
@@ -828,7 +829,7 @@ __device__ __forceinline__ void order_row_entries(const int (&kr)[SPT], const do
         group_sync<WPR>();
 #pragma unroll
         for (int s = 0; s < SPT; ++s)
-            if (kr[s] != kEmpty) atomicOr(&bm[kr[s] >> 5], 1u << (kr[s] & 31));
+            if (kr[s] != kEmpty) atomicOr(&bm[(kr[s] - lo) >> 5], 1u << ((kr[s] - lo) & 31));
         group_sync<WPR>();
         int run = 0;
         for (int g0 = 0; g0 < NGR; g0 += G) {
@@ -855,7 +856,7 @@ __device__ __forceinline__ void order_row_entries(const int (&kr)[SPT], const do
         for (int s = 0; s < SPT; ++s) {
             rk[s] = -1;
             if (kr[s] != kEmpty) {
-                const int j = kr[s], w = j >> 5;
+                const int j = kr[s] - lo, w = j >> 5;
                 int r = pref[w >> 3];
                 for (int q = w & ~7; q < w; ++q) r += __popc(bm[q]);
                 rk[s] = r + __popc(bm[w] & ((1u << (j & 31)) - 1u));
@@ -1272,11 +1273,10 @@ __global__ __launch_bounds__(kWave) void k_seg_scan(int nchunks, int *__restrict
 
 // Hashed segment of a heavy row: products of the row whose columns lie in
 // chunks [c0, c1) merged in an LDS table of 2^LOGT slots; entries ranked by
-// an occupancy bitmap of the segment's columns, staged in column order in
-// the table's own storage and copied out with coalesced stores.
-constexpr int kSegWords = kSegMaxSpan * kChunkWords;
-constexpr int kSegPrefGroup = 8;        // bitmap words per prefix entry
-
+// an occupancy bitmap of the segment's columns (built in the table's own
+// storage once the entries are in registers, so the block needs no other
+// LDS and more blocks fit a CU), staged in column order and copied out with
+// coalesced stores.
 template <typename V, int LOGT, int THREADS>
 __global__ __launch_bounds__(THREADS) void k_num_seg(
     const int *__restrict__ Arp, const int *__restrict__ Acol, const V *__restrict__ Aval,
@@ -1288,23 +1288,20 @@ __global__ __launch_bounds__(THREADS) void k_num_seg(
     constexpr int T = 1 << LOGT;
     constexpr int SPT = T / THREADS;
     static_assert(SPT >= 1, "table smaller than the block");
+    constexpr int WPR = THREADS / kWave;
     __shared__ int keys[T];
     __shared__ double vals[T];
-    __shared__ unsigned bm[kSegWords];
-    __shared__ int pref[kSegWords / kSegPrefGroup];
     __shared__ EnumScratch<V, THREADS> S;
-    __shared__ int s_tmp[THREADS / kWave + 1];
+    __shared__ int s_scan[WPR + 1];
     const Seg sg = segs[blockIdx.x];
     const int gt = threadIdx.x;
     const int lo = sg.c0 * kChunkCols;
-    const int words = (sg.c1 - sg.c0) * kChunkWords;
     const int *__restrict__ split0 = Bsplit + sg.c0;
     const int *__restrict__ split1 = Bsplit + sg.c1;
     for (int t = gt; t < T; t += THREADS) {
         keys[t] = kEmpty;
         vals[t] = 0.0;
     }
-    for (int t = gt; t < words; t += THREADS) bm[t] = 0u;
     __syncthreads();
     auto get = [&](int e, int &bs, int &bl, V &a) {
         const int k = Acol[e];
@@ -1320,48 +1317,28 @@ __global__ __launch_bounds__(THREADS) void k_num_seg(
     __syncthreads();
     int kr[SPT];
     double vr[SPT];
+    int cnt = 0;
 #pragma unroll
     for (int s = 0; s < SPT; ++s) {
-        kr[s] = keys[s * THREADS + gt];
-        vr[s] = vals[s * THREADS + gt];
-        if (kr[s] != kEmpty) {
-            const int jl = kr[s] - lo;
-            atomicOr(&bm[jl >> 5], 1u << (jl & 31));
-        }
+        kr[s] = keys[gt * SPT + s];
+        vr[s] = vals[gt * SPT + s];
+        cnt += kr[s] != kEmpty;
     }
+    const int lane = lane_id(), wg = gt / kWave;
+    const int incl = wave_incl_scan(cnt);
+    if (lane == kWave - 1) s_scan[wg] = incl;
     __syncthreads();
-    // prefix of popcounts per group of kSegPrefGroup words
-    const int ngroups = words / kSegPrefGroup;
-    int tot_all = 0;
-    for (int g0 = 0; g0 < ngroups; g0 += THREADS) {
-        const int g = g0 + gt;
-        int pc = 0;
-        if (g < ngroups)
-#pragma unroll
-            for (int q = 0; q < kSegPrefGroup; ++q) pc += __popc(bm[g * kSegPrefGroup + q]);
-        int tot;
-        const int ex = block_excl_scan<int, THREADS>(pc, s_tmp, tot);
-        if (g < ngroups) pref[g] = tot_all + ex;
-        tot_all += tot;
+    int wbase = 0, total = 0;
+    for (int w = 0; w < WPR; ++w) {
+        const int t = s_scan[w];
+        if (w < wg) wbase += t;
+        total += t;
     }
-    __syncthreads();
-    if (gt == 0 && tot_all != sg.count) atomicOr(err, kErrCount);
-#pragma unroll
-    for (int s = 0; s < SPT; ++s) {
-        if (kr[s] == kEmpty) continue;
-        const int jl = kr[s] - lo;
-        const int wd = jl >> 5;
-        int rank = pref[wd / kSegPrefGroup];
-        for (int q = wd & ~(kSegPrefGroup - 1); q < wd; ++q) rank += __popc(bm[q]);
-        rank += __popc(bm[wd] & ((1u << (jl & 31)) - 1u));
-        if (rank < T) {
-            keys[rank] = kr[s];
-            vals[rank] = vr[s];
-        }
-    }
-    __syncthreads();
+    if (gt == 0 && total != sg.count) atomicOr(err, kErrCount);
+    order_row_entries<T, WPR, SPT>(kr, vr, keys, vals, s_scan, total, wbase, incl, cnt,
+                                   (sg.c1 - sg.c0) * kChunkCols, gt, lo);
     const long long out0 = sg.out;
-    const int n = tot_all < sg.count ? tot_all : sg.count;
+    const int n = total < sg.count ? total : sg.count;
     for (int t = gt; t < n; t += THREADS) {
         store_c(&Ccol[out0 + t], keys[t]);
         store_c(&Cval[out0 + t], (V)vals[t]);
