@@ -1205,7 +1205,7 @@ void bbin(const BPlan &p, hipStream_t s, const unsigned char *bin_of, BinHdr *h,
 void batch_analyze(const BPlan &p, hipStream_t s)
 {
     k_fill_i32<<<1, 256, 0, s>>>((long long)(sizeof(BatchHdr) / sizeof(int)), (int *)p.d_hdr, 0);
-    k_banalyze<<<bgrid(p, blocks_for(p.M, 4)), 256, 0, s>>>(p.M, p.count, p.d_row0, p.d_desc, p.cfg.lds_row_max,
+    k_banalyze<<<bgrid(p, blocks_for(p.M, 4 * kWave)), 256, 0, s>>>(p.M, p.count, p.d_row0, p.d_desc, p.cfg.lds_row_max,
                                                             p.cfg.table_shift, p.prob, p.ub, p.cap, p.nnzc,
                                                             p.sym_bin, p.gsz);
 }

@@ -56,7 +56,13 @@ __device__ __forceinline__ int lds_bin_shift(long long bound, int shift)
 
 // Per global row: its problem, products ub, bound cap = min(ub, cols), bin
 // (empty, LDS by cap << shift, or heavy above lds_row_max) and, for heavy
-// rows, its global table size.  One wave per row, grid-stride.
+// rows of problems wider than kWideMaxCols, its global table size.  A wave
+// takes 64 consecutive rows, one per lane: the problem of the first by
+// binary search over the problems' first rows, the others by stepping
+// forward; a lane sums the B-row lengths of its row when the row has at
+// most kAnalyzeShort entries, and the whole wave sums each longer row.
+constexpr int kAnalyzeShort = 32;
+
 __global__ __launch_bounds__(256) void k_banalyze(long long M, int count, const long long *__restrict__ row0s,
                                                   const BatchDesc *__restrict__ desc, int lds_row_max, int shift,
                                                   int *__restrict__ prob, long long *__restrict__ ub_out,
@@ -64,30 +70,52 @@ __global__ __launch_bounds__(256) void k_banalyze(long long M, int count, const 
                                                   unsigned char *__restrict__ bin_out, long long *__restrict__ gsz)
 {
     const int lane = lane_id();
-    for (long long g = (long long)blockIdx.x * 4 + threadIdx.x / kWave; g < M; g += (long long)gridDim.x * 4) {
-        int lo = 0, hi = count;     // row0s[lo] <= g < row0s[hi]
+    const long long nw = (long long)gridDim.x * 4;
+    for (long long base = ((long long)blockIdx.x * 4 + threadIdx.x / kWave) * kWave; base < M; base += nw * kWave) {
+        int lo = 0, hi = count;     // row0s[lo] <= base < row0s[hi]
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
-            if (row0s[mid] <= g) lo = mid;
+            if (row0s[mid] <= base) lo = mid;
             else hi = mid;
         }
-        const BatchDesc &d = desc[lo];
-        const int row = (int)(g - d.row0);
-        const int e0 = d.Arp[row], e1 = d.Arp[row + 1];
+        const long long g = base + lane;
+        const bool valid = g < M;
+        int pr = lo;
+        if (valid)
+            while (row0s[pr + 1] <= g) ++pr;
+        const BatchDesc &d = desc[pr];
+        const int row = valid ? (int)(g - d.row0) : 0;
+        const int e0 = valid ? d.Arp[row] : 0, e1 = valid ? d.Arp[row + 1] : 0;
+        const bool lng = e1 - e0 > kAnalyzeShort;
         long long ub = 0;
-        for (int e = e0 + lane; e < e1; e += kWave) {
-            const int k = d.Acol[e];
-            ub += d.Brp[k + 1] - d.Brp[k];
+        if (!lng)
+            for (int e = e0; e < e1; ++e) {
+                const int k = d.Acol[e];
+                ub += d.Brp[k + 1] - d.Brp[k];
+            }
+        // long rows: the whole wave sums each in turn
+        unsigned long long todo = __ballot(valid && lng);
+        while (todo) {
+            const int src = __ffsll((long long)todo) - 1;
+            todo &= todo - 1;
+            const int le0 = __shfl(e0, src, kWave), le1 = __shfl(e1, src, kWave), lp = __shfl(pr, src, kWave);
+            const BatchDesc &ld = desc[lp];
+            long long part = 0;
+            for (int e = le0 + lane; e < le1; e += kWave) {
+                const int k = ld.Acol[e];
+                part += ld.Brp[k + 1] - ld.Brp[k];
+            }
+            part = wave_sum(part);
+            if (lane == src) ub = part;
         }
-        ub = wave_sum(ub);
-        if (lane == 0) {
+        if (valid) {
             const int cap = (int)(ub < d.cols ? ub : d.cols);
             int b = kBinEmpty;
             if (ub > 0) {
                 b = cap > lds_row_max ? kBinHeavy : lds_bin_shift(cap, shift);
                 if (b >= kLdsBins) b = kBinHeavy;
             }
-            prob[g] = lo;
+            prob[g] = pr;
             ub_out[g] = ub;
             cap_out[g] = cap;
             nnzc[g] = 0;
@@ -296,7 +324,7 @@ __global__ __launch_bounds__(kWideThreads) void k_bnum_wide(const BatchDesc *__r
     constexpr int NW = kWideThreads / kWave;
     constexpr int CPW = kWideWin / NW;                  // columns ranked by each wave
     constexpr int ROUNDS = CPW / kWave;
-    extern __shared__ unsigned char s_raw[];
+    extern __shared__ __align__(16) unsigned char s_raw[];
     double *acc = (double *)s_raw;                      // [kWideWin]
     __shared__ EnumScratch<V, kWideThreads> S;
     __shared__ int s_wt[NW];

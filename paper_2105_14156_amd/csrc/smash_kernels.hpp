@@ -1367,7 +1367,7 @@ __global__ __launch_bounds__(kDenseThreads) void k_num_dense(
     constexpr int NW = kDenseThreads / kWave;
     constexpr int CPW = kChunkCols / NW;              // columns ranked by each wave
     constexpr int ROUNDS = CPW / kWave;
-    extern __shared__ unsigned char s_raw[];
+    extern __shared__ __align__(16) unsigned char s_raw[];
     double *acc = (double *)s_raw;                      // [kChunkCols]
     __shared__ EnumScratch<V, kDenseThreads> S;
     __shared__ int s_wt[NW];
