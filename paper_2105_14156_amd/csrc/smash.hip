@@ -1142,6 +1142,7 @@ struct smash_batch_plan_s {
     int *prob = nullptr, *cap = nullptr, *nnzc = nullptr, *sym_perm = nullptr, *num_perm = nullptr, *bcount = nullptr;
     unsigned char *sym_bin = nullptr, *num_bin = nullptr;
     unsigned long long *bprod = nullptr;
+    RowDesc *rd = nullptr;               // row records of the LDS bins
     int nblk = 0;
     BatchHdr *d_hdr = nullptr, *h_hdr = nullptr;
     int *gkeys = nullptr;
@@ -1215,7 +1216,7 @@ void bsym_bin(const BPlan &p, hipStream_t s)
 {
     using S = BShape<LT, WIDE>;
     k_bsym_rows<LT, S::WPR, S::RPW><<<bgrid(p, blocks_for(p.M, S::RPW)), S::THREADS, 0, s>>>(
-        p.d_desc, p.prob, &p.d_hdr->sym, LT - kMinLogT, p.sym_perm, p.nnzc, &p.d_hdr->error);
+        p.d_desc, p.rd, &p.d_hdr->sym, LT - kMinLogT, p.nnzc, &p.d_hdr->error);
 }
 
 template <typename V, int LT, int WIDE>
@@ -1223,7 +1224,7 @@ void bnum_bin(const BPlan &p, hipStream_t s)
 {
     using S = BShape<LT, WIDE>;
     k_bnum_rows<V, LT, S::WPR, S::RPW><<<bgrid(p, blocks_for(p.M, S::RPW)), S::THREADS, 0, s>>>(
-        p.d_desc, p.prob, p.d_hdr, LT - kMinLogT, p.num_perm, p.ccap, p.crp, p.ccol, (V *)p.cval, &p.d_hdr->error);
+        p.d_desc, p.rd, p.d_hdr, LT - kMinLogT, p.ccap, p.ccol, (V *)p.cval, &p.d_hdr->error);
 }
 
 template <int WIDE>
@@ -1271,6 +1272,8 @@ void batch_enqueue(const BPlan &p, hipStream_t s)
     batch_analyze(p, s);
     bbin(p, s, p.sym_bin, &p.d_hdr->sym, p.sym_perm, true);
     bscan<long long>(p, s, p.M, p.gsz, p.goff, &p.d_hdr->gneed);
+    k_browdesc<<<bgrid(p, blocks_for(p.M, 256)), 256, 0, s>>>(p.d_desc, p.prob, &p.d_hdr->sym, p.sym_perm, nullptr,
+                                                               p.rd);
     if (p.cfg.wide_groups) bsym_bins<1>(p, s);
     else bsym_bins<0>(p, s);
     k_bsym_wide<<<bgrid(p, p.M), kWideThreads, p.wide_words * sizeof(unsigned), s>>>(
@@ -1283,6 +1286,8 @@ void batch_enqueue(const BPlan &p, hipStream_t s)
     k_bnum_bins<<<bgrid(p, blocks_for(p.M, 256)), 256, 0, s>>>(p.M, p.cfg.table_shift, p.nnzc, p.sym_bin,
                                                                p.num_bin);
     bbin(p, s, p.num_bin, &p.d_hdr->num, p.num_perm, false);
+    k_browdesc<<<bgrid(p, blocks_for(p.M, 256)), 256, 0, s>>>(p.d_desc, p.prob, &p.d_hdr->num, p.num_perm, p.crp,
+                                                               p.rd);
     if (p.dtype == SMASH_F32) batch_numeric<float>(p, s);
     else batch_numeric<double>(p, s);
 }
@@ -1394,7 +1399,7 @@ smash_status smash_batch_plan_create(smash_ctx c, smash_dtype dtype, int32_t cou
                                     (size_t)M * 8, (size_t)M * 4, (size_t)M * 4, (size_t)M, (size_t)M,
                                     (size_t)M * 8, (size_t)(M + 1) * 8, (size_t)M * 4, (size_t)M * 4,
                                     (size_t)p->nblk * kNumBins * 4, (size_t)p->nblk * 8, (size_t)(nsb + 1) * 8,
-                                    (size_t)std::max(count, 1) * 8, sizeof(BatchHdr)});
+                                    (size_t)std::max(count, 1) * 8, sizeof(BatchHdr), (size_t)M * sizeof(RowDesc)});
     if (hipMalloc(&p->ws, need) != hipSuccess) return bail(fail(c, SMASH_ERR_OUT_OF_MEMORY, "batch workspace"));
     if (hipHostMalloc((void **)&p->h_hdr, sizeof(BatchHdr), hipHostMallocDefault) != hipSuccess)
         return bail(fail(c, SMASH_ERR_HIP, "pinned header"));
@@ -1427,6 +1432,7 @@ smash_status smash_batch_plan_create(smash_ctx c, smash_dtype dtype, int32_t cou
     p->bsum = cv.take<long long>(nsb + 1);
     p->pnnz = cv.take<long long>(std::max(count, 1));
     p->d_hdr = cv.take<BatchHdr>(1);
+    p->rd = cv.take<RowDesc>(M);
     if (hipMemcpyAsync(p->d_desc, p->desc.data(), p->desc.size() * sizeof(BatchDesc), hipMemcpyHostToDevice, s) !=
             hipSuccess ||
         hipMemcpyAsync(p->d_row0, p->row0.data(), ((size_t)count + 1) * 8, hipMemcpyHostToDevice, s) != hipSuccess)

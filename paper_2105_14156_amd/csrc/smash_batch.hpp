@@ -47,6 +47,19 @@ constexpr int kWideMaxCols = 1 << 20;
 constexpr int kWideWin = 8192;
 constexpr int kWideThreads = 512;
 
+// What an LDS-bin kernel needs of one row, gathered in permutation order by
+// k_browdesc so that the bin kernels read one contiguous record per row
+// instead of a chain of dependent loads (row id, problem, row pointers,
+// C offset).
+struct RowDesc {
+    int grow;                   // global row
+    int prob;                   // problem
+    int e0, e1;                 // the row's entries in A_p
+    long long rb;               // C offset (numeric only)
+    int nc;                     // C entries (numeric only)
+    int pad;
+};
+
 // Table size class of a row bound: 2^LOGT >= bound << shift slots.
 __device__ __forceinline__ int lds_bin_shift(long long bound, int shift)
 {
@@ -139,12 +152,35 @@ __global__ __launch_bounds__(256) void k_bnum_bins(long long M, int shift, const
     }
 }
 
-// Symbolic, LDS bin `bin`: RPW rows of WPR waves per work item.
+// Row records of the rows in the LDS bins of one binning (positions
+// [0, offset[kLdsBins]) of perm), for k_bsym_rows / k_bnum_rows; with Crp
+// non-NULL also their C offsets and counts.
+__global__ __launch_bounds__(256) void k_browdesc(const BatchDesc *__restrict__ desc, const int *__restrict__ prob,
+                                                  const BinHdr *h, const int *__restrict__ perm,
+                                                  const long long *__restrict__ Crp, RowDesc *__restrict__ rd)
+{
+    const int n = h->offset[kLdsBins];
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+        RowDesc o;
+        o.grow = perm[r];
+        o.prob = prob[o.grow];
+        const BatchDesc &d = desc[o.prob];
+        const int arow = (int)(o.grow - d.row0);
+        o.e0 = d.Arp[arow];
+        o.e1 = d.Arp[arow + 1];
+        o.rb = Crp ? Crp[o.grow] : 0;
+        o.nc = Crp ? (int)(Crp[o.grow + 1] - o.rb) : 0;
+        o.pad = 0;
+        rd[r] = o;
+    }
+}
+
+// Symbolic, LDS bin `bin`: RPW rows of WPR waves per work item; the next
+// item's row record is loaded while this one is processed.
 template <int LOGT, int WPR, int RPW>
 __global__ __launch_bounds__(kWave *WPR *RPW) void k_bsym_rows(const BatchDesc *__restrict__ desc,
-                                                               const int *__restrict__ prob, const BinHdr *h, int bin,
-                                                               const int *__restrict__ perm, int *__restrict__ nnzc,
-                                                               int *err)
+                                                               const RowDesc *__restrict__ rd, const BinHdr *h,
+                                                               int bin, int *__restrict__ nnzc, int *err)
 {
     static_assert(RPW == 1 || WPR == 1, "multi-row blocks use one wave per row");
     constexpr int G = WPR * kWave;
@@ -152,28 +188,33 @@ __global__ __launch_bounds__(kWave *WPR *RPW) void k_bsym_rows(const BatchDesc *
     __shared__ EnumScratch<float, G> s_en[RPW];
     __shared__ int s_cnt[RPW];
     const int cnt = h->count[bin];
-    const int *rows = perm + h->offset[bin];
+    const RowDesc *rows = rd + h->offset[bin];
     const int g = threadIdx.x / kWave / WPR;
     const int gt = threadIdx.x - g * G;
-    for (int base = blockIdx.x * RPW; base < cnt; base += gridDim.x * RPW) {
-        const int r = base + g;
-        const bool active = r < cnt;
-        const int grow = active ? rows[r] : 0;
-        const BatchDesc &d = desc[active ? prob[grow] : 0];
-        sym_row<LOGT, WPR>(d.Arp, d.Acol, d.Brp, d.Bcol, (int)(grow - d.row0), active, gt, s_keys[g], s_en[g],
-                           &s_cnt[g], &nnzc[grow], err);
+    const int stride = gridDim.x * RPW;
+    int base = blockIdx.x * RPW;
+    RowDesc cur{};
+    if (base + g < cnt) cur = rows[base + g];
+    for (; base < cnt; base += stride) {
+        const bool active = base + g < cnt;
+        RowDesc nxt{};
+        if (base + stride + g < cnt) nxt = rows[base + stride + g];
+        const BatchDesc &d = desc[active ? cur.prob : 0];
+        sym_row<LOGT, WPR>(cur.e0, cur.e1, d.Acol, d.Brp, d.Bcol, active, gt, s_keys[g], s_en[g], &s_cnt[g],
+                           &nnzc[active ? cur.grow : 0], err);
         group_sync<WPR>();
+        cur = nxt;
     }
 }
 
-// Numeric, LDS bin `bin`.  Does nothing when the output pool is too small
-// (the capacity check has then flagged the batch).
+// Numeric, LDS bin `bin` (row records with C offsets).  Does nothing when
+// the output pool is too small (the capacity check has then flagged the
+// batch).
 template <typename V, int LOGT, int WPR, int RPW>
 __global__ __launch_bounds__(kWave *WPR *RPW) void k_bnum_rows(const BatchDesc *__restrict__ desc,
-                                                               const int *__restrict__ prob, const BatchHdr *bh,
-                                                               int bin, const int *__restrict__ perm,
-                                                               long long ccap, const long long *__restrict__ Crp,
-                                                               int *__restrict__ Ccol, V *__restrict__ Cval, int *err)
+                                                               const RowDesc *__restrict__ rd, const BatchHdr *bh,
+                                                               int bin, long long ccap, int *__restrict__ Ccol,
+                                                               V *__restrict__ Cval, int *err)
 {
     static_assert(RPW == 1 || WPR == 1, "multi-row blocks use one wave per row");
     constexpr int T = 1 << LOGT;
@@ -184,18 +225,22 @@ __global__ __launch_bounds__(kWave *WPR *RPW) void k_bnum_rows(const BatchDesc *
     __shared__ int s_scan[RPW][WPR + 1];
     if (bh->nnz_c > ccap) return;
     const int cnt = bh->num.count[bin];
-    const int *rows = perm + bh->num.offset[bin];
+    const RowDesc *rows = rd + bh->num.offset[bin];
     const int g = threadIdx.x / kWave / WPR;
     const int gt = threadIdx.x - g * G;
-    for (int base = blockIdx.x * RPW; base < cnt; base += gridDim.x * RPW) {
-        const int r = base + g;
-        const bool active = r < cnt;
-        const int grow = active ? rows[r] : 0;
-        const BatchDesc &d = desc[active ? prob[grow] : 0];
-        num_row<V, LOGT, WPR>(d.Arp, d.Acol, (const V *)d.Aval, d.Brp, d.Bcol, (const V *)d.Bval,
-                              (int)(grow - d.row0), grow, active, gt, s_keys[g], s_vals[g], s_en[g], s_scan[g], Crp,
-                              Ccol, Cval, d.cols, err);
+    const int stride = gridDim.x * RPW;
+    int base = blockIdx.x * RPW;
+    RowDesc cur{};
+    if (base + g < cnt) cur = rows[base + g];
+    for (; base < cnt; base += stride) {
+        const bool active = base + g < cnt;
+        RowDesc nxt{};
+        if (base + stride + g < cnt) nxt = rows[base + stride + g];
+        const BatchDesc &d = desc[active ? cur.prob : 0];
+        num_row<V, LOGT, WPR>(cur.e0, cur.e1, d.Acol, (const V *)d.Aval, d.Brp, d.Bcol, (const V *)d.Bval, cur.rb,
+                              cur.nc, active, gt, s_keys[g], s_vals[g], s_en[g], s_scan[g], Ccol, Cval, d.cols, err);
         group_sync<WPR>();
+        cur = nxt;
     }
 }
 

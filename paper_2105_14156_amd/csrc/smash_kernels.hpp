@@ -722,13 +722,12 @@ __global__ __launch_bounds__(256) void k_scatter(int m, const unsigned char *__r
 
 // Symbolic count of one light row by a group of WPR waves (gt: thread index
 // in the group; every thread of the group calls it): the distinct columns of
-// A row `arow` times B, counted in an LDS key table of 2^LOGT slots (step
-// a3), are stored to *out by the group's first thread.
+// the row's A entries [e0, e1) times B, counted in an LDS key table of
+// 2^LOGT slots (step a3), are stored to *out by the group's first thread.
 template <int LOGT, int WPR>
-__device__ __forceinline__ void sym_row(const int *__restrict__ Arp, const int *__restrict__ Acol,
-                                        const int *__restrict__ Brp, const int *__restrict__ Bcol, int arow,
-                                        bool active, int gt, int *keys, EnumScratch<float, WPR * kWave> &en,
-                                        int *s_cnt, int *out, int *err)
+__device__ __forceinline__ void sym_row(int e0, int e1, const int *__restrict__ Acol, const int *__restrict__ Brp,
+                                        const int *__restrict__ Bcol, bool active, int gt, int *keys,
+                                        EnumScratch<float, WPR * kWave> &en, int *s_cnt, int *out, int *err)
 {
     constexpr int T = 1 << LOGT;
     constexpr int G = WPR * kWave;
@@ -743,8 +742,8 @@ __device__ __forceinline__ void sym_row(const int *__restrict__ Arp, const int *
             bl = Brp[k + 1] - bs;
         };
         auto sink = [&](const int (&j)[4], const bool (&ok)[4]) { mine += lds_insert_key_u<4>(keys, LOGT, j, ok, err); };
-        group_products<float, false, G, 4, decltype(get), decltype(sink), true>(
-            Arp[arow], Arp[arow + 1], gt, en, Bcol, (const float *)nullptr, get, sink);
+        group_products<float, false, G, 4, decltype(get), decltype(sink), true>(e0, e1, gt, en, Bcol,
+                                                                                (const float *)nullptr, get, sink);
     }
     mine = wave_sum(mine);
     if (lane_id() == 0 && mine) atomicAdd(s_cnt, mine);
@@ -770,7 +769,8 @@ __global__ __launch_bounds__(kWave *WPR *RPW) void k_sym_rows(const int *__restr
     const int r = blockIdx.x * RPW + g;
     const bool active = r < nrows;
     const int row = active ? rows[r] : 0;
-    sym_row<LOGT, WPR>(Arp, Acol, Brp, Bcol, row, active, gt, s_keys[g], s_en[g], &s_cnt[g], &nnzc[row], err);
+    const int e0 = active ? Arp[row] : 0, e1 = active ? Arp[row + 1] : 0;
+    sym_row<LOGT, WPR>(e0, e1, Acol, Brp, Bcol, active, gt, s_keys[g], s_en[g], &s_cnt[g], &nnzc[row], err);
 }
 
 // -------------------------------------------------------- numeric, LDS hash
@@ -888,18 +888,18 @@ __device__ __forceinline__ void order_row_entries(const int (&kr)[SPT], const do
 }
 
 // Numeric pass of one light row by a group of WPR waves (steps a5 and a7):
-// the products of A row `arow` times B merged in an LDS tag/value table of
-// 2^LOGT slots, then written in column order at C's row `crow`.  When B has
+// the products of the row's A entries [e0, e1) times B merged in an LDS
+// tag/value table of 2^LOGT slots, then written in column order at C's
+// offset rb (nc entries expected).  When B has
 // at most 64 * 2^LOGT columns the order comes from ranks in an occupancy
 // bitmap over all of B's columns, built in the table's own LDS once its
 // entries are in registers (no sort); otherwise the occupied slots are
 // compacted and sorted (bitonic).
 template <typename V, int LOGT, int WPR>
-__device__ __forceinline__ void num_row(const int *__restrict__ Arp, const int *__restrict__ Acol,
-                                        const V *__restrict__ Aval, const int *__restrict__ Brp,
-                                        const int *__restrict__ Bcol, const V *__restrict__ Bval, int arow,
-                                        long long crow, bool active, int gt, int *keys, double *vals,
-                                        EnumScratch<V, WPR * kWave> &en, int *s_scan, const long long *__restrict__ Crp,
+__device__ __forceinline__ void num_row(int e0, int e1, const int *__restrict__ Acol, const V *__restrict__ Aval,
+                                        const int *__restrict__ Brp, const int *__restrict__ Bcol,
+                                        const V *__restrict__ Bval, long long rb, int nc, bool active, int gt,
+                                        int *keys, double *vals, EnumScratch<V, WPR * kWave> &en, int *s_scan,
                                         int *__restrict__ Ccol, V *__restrict__ Cval, int ncols, int *err)
 {
     constexpr int T = 1 << LOGT;
@@ -922,8 +922,7 @@ __device__ __forceinline__ void num_row(const int *__restrict__ Arp, const int *
         auto sink = [&](const int (&j)[4], const double (&p)[4], const bool (&ok)[4]) {
             lds_insert_add_u<4>(keys, vals, LOGT, j, p, ok, err);
         };
-        group_products<V, true, G, 4, decltype(get), decltype(sink), true>(Arp[arow], Arp[arow + 1], gt, en, Bcol,
-                                                                            Bval, get, sink);
+        group_products<V, true, G, 4, decltype(get), decltype(sink), true>(e0, e1, gt, en, Bcol, Bval, get, sink);
     }
     group_sync<WPR>();
     // compaction of the occupied slots to the front of the table
@@ -947,8 +946,6 @@ __device__ __forceinline__ void num_row(const int *__restrict__ Arp, const int *
     }
     order_row_entries<T, WPR, SPT>(kr, vr, keys, vals, s_scan, total, wbase, incl, cnt, ncols, gt);
     if (active) {
-        const long long rb = Crp[crow];
-        const int nc = (int)(Crp[crow + 1] - rb);
         if (gt == 0 && nc != total) atomicOr(err, kErrCount);
         const int nw = total < nc ? total : nc;
         for (int t = gt; t < nw; t += G) {
@@ -978,8 +975,11 @@ __global__ __launch_bounds__(kWave *WPR *RPW) void k_num_rows(
     const int r = blockIdx.x * RPW + g;
     const bool active = r < nrows;
     const int row = active ? rows[r] : 0;
-    num_row<V, LOGT, WPR>(Arp, Acol, Aval, Brp, Bcol, Bval, row, row, active, gt, s_keys[g], s_vals[g], s_en[g],
-                          s_scan[g], Crp, Ccol, Cval, ncols, err);
+    const int e0 = active ? Arp[row] : 0, e1 = active ? Arp[row + 1] : 0;
+    const long long rb = active ? Crp[row] : 0;
+    const int nc = active ? (int)(Crp[row + 1] - rb) : 0;
+    num_row<V, LOGT, WPR>(e0, e1, Acol, Aval, Brp, Bcol, Bval, rb, nc, active, gt, s_keys[g], s_vals[g], s_en[g],
+                          s_scan[g], Ccol, Cval, ncols, err);
 }
 
 // ---------------------------------------------------------------- row scan
