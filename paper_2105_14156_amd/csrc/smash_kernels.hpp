@@ -30,9 +30,12 @@
 //     dense/sparse decision of the Window Distribution Phase).  Optionally a
 //     heavy row instead uses one hash table in global memory (version 3,
 //     "Fragmenting Memory").
-//   * output is written in column order: bitonic sort of small tables, rank
-//     from an occupancy bitmap for segments and dense chunks, staged in LDS so
-//     the global stores are coalesced.
+//   * output is written in column order: ranks from an occupancy bitmap of
+//     the row's (or segment's) column range, built in the table's own LDS
+//     once its entries are in registers, where that range is at most 64
+//     times the table size, else a bitonic sort; dense chunks rank by
+//     ballots over the accumulator; entries are staged in LDS so the global
+//     stores are coalesced.
 #pragma once
 
 #include <hip/hip_runtime.h>
