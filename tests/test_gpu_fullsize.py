@@ -1,5 +1,7 @@
-"""Full-size GPU parity for RMAT scale 19, edge factor 16, C = A.A in FP32: the
-benchmark's workload, in the benchmark's launch configuration.
+"""Full-size GPU parity for RMAT scale 19, edge factor 16, C = A.A in FP32 (the
+benchmark's workload, in the benchmark's launch configuration), for the same
+product through the fused pass, and for the rectangular workload (RMAT scale
+21, edge factor 8, times a 2^21 x 4096 matrix with 16 columns per row).
 
 The whole C does not fit the oracle's time budget, so it is checked
 - structurally everywhere: every row's count against the oracle's exact
@@ -37,6 +39,30 @@ def _spmv(torch, rp, col, val, x, m, absolute=False, chunk=1 << 27):
         y[r0:r1] = torch.segment_reduce(prod, "sum", offsets=rp[r0:r1 + 1] - s)
         r0 = r1
     return y
+
+
+def _sampled_rows(A, B, oracle_mod, rp, ub, seed):
+    top = np.argsort(-ub, kind="stable")[:16]
+    rand = (syn.uniform01(seed, 0, 4000) * A.rows).astype(np.int64)
+    by_class = []
+    for lo, hi in [(1, 32), (33, 512), (513, 1024), (1025, 8192), (8193, 65536), (65537, 1 << 40)]:
+        cls = np.nonzero((ub >= lo) & (ub <= hi))[0]
+        if cls.size:
+            by_class.append(cls[(syn.uniform01(lo, 0, 50) * cls.size).astype(np.int64)])
+    return np.unique(np.concatenate([top, rand] + by_class))
+
+
+def _check_sampled(torch, C, A, B, oracle_mod, sel, where):
+    rp = C.row_ptr.cpu().numpy()
+    ref = oracle_mod.spgemm(A, B, rows=sel)
+    starts = rp[sel]
+    lens = rp[sel + 1] - starts
+    idx = np.repeat(starts - np.concatenate([[0], np.cumsum(lens)[:-1]]), lens) + np.arange(lens.sum())
+    tidx = torch.from_numpy(idx).cuda()
+    col = C.col_idx.index_select(0, tidx).cpu().numpy()
+    val = C.val.index_select(0, tidx).cpu().numpy()
+    srp = np.concatenate([[0], np.cumsum(lens)])
+    return check_rows(srp, col, val, ref, np.float32, where), int(lens.sum())
 
 
 @pytest.mark.timeout(900)
@@ -97,4 +123,38 @@ def test_rmat_s19_full_size(oracle_mod):
         ok = err <= 1e-5 * bnd + 1e-9 * bnd
         assert bool(ok.all()), f"Freivalds check failed on {int((~ok).sum())} rows"
         print(f"Freivalds {s} ok: max err/bound {float((err / bnd.clamp_min(1e-300)).max()):.2e}", flush=True)
+
+    # 4. the fused pass on the same product: identical structure, sampled values
+    C = None
+    torch.cuda.synchronize()
+    ctx.predictor_load()
+    Cf = ctx.spgemm_fused(dA, dA)
+    st = ctx.stats()
+    print("fused done", st["fused_rows"], st["fused_overflow"], flush=True)
+    assert st["fused_rows"] > 0
+    assert np.array_equal(np.diff(Cf.row_ptr.cpu().numpy()), nz), "fused row counts differ from the oracle"
+    margin, n = _check_sampled(torch, Cf, A, A, oracle_mod, sel, "s19 fused sampled rows")
+    print(f"fused: {sel.size} sampled rows ok ({n} entries, max err/absmass {margin:.2e})", flush=True)
+    ctx.close()
+
+
+@pytest.mark.timeout(900)
+def test_rect_full_size(oracle_mod):
+    import torch
+    from paper_2105_14156_amd import smash
+    w = syn.workload_rect(np.float32)
+    A, B = w.A, w.B
+    print(f"rect: A {A.rows}x{A.cols} nnz {A.nnz}, B {B.rows}x{B.cols} nnz {B.nnz}", flush=True)
+    ctx = smash.Context(0)
+    dA, dB = smash.to_device(A), smash.to_device(B)
+    C = ctx.spgemm(dA, dB)
+    torch.cuda.synchronize()
+    print("gpu done", ctx.stats(), flush=True)
+    nz = oracle_mod.row_nnz(A, B)
+    assert np.array_equal(np.diff(C.row_ptr.cpu().numpy()), nz), "row counts differ from the oracle"
+    print("row counts ok", flush=True)
+    ub = oracle_mod.products_per_row(A, B)
+    sel = _sampled_rows(A, B, oracle_mod, C.row_ptr.cpu().numpy(), ub, 0x52EC)
+    margin, n = _check_sampled(torch, C, A, B, oracle_mod, sel, "rect sampled rows")
+    print(f"{sel.size} sampled rows ok ({n} entries, max err/absmass {margin:.2e})", flush=True)
     ctx.close()
