@@ -298,31 +298,45 @@ def main():
         "stats": st,
     }
     if not args.no_variants:
-        # the learned fused pass on the same product, and the batched launch
-        other = "fused" if args.path == "plain" else "plain"
-        if other == "fused":
-            ctx.predictor_load()
-        run2 = (lambda: ctx.spgemm_fused(dA, dB, stream)) if other == "fused" else (lambda: ctx.spgemm(dA, dB, stream))
-        for _ in range(max(1, args.warmup)):
-            C = None
-            C = run2()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            C = None
-            C = run2()
-        torch.cuda.synchronize()
-        ms2 = (time.perf_counter() - t0) / args.steps * 1e3
-        st2 = ctx.stats()
+        # the fused pass on the same product, with the learned capacities and
+        # with the exact upper bound min(products, cols) (no network), and the
+        # batched launch
+        ctx.predictor_load()
+
+        def timed(fn):
+            nonlocal_c = None
+            for _ in range(max(1, args.warmup)):
+                nonlocal_c = None
+                nonlocal_c = fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                nonlocal_c = None
+                nonlocal_c = fn()
+            torch.cuda.synchronize()
+            del nonlocal_c
+            return (time.perf_counter() - t0) / args.steps * 1e3, ctx.stats()
+
         C = None
-        log(f"{other} path: {ms2:.3f} ms per step")
+        fused = {}
+        for sizing, name in ((0, "learned"), (1, "upper_bound")):
+            ctx.set_option(smash.OPT_FUSED_SIZING, sizing)
+            ms_f, st_f = timed(lambda: ctx.spgemm_fused(dA, dB, stream))
+            fused[name] = {"ms_per_step": round(ms_f, 4), "fused_rows": st_f["fused_rows"],
+                           "overflow_rows": st_f["fused_overflow"], "reserved_slots": st_f["fused_capacity"]}
+            log(f"fused ({name} capacities): {ms_f:.3f} ms per step")
+        ctx.set_option(smash.OPT_FUSED_SIZING, 0)
+        if args.path == "plain":
+            ms_plain = ms_step
+        else:
+            ms_plain, _ = timed(lambda: ctx.spgemm(dA, dB, stream))
         b = run_batch(args.batch_count, args.steps, args.warmup)
         out["variants"] = {
-            f"{other}_ms_per_step": round(ms2, 4),
-            f"{args.path}_ms_per_step": round(ms_step, 4),
-            "fused_speedup_vs_plain": round((ms2 / ms_step) if other == "plain" else (ms_step / ms2), 4),
-            "fused_rows": st2["fused_rows"] if other == "fused" else st["fused_rows"],
-            "fused_overflow": st2["fused_overflow"] if other == "fused" else st["fused_overflow"],
+            "plain_ms_per_step": round(ms_plain, 4),
+            "fused": fused,
+            "fused_speedup_vs_plain": round(ms_plain / fused["learned"]["ms_per_step"], 4),
+            "network_speedup_vs_upper_bound": round(fused["upper_bound"]["ms_per_step"]
+                                                    / fused["learned"]["ms_per_step"], 4),
             "batch": {"workload": f"batch{b['count']}_rmat_x_uniform8", "graph_ms": round(b["graph_ms"], 4),
                       "plain_loop_ms": round(b["plain_loop_ms"], 3),
                       "speedup_vs_plain_loop": round(b["plain_loop_ms"] / b["graph_ms"], 2),
