@@ -89,7 +89,15 @@ typedef enum {
      * (default); 1 = the exact upper bound min(products, cols), without the
      * network (the baseline that shows what the network gains). */
     SMASH_OPT_FUSED_SIZING = 4,
-    SMASH_OPT_COUNT = 5
+    /* Global mode (SMASH_OPT_HEAVY_MODE = 1): the most hash-table slots the
+     * heavy rows may hold at once; 0 = no limit (default).  Every heavy row
+     * has a table of next_pow2(2 x its bound) slots; when the tables of all
+     * heavy rows exceed the limit, the rows are processed in waves of
+     * consecutive rows whose tables fit, and the pool is reused from wave
+     * to wave (a row whose own table exceeds the limit forms a wave alone,
+     * with a pool of its size). */
+    SMASH_OPT_GLOBAL_POOL = 5,
+    SMASH_OPT_COUNT = 6
 } smash_option;
 
 /* Counters of the last symbolic/numeric call (smash_get_stats). */
@@ -108,6 +116,8 @@ typedef struct {
     int64_t fused_rows;         /* rows completed by the fused pass (smash_spgemm_fused) */
     int64_t fused_overflow;     /* rows the fused pass handed back (prediction too small) */
     int64_t fused_capacity;     /* sum of the capacities the fused pass reserved (staging slots) */
+    int64_t global_waves;       /* launches of global-mode row waves (symbolic + numeric) */
+    int64_t global_pool;        /* slots of the global table pool used (the largest wave) */
 } smash_stats;
 
 /* Allocation callback of smash_spgemm: return device memory of at least

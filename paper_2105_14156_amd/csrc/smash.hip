@@ -21,6 +21,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <utility>
 #include <vector>
 
 using namespace smash;
@@ -83,6 +84,10 @@ struct Plan {
     long long *bsum = nullptr, *gsz = nullptr, *goff_sym = nullptr, *goff_num = nullptr;
     int *bsplit = nullptr, *wcnt = nullptr, *woff = nullptr, *seg_bcount = nullptr;
     Seg *segs = nullptr;
+    // global mode: waves of heavy rows (first row and table offset of each
+    // wave, then the end) and the pool each pass needs
+    std::vector<std::pair<int, long long>> sym_waves, num_waves;
+    long long sym_pool = 0, num_pool = 0;
     // fused pass (rows sized by the predictor)
     bool fused = false;
     int fused_dtype = 0;
@@ -104,7 +109,7 @@ struct Pending {
 struct smash_ctx_s {
     int device = 0;
     std::string err;
-    int64_t opt[SMASH_OPT_COUNT] = {1, 1024, 0, 0, 0};
+    int64_t opt[SMASH_OPT_COUNT] = {1, 1024, 0, 0, 0, 0};
     DevHdr *h_hdr = nullptr;   // pinned host mirror
     DevHdr *d_hdr = nullptr;
     Arena plan_mem, heavy_mem, gkeys, gvals, mlp_mem, pred_mem, fused_mem, stage_mem;
@@ -384,19 +389,24 @@ smash_status numeric_impl(smash_ctx c, hipStream_t s, const Plan &p, const V *Av
         }
         return SMASH_OK;
     }
-    // global-memory hash tables
-    const unsigned long long slots = p.hdr.gneed[1];
-    TRY(ensure(c, c->gkeys, slots * sizeof(int), s));
-    TRY(ensure(c, c->gvals, slots * sizeof(V), s));
+    // global-memory hash tables, in the waves planned by the symbolic phase
+    // (each row clears its own table, so the pool is reused as it is)
+    TRY(ensure(c, c->gkeys, (size_t)p.num_pool * sizeof(int), s));
+    TRY(ensure(c, c->gvals, (size_t)p.num_pool * sizeof(V), s));
     const size_t lds = (size_t)kGlobalRankBits / 8;
     (void)hipFuncSetAttribute((const void *)k_num_global<V>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     const int *rows = p.num_perm + p.hdr.num.offset[kBinHeavy];
-    return launch(c, K_NUM_GLOBAL, s, [&] {
-        k_num_global<V><<<H, kGlobalThreads, lds, s>>>(p.A.row_ptr, p.A.col_idx, Aval, p.B.row_ptr, p.B.col_idx, Bval,
-                                                       rows, (int)p.n, p.goff_num, (int *)c->gkeys.ptr,
-                                                       (V *)c->gvals.ptr, (const long long *)crp, ccol, cval,
-                                                       &c->d_hdr->error);
-    });
+    for (size_t w = 0; w + 1 < p.num_waves.size(); ++w) {
+        const int h0 = p.num_waves[w].first, nh = p.num_waves[w + 1].first - h0;
+        const long long base = p.num_waves[w].second;
+        TRY(launch(c, K_NUM_GLOBAL, s, [&] {
+            k_num_global<V><<<nh, kGlobalThreads, lds, s>>>(p.A.row_ptr, p.A.col_idx, Aval, p.B.row_ptr, p.B.col_idx,
+                                                            Bval, rows + h0, (int)p.n, p.goff_num + h0, base,
+                                                            (int *)c->gkeys.ptr, (V *)c->gvals.ptr,
+                                                            (const long long *)crp, ccol, cval, &c->d_hdr->error);
+        }));
+    }
+    return SMASH_OK;
 }
 
 template <typename V, int LOGT>
@@ -591,6 +601,9 @@ smash_status smash_set_option(smash_ctx c, smash_option opt, int64_t v)
     case SMASH_OPT_HEAVY_MODE:
         if (v != 0 && v != 1) return fail(c, SMASH_ERR_INVALID_ARG, "heavy mode is 0 (windowed) or 1 (global hash)");
         break;
+    case SMASH_OPT_GLOBAL_POOL:
+        if (v < 0) return fail(c, SMASH_ERR_INVALID_ARG, "global pool limit must be >= 0 (0 = no limit)");
+        break;
     default: return fail(c, SMASH_ERR_INVALID_ARG, "unknown option %d", (int)opt);
     }
     c->opt[opt] = v;
@@ -606,6 +619,38 @@ smash_status smash_get_option(smash_ctx c, smash_option opt, int64_t *v)
 }
 
 namespace {
+
+// Heavy rows [0, H) of the global mode in waves of consecutive rows whose
+// tables fit `limit` slots (goff: device, the H + 1 table offsets, an
+// exclusive prefix).  One wave without a limit or when all tables fit;
+// otherwise the offsets are read back and split greedily, a row whose table
+// alone exceeds the limit forming a wave of its own.  bounds receives the
+// first row and table offset of every wave followed by (H, goff[H]); pool
+// the slots of the largest wave.
+smash_status plan_global_waves(smash_ctx c, hipStream_t s, const long long *goff, int H, long long total,
+                               int64_t limit, std::vector<std::pair<int, long long>> &bounds, long long &pool)
+{
+    bounds.clear();
+    if (limit <= 0 || total <= limit) {
+        bounds.push_back({0, 0});
+        bounds.push_back({H, total});
+        pool = total;
+        return SMASH_OK;
+    }
+    std::vector<long long> off((size_t)H + 1);
+    HIP_TRY(c, hipMemcpyAsync(off.data(), goff, off.size() * sizeof(long long), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    pool = 0;
+    for (int h = 0; h < H;) {
+        int e = h + 1;
+        while (e < H && off[e + 1] - off[h] <= limit) ++e;
+        bounds.push_back({h, off[h]});
+        pool = std::max(pool, off[e] - off[h]);
+        h = e;
+    }
+    bounds.push_back({H, off[H]});
+    return SMASH_OK;
+}
 
 // The symbolic pipeline; with fused_dtype >= 0 it first runs the fused stage
 // for the rows the predictor sizes into LDS (smash_spgemm_fused).
@@ -740,13 +785,19 @@ smash_status symbolic_impl(smash_ctx c, const smash_csr *A, const smash_csr *B, 
         }));
     } else if (H > 0) {
         TRY(read_hdr(c, s));
-        const unsigned long long need = c->h_hdr->gneed[0];
-        TRY(ensure(c, c->gkeys, need * sizeof(int), s));
-        TRY(launch(c, K_FILL, s, [&] { k_fill_i32<<<2048, 256, 0, s>>>((long long)need, (int *)c->gkeys.ptr, kEmpty); }));
-        TRY(launch(c, K_SYM_GLOBAL, s, [&] {
-            k_sym_global<<<H, kGlobalThreads, 0, s>>>(A->row_ptr, A->col_idx, B->row_ptr, B->col_idx, heavy_rows, p.cap,
-                                                      p.goff_sym, (int *)c->gkeys.ptr, p.nnzc, &c->d_hdr->error);
-        }));
+        TRY(plan_global_waves(c, s, p.goff_sym, H, (long long)c->h_hdr->gneed[0], c->opt[SMASH_OPT_GLOBAL_POOL],
+                              p.sym_waves, p.sym_pool));
+        TRY(ensure(c, c->gkeys, (size_t)p.sym_pool * sizeof(int), s));
+        for (size_t w = 0; w + 1 < p.sym_waves.size(); ++w) {
+            const int h0 = p.sym_waves[w].first, nh = p.sym_waves[w + 1].first - h0;
+            const long long base = p.sym_waves[w].second, slots = p.sym_waves[w + 1].second - base;
+            TRY(launch(c, K_FILL, s, [&] { k_fill_i32<<<2048, 256, 0, s>>>(slots, (int *)c->gkeys.ptr, kEmpty); }));
+            TRY(launch(c, K_SYM_GLOBAL, s, [&] {
+                k_sym_global<<<nh, kGlobalThreads, 0, s>>>(A->row_ptr, A->col_idx, B->row_ptr, B->col_idx,
+                                                           heavy_rows + h0, p.cap, p.goff_sym + h0, base,
+                                                           (int *)c->gkeys.ptr, p.nnzc, &c->d_hdr->error);
+            }));
+        }
     }
 
     // a4: C_row_ptr = exclusive scan of the row counts
@@ -780,6 +831,9 @@ smash_status symbolic_impl(smash_ctx c, const smash_csr *A, const smash_csr *B, 
     TRY(read_hdr(c, s));
     p.hdr = *c->h_hdr;
     TRY(device_errors(c, p.hdr.error));
+    if (H > 0 && global)
+        TRY(plan_global_waves(c, s, p.goff_num, H, (long long)p.hdr.gneed[1], c->opt[SMASH_OPT_GLOBAL_POOL],
+                              p.num_waves, p.num_pool));
     *C_nnz = p.hdr.nnz_c;
     c->stats.products = (int64_t)p.hdr.products;
     c->stats.nnz_c = p.hdr.nnz_c;
@@ -791,6 +845,9 @@ smash_status symbolic_impl(smash_ctx c, const smash_csr *A, const smash_csr *B, 
     c->stats.nnz_heavy = p.hdr.num.wsum[kBinHeavy];
     c->stats.nnz_dense = global ? 0 : p.hdr.seg.nnz[kSegDense];
     c->stats.global_slots = global ? (int64_t)(p.hdr.gneed[0] + p.hdr.gneed[1]) : 0;
+    c->stats.global_waves = (int64_t)(p.sym_waves.empty() ? 0 : p.sym_waves.size() - 1) +
+                            (int64_t)(p.num_waves.empty() ? 0 : p.num_waves.size() - 1);
+    c->stats.global_pool = std::max(p.sym_pool, p.num_pool);
     if (fuse) {
         c->stats.fused_rows = p.hdr.fused_ok;
         c->stats.fused_overflow = p.hdr.fz.offset[kLdsBins] - p.hdr.fused_ok;

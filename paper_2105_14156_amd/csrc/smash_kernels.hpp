@@ -1491,12 +1491,13 @@ __device__ __forceinline__ void sym_global_row(const int *__restrict__ Arp, cons
 __global__ __launch_bounds__(kGlobalThreads) void k_sym_global(
     const int *__restrict__ Arp, const int *__restrict__ Acol, const int *__restrict__ Brp,
     const int *__restrict__ Bcol, const int *__restrict__ rows, const int *__restrict__ cap,
-    const long long *__restrict__ goff, int *gkeys, int *__restrict__ nnzc, int *err)
+    const long long *__restrict__ goff, long long gbase, int *gkeys, int *__restrict__ nnzc, int *err)
 {
     __shared__ EnumScratch<float, kGlobalThreads> S;
     __shared__ int s_cnt;
     const int row = rows[blockIdx.x];
-    sym_global_row(Arp, Acol, Brp, Bcol, row, cap[row], gkeys + goff[blockIdx.x], S, &s_cnt, &nnzc[row], err);
+    sym_global_row(Arp, Acol, Brp, Bcol, row, cap[row], gkeys + (goff[blockIdx.x] - gbase), S, &s_cnt, &nnzc[row],
+                   err);
 }
 
 // Numeric pass of one heavy row in global mode by a whole block: clears the
@@ -1601,14 +1602,15 @@ template <typename V>
 __global__ __launch_bounds__(kGlobalThreads) void k_num_global(
     const int *__restrict__ Arp, const int *__restrict__ Acol, const V *__restrict__ Aval,
     const int *__restrict__ Brp, const int *__restrict__ Bcol, const V *__restrict__ Bval,
-    const int *__restrict__ rows, int ncols, const long long *__restrict__ goff, int *gkeys, V *gvals,
-    const long long *__restrict__ Crp, int *__restrict__ Ccol, V *__restrict__ Cval, int *err)
+    const int *__restrict__ rows, int ncols, const long long *__restrict__ goff, long long gbase, int *gkeys,
+    V *gvals, const long long *__restrict__ Crp, int *__restrict__ Ccol, V *__restrict__ Cval, int *err)
 {
     extern __shared__ unsigned s_bm[];                     // [kGlobalRankBits / 32]
     __shared__ GlobalNumLds<V> L;
     const int row = rows[blockIdx.x];
-    num_global_row<V>(Arp, Acol, Aval, Brp, Bcol, Bval, row, row, ncols, gkeys + goff[blockIdx.x],
-                      gvals + goff[blockIdx.x], L, s_bm, Crp, Ccol, Cval, err);
+    const long long at = goff[blockIdx.x] - gbase;
+    num_global_row<V>(Arp, Acol, Aval, Brp, Bcol, Bval, row, row, ncols, gkeys + at, gvals + at, L, s_bm, Crp, Ccol,
+                      Cval, err);
 }
 
 }  // namespace smash

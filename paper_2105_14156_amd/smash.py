@@ -24,7 +24,7 @@ OK = 0
 STATUS = {0: "SMASH_OK", 1: "SMASH_ERR_INVALID_ARG", 2: "SMASH_ERR_INVALID_CSR", 3: "SMASH_ERR_INDEX_OVERFLOW",
           4: "SMASH_ERR_CAPACITY", 5: "SMASH_ERR_OUT_OF_MEMORY", 6: "SMASH_ERR_HIP", 7: "SMASH_ERR_NO_PLAN"}
 F32, F64 = 0, 1
-OPT_VALIDATE, OPT_LDS_ROW_MAX, OPT_HEAVY_MODE, OPT_TIMING, OPT_FUSED_SIZING = range(5)
+OPT_VALIDATE, OPT_LDS_ROW_MAX, OPT_HEAVY_MODE, OPT_TIMING, OPT_FUSED_SIZING, OPT_GLOBAL_POOL = range(6)
 
 
 class CsrDesc(ctypes.Structure):
@@ -36,7 +36,8 @@ class Stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in ("rows", "products", "nnz_c", "rows_empty", "rows_lds",
                                                "rows_heavy", "heavy_segments", "heavy_dense_chunks",
                                                "global_slots", "nnz_heavy", "nnz_dense", "fused_rows",
-                                               "fused_overflow", "fused_capacity")]
+                                               "fused_overflow", "fused_capacity", "global_waves",
+                                               "global_pool")]
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}

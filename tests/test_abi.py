@@ -57,3 +57,23 @@ def test_binding_matches_header():
     from paper_2105_14156_amd import smash
     for n in declared_functions():
         assert hasattr(smash._lib, n)
+
+
+def _struct_fields(name):
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct \{([^}]*)\}\s*" + name + ";", text).group(1)
+    return [f for decl in body.split(";") if decl.strip()
+            for f in re.sub(r"^\s*[a-z0-9_]+\s+", "", decl.strip()).replace(" ", "").split(",")]
+
+
+def test_binding_layouts_match_header():
+    """Field order of smash_stats and the option numbers in the binding
+    follow the header (the binding mirrors them by hand)."""
+    from paper_2105_14156_amd import smash
+    assert [n for n, _ in smash.Stats._fields_] == _struct_fields("smash_stats")
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    opts = dict((k, int(v)) for k, v in re.findall(r"SMASH_OPT_([A-Z_]+)\s*=\s*(\d+)", text))
+    for k, v in opts.items():
+        if k != "COUNT":
+            assert getattr(smash, "OPT_" + k) == v, k
+    assert opts["COUNT"] == len(opts) - 1

@@ -101,6 +101,30 @@ def test_forced_heavy_rows(sm, ctx, oracle_mod, mode, row_max):
         assert ctx.stats()["rows_heavy"] > 100
 
 
+@pytest.mark.parametrize("limit", [1, 1 << 15])
+def test_global_hash_waves(sm, ctx, oracle_mod, limit):
+    """Global mode with a bounded table pool: heavy rows run in waves of
+    consecutive rows whose tables fit (limit 1: every row alone, the pool
+    grows to the largest single table), in both phases."""
+    A = syn.rmat(13, 8, 0x77, np.float32)
+    ctx.set_option(sm.OPT_LDS_ROW_MAX, 64)
+    ctx.set_option(sm.OPT_HEAVY_MODE, 1)
+    full_check(sm, ctx, A, None, np.float32, oracle_mod, False, "global, one wave")
+    st0 = ctx.stats()
+    assert st0["global_waves"] == 2 and st0["rows_heavy"] > 100
+    ctx.set_option(sm.OPT_GLOBAL_POOL, limit)
+    for dtype in (np.float32, np.float64):
+        for split in (False, True):
+            full_check(sm, ctx, A, None, dtype, oracle_mod, split, f"global waves limit={limit} split={split}")
+            st = ctx.stats()
+            assert st["global_waves"] > 2 and st["global_pool"] < st0["global_pool"]
+            assert st["global_slots"] == st0["global_slots"]
+            if limit == 1:
+                assert st["global_waves"] == 2 * st["rows_heavy"]
+            else:
+                assert st["global_pool"] <= limit
+
+
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
 def test_rectangular(sm, ctx, oracle_mod, dtype):
     A = syn.rmat(14, 8, 0x5EED0501, dtype)
@@ -213,3 +237,7 @@ def test_errors(sm, ctx, torch_mod):
         assert e.value.status == 2
     with pytest.raises(sm.SmashError):
         ctx.set_option(sm.OPT_LDS_ROW_MAX, 5)
+    with pytest.raises(sm.SmashError):
+        ctx.set_option(sm.OPT_GLOBAL_POOL, -1)
+    with pytest.raises(sm.SmashError):
+        ctx.set_option(6, 0)
