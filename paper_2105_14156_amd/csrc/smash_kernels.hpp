@@ -310,27 +310,44 @@ __device__ __forceinline__ void group_products(int e0, int e1, int gt, EnumScrat
         const int ptot = S.pincl[G - 1], stot = S.sincl[G - 1];
         // long ranges, piece by piece: wave wg takes U consecutive pieces per
         // round; with PIPELINE the pieces of the next round are located (LDS
-        // searches) while the loads of this round are in flight
+        // searches) while the loads of this round are in flight.  A wave's
+        // pieces only move forward, so it keeps a cursor `cur` (no piece of
+        // it lies in an A entry before cur) and finds the A entry of piece
+        // pc from one wave-wide read: lane l holds the boundary
+        // pincl[cur + l - 1] (lane 0 the one before cur, never above pc),
+        // and the first lane whose boundary exceeds pc names the entry.  One
+        // read serves all U pieces of a round unless they run past it.
+        int cur = 0;
+        auto window = [&]() {
+            const int t = cur + lane - 1;
+            return t < 0 ? 0 : S.pincl[t < G ? t : G - 1];
+        };
         auto locate_pieces = [&](int pc0, int (&pos)[U], double (&av)[U]) {
-            int src = 0;
-#pragma unroll
-            for (int step = G / 2; step > 0; step >>= 1)
-                if (S.pincl[src + step - 1] <= pc0) src += step;
+            int v = window();
+            int last = cur;
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int pc = pc0 + u;
                 pos[u] = -1;
                 av[u] = 0.0;
-                if (pc < ptot) {
-                    while (S.pincl[src] <= pc) ++src;
-                    const int pex = src ? S.pincl[src - 1] : 0;
+                if (pc < ptot) {                                   // wave-uniform
+                    unsigned long long hit;
+                    while (!(hit = __ballot(v > pc))) {
+                        cur += kWave - 1;
+                        v = window();
+                    }
+                    const int k = __ffsll((long long)hit) - 1;     // >= 1
+                    const int src = cur + k - 1;
+                    const int pex = __builtin_amdgcn_readlane(v, k - 1);
                     const int p = S.bs[src] + (pc - pex) * kWave + lane;
                     if (p < S.be[src]) {
                         pos[u] = p;
                         if constexpr (WITH_VAL) av[u] = (double)S.a[src];
                     }
+                    last = src;
                 }
             }
+            cur = last;
         };
         {
             int pos[U];
