@@ -112,7 +112,7 @@ struct smash_ctx_s {
     int64_t opt[SMASH_OPT_COUNT] = {1, 1024, 0, 0, 0, 0};
     DevHdr *h_hdr = nullptr;   // pinned host mirror
     DevHdr *d_hdr = nullptr;
-    Arena plan_mem, heavy_mem, gkeys, gvals, mlp_mem, pred_mem, fused_mem, stage_mem;
+    Arena plan_mem, heavy_mem, gkeys, gvals, mlp_mem, pred_mem, fused_mem, stage_mem, valid_mem;
     bool has_predictor = false;
     float pred_delta = 0.f;
     Plan plan;
@@ -573,7 +573,7 @@ void smash_destroy(smash_ctx c)
     if (!c) return;
     DeviceGuard g(c->device);
     for (Arena *a : {&c->plan_mem, &c->heavy_mem, &c->gkeys, &c->gvals, &c->mlp_mem, &c->pred_mem, &c->fused_mem,
-                     &c->stage_mem})
+                     &c->stage_mem, &c->valid_mem})
         if (a->ptr) (void)hipFree(a->ptr);
     if (c->d_hdr) (void)hipFree(c->d_hdr);
     if (c->h_hdr) (void)hipHostFree(c->h_hdr);
@@ -653,6 +653,25 @@ smash_status plan_global_waves(smash_ctx c, hipStream_t s, const long long *goff
     return SMASH_OK;
 }
 
+// Queues the CSR checks of one matrix (k_validate_rows, k_validate_cols)
+// on s; a violation sets `flag` in *err.  The row-start bitmap lives in the
+// context's validation arena (the stream orders successive checks).
+smash_status validate_csr(smash_ctx c, hipStream_t s, const smash_csr &M, int flag, int *err)
+{
+    if (M.rows == 0 && M.nnz == 0) return SMASH_OK;
+    const long long words = (M.nnz + 31) / 32 + 1;
+    TRY(ensure(c, c->valid_mem, (size_t)words * sizeof(unsigned), s));
+    unsigned *starts = (unsigned *)c->valid_mem.ptr;
+    TRY(launch(c, K_VALIDATE, s, [&] {
+        k_fill_i32<<<blocks_for(words, 256), 256, 0, s>>>(words, (int *)starts, 0);
+        k_validate_rows<<<blocks_for(std::max<int64_t>(M.rows, 1), 256), 256, 0, s>>>((int)M.rows, M.nnz, M.row_ptr,
+                                                                                      starts, flag, err);
+        if (M.nnz > 0)
+            k_validate_cols<<<blocks_for(M.nnz, 256), 256, 0, s>>>((int)M.cols, M.nnz, M.col_idx, starts, flag, err);
+    }));
+    return SMASH_OK;
+}
+
 // The symbolic pipeline; with fused_dtype >= 0 it first runs the fused stage
 // for the rows the predictor sizes into LDS (smash_spgemm_fused).
 smash_status symbolic_impl(smash_ctx c, const smash_csr *A, const smash_csr *B, int64_t *C_row_ptr, int64_t *C_nnz,
@@ -686,14 +705,8 @@ smash_status symbolic_impl(smash_ctx c, const smash_csr *A, const smash_csr *B, 
 
     HIP_TRY(c, hipMemsetAsync(c->d_hdr, 0, sizeof(DevHdr), s));
     if (c->opt[SMASH_OPT_VALIDATE]) {
-        TRY(launch(c, K_VALIDATE, s, [&] {
-            k_validate<<<blocks_for(std::max<int64_t>(A->rows, 1), 4), 256, 0, s>>>(
-                (int)A->rows, (int)A->cols, A->nnz, A->row_ptr, A->col_idx, kErrCsrA, &c->d_hdr->error);
-        }));
-        TRY(launch(c, K_VALIDATE, s, [&] {
-            k_validate<<<blocks_for(std::max<int64_t>(B->rows, 1), 4), 256, 0, s>>>(
-                (int)B->rows, (int)B->cols, B->nnz, B->row_ptr, B->col_idx, kErrCsrB, &c->d_hdr->error);
-        }));
+        TRY(validate_csr(c, s, *A, kErrCsrA, &c->d_hdr->error));
+        TRY(validate_csr(c, s, *B, kErrCsrB, &c->d_hdr->error));
     }
     if (c->opt[SMASH_OPT_VALIDATE] && m > 0) {
         // no kernel below may dereference an index of an invalid matrix
@@ -1497,14 +1510,11 @@ smash_status smash_batch_plan_create(smash_ctx c, smash_dtype dtype, int32_t cou
         return bail(fail(c, SMASH_ERR_HIP, "descriptor upload"));
     if (c->opt[SMASH_OPT_VALIDATE] && count > 0) {
         k_fill_i32<<<1, 256, 0, s>>>((long long)(sizeof(BatchHdr) / sizeof(int)), (int *)p->d_hdr, 0);
-        for (int q = 0; q < count; ++q) {
-            if (A[q].rows > 0 || A[q].nnz > 0)
-                k_validate<<<blocks_for(std::max<int64_t>(A[q].rows, 1), 4), 256, 0, s>>>(
-                    (int)A[q].rows, (int)A[q].cols, A[q].nnz, A[q].row_ptr, A[q].col_idx, kErrCsrA, &p->d_hdr->error);
-            if (B[q].rows > 0 || B[q].nnz > 0)
-                k_validate<<<blocks_for(std::max<int64_t>(B[q].rows, 1), 4), 256, 0, s>>>(
-                    (int)B[q].rows, (int)B[q].cols, B[q].nnz, B[q].row_ptr, B[q].col_idx, kErrCsrB, &p->d_hdr->error);
+        for (int q = 0; q < count && st == SMASH_OK; ++q) {
+            st = validate_csr(c, s, A[q], kErrCsrA, &p->d_hdr->error);
+            if (st == SMASH_OK) st = validate_csr(c, s, B[q], kErrCsrB, &p->d_hdr->error);
         }
+        if (st != SMASH_OK) return bail(st);
         st = batch_sync(*p, s);
         if (st != SMASH_OK) return bail(st);
         if (p->h_hdr->error)

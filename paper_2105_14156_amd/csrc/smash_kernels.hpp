@@ -523,30 +523,58 @@ __device__ __forceinline__ int lds_insert_key_u(int *keys, int logT, const int (
 
 // --------------------------------------------------------------- validation
 
-// Checks the CSR preconditions of one matrix, one wave per row; sets `flag`
-// in *err on failure.
-__global__ __launch_bounds__(256) void k_validate(int rows, int cols, long long nnz, const int *__restrict__ rp,
-                                                  const int *__restrict__ ci, int flag, int *err)
+// CSR preconditions of one matrix in two passes (a violation sets `flag` in
+// *err).  Rows, one thread per row: row_ptr starts at 0, ends at nnz and
+// never decreases; the first entry of every non-empty row is marked in a
+// bitmap over the entries (cleared beforehand).  Entries, one thread per
+// entry (coalesced): the column is in range and above the previous entry's
+// unless the entry starts a row.
+__global__ __launch_bounds__(256) void k_validate_rows(int rows, long long nnz, const int *__restrict__ rp,
+                                                       unsigned *__restrict__ starts, int flag, int *err)
 {
-    const int lane = lane_id();
-    const long long row = (long long)blockIdx.x * 4 + threadIdx.x / kWave;
+    const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     bool bad = false;
-    if (row == 0 && lane == 0 && (rp[0] != 0 || (long long)rp[rows] != nnz)) bad = true;
-    if (row < rows) {
-        const int a = rp[row], b = rp[row + 1];
-        if (b < a || a < 0 || (long long)b > nnz) {
-            bad = true;
-        } else {
-            for (int p = a + lane; p < b; p += kWave) {
-                const int c = ci[p];
-                if (c < 0 || c >= cols || (p > a && c <= ci[p - 1])) bad = true;
-            }
-        }
+    if (r == 0 && (rp[0] != 0 || (long long)rp[rows] != nnz)) bad = true;
+    if (r < rows) {
+        const int a = rp[r], b = rp[r + 1];
+        if (b < a || a < 0 || (long long)b > nnz) bad = true;
+        else if (a < b) atomicOr(&starts[a >> 5], 1u << (a & 31));
     }
-    if (__ballot(bad) && lane == 0) atomicOr(err, flag);
+    if (__syncthreads_or(bad) && threadIdx.x == 0) atomicOr(err, flag);
+}
+
+__global__ __launch_bounds__(256) void k_validate_cols(int cols, long long nnz, const int *__restrict__ ci,
+                                                       const unsigned *__restrict__ starts, int flag, int *err)
+{
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    bool bad = false;
+    if (p < nnz) {
+        const int c = ci[p];
+        if (c < 0 || c >= cols) bad = true;
+        else if (p > 0 && c <= ci[p - 1] && !((starts[p >> 5] >> (p & 31)) & 1u)) bad = true;
+    }
+    if (__syncthreads_or(bad) && threadIdx.x == 0) atomicOr(err, flag);
 }
 
 // --------------------------------------------------------- analysis & bins
+
+// Feature t (0..5) of the learned predictor for a row with na A entries:
+// log2(1 + x) of na, the products ub, max_k nnz(B_k), min_k nnz(B_k),
+// min(ub, cols) and sum_k nnz(B_k)^2 / ub, in double, rounded to float; 0 for
+// a row without entries.  The selection is branch-free so that six lanes
+// evaluate their features together.
+__device__ __forceinline__ float row_feature(int t, int na, long long ub, double sq, int mx, int mn, int ncols)
+{
+    if (na == 0) return 0.f;
+    const double cap = ub < ncols ? (double)ub : (double)ncols;
+    const double x = t == 0 ? (double)na
+                   : t == 1 ? (double)ub
+                   : t == 2 ? (double)mx
+                   : t == 3 ? (double)mn
+                   : t == 4 ? cap
+                            : (ub > 0 ? sq / (double)ub : 0.0);
+    return (float)log2(1.0 + x);
+}
 
 // Row analysis (step a1): products ub_i = sum_k nnz(B_k) over row i of A, the
 // output bound cap_i = min(ub_i, cols) and the row's symbolic bin.  One wave
@@ -586,22 +614,9 @@ __global__ __launch_bounds__(256) void k_analyze(int m, int ncols, int lds_row_m
             mx = a > mx ? a : mx;
             mn = b < mn ? b : mn;
         }
-        if (lane == 0) {
-            const int na = e1 - e0;
-            float *f = feats + (long long)row * 6;
-            if (na == 0) {
-                for (int t = 0; t < 6; ++t) f[t] = 0.f;
-            } else {
-                const double capd = ub < ncols ? (double)ub : (double)ncols;
-                f[0] = log2f(1.f + (float)na);
-                f[1] = (float)log2(1.0 + (double)ub);
-                f[2] = log2f(1.f + (float)mx);
-                f[3] = log2f(1.f + (float)mn);
-                f[4] = (float)log2(1.0 + capd);
-                f[5] = (float)log2(1.0 + (ub > 0 ? sq / (double)ub : 0.0));
-            }
-            maxb_out[row] = na ? mx : 0;
-        }
+        // lanes 0..5 write one feature each
+        if (lane < 6) feats[(long long)row * 6 + lane] = row_feature(lane, e1 - e0, ub, sq, mx, mn, ncols);
+        if (lane == 0) maxb_out[row] = e1 > e0 ? mx : 0;
     }
     if (lane == 0) {
         const int cap = (int)(ub < ncols ? ub : ncols);

@@ -60,22 +60,10 @@ __global__ __launch_bounds__(256) void k_features(int m, int ncols, const int *_
         mx = a > mx ? a : mx;
         mn = b < mn ? b : mn;
     }
+    if (lane < kFeat) feats[(long long)row * kFeat + lane] = row_feature(lane, e1 - e0, ub, sq, mx, mn, ncols);
     if (lane == 0) {
-        const int na = e1 - e0;
-        float *f = feats + (long long)row * kFeat;
-        if (na == 0) {
-            for (int t = 0; t < kFeat; ++t) f[t] = 0.f;
-        } else {
-            const double cap = ub < ncols ? (double)ub : (double)ncols;
-            f[0] = log2f(1.f + (float)na);
-            f[1] = (float)log2(1.0 + (double)ub);
-            f[2] = log2f(1.f + (float)mx);
-            f[3] = log2f(1.f + (float)mn);
-            f[4] = (float)log2(1.0 + cap);
-            f[5] = (float)log2(1.0 + (ub > 0 ? sq / (double)ub : 0.0));
-        }
         if (ub_out) ub_out[row] = ub;
-        if (maxb_out) maxb_out[row] = na ? mx : 0;
+        if (maxb_out) maxb_out[row] = e1 > e0 ? mx : 0;
     }
 }
 

@@ -131,6 +131,21 @@ def test_batch_without_rows(env):
     plan.close()
 
 
+def test_batch_invalid_operand(env):
+    """Creation validates every operand: one problem whose B has a repeated
+    column in a row fails the whole batch with INVALID_CSR."""
+    torch, smash, ctx = env
+    probs = _problems(6)
+    A, B = probs[4]
+    ci = B.col_idx.copy()
+    r = int(np.argmax(np.diff(B.row_ptr)))                 # a row with at least two entries
+    ci[B.row_ptr[r] + 1] = ci[B.row_ptr[r]]
+    probs[4] = (A, syn.CSR(B.rows, B.cols, B.row_ptr, ci, B.val))
+    with pytest.raises(smash.SmashError) as e:
+        _make_plan(smash, ctx, probs)
+    assert e.value.status == 2
+
+
 def test_batch_capacity_error(env):
     """A structure change after creation that needs more entries than the
     pool holds is reported as CAPACITY."""

@@ -208,6 +208,56 @@ def test_repeat_numeric_and_determinism(sm, ctx, oracle_mod, torch_mod):
     check_rows(rp.cpu().numpy(), col.cpu().numpy(), val.cpu().numpy(), oracle_mod.spgemm(A2, A2), np.float32, "revalued")
 
 
+def _mutated(base, how):
+    rp, ci = base.row_ptr.copy(), base.col_idx.copy()
+    how(rp, ci)
+    return syn.CSR(base.rows, base.cols, rp, ci, np.ones(ci.size, np.float32))
+
+
+def test_validation_walk(sm, ctx, torch_mod):
+    """Validation reads each wave's 64 rows as one range of entries, 64 at a
+    time: violations inside long rows, at a window boundary, at a row start
+    and in the row pointers of a later wave are caught; valid matrices with
+    empty rows and row starts below the previous row's last column pass."""
+    torch = torch_mod
+    n = 300
+    lens = np.where(np.arange(n) % 7 == 3, 0, 100)                      # some empty rows
+    rp = np.zeros(n + 1, np.int32)
+    rp[1:] = np.cumsum(lens)
+    ci = np.concatenate([np.sort(syn.uniform_k_per_row(1, 4096, 100, 7000 + i, np.float32).col_idx)
+                         for i in range(n) if lens[i]]).astype(np.int32)
+    base = syn.CSR(n, 4096, rp, ci, np.ones(ci.size, np.float32))
+    B = syn.uniform_k_per_row(4096, 64, 2, 5, np.float32)
+    dB = sm.to_device(B)
+    out = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+    ctx.symbolic(sm.to_device(base), dB, out)                              # valid
+    p0 = int(rp[64])                                                       # first entry of the second wave
+
+    def dup_inside(rp, ci):
+        ci[rp[200] + 50] = ci[rp[200] + 49]
+
+    def desc_at_window(rp, ci):
+        ci[p0 + 64], ci[p0 + 63] = ci[p0 + 63], ci[p0 + 64]
+
+    def out_of_range(rp, ci):
+        ci[rp[n] - 1] = 4096
+
+    def negative(rp, ci):
+        ci[rp[130]] = -1
+
+    def rp_descends(rp, ci):
+        rp[131] = rp[130] - 1
+
+    def rp_last(rp, ci):
+        rp[n] -= 1
+
+    for how in (dup_inside, desc_at_window, out_of_range, negative, rp_descends, rp_last):
+        M = _mutated(base, how)
+        with pytest.raises(sm.SmashError) as e:
+            ctx.symbolic(sm.to_device(M), dB, out)
+        assert e.value.status == 2, how.__name__
+
+
 def test_errors(sm, ctx, torch_mod):
     torch = torch_mod
     A = syn.rmat(10, 4, 1, np.float32)
