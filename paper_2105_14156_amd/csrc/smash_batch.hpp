@@ -101,11 +101,19 @@ __global__ __launch_bounds__(256) void k_banalyze(long long M, int count, const 
         const int e0 = valid ? d.Arp[row] : 0, e1 = valid ? d.Arp[row + 1] : 0;
         const bool lng = e1 - e0 > kAnalyzeShort;
         long long ub = 0;
-        if (!lng)
-            for (int e = e0; e < e1; ++e) {
+        if (!lng) {
+            // four entries at a time, so that their loads are in flight together
+            int e = e0;
+            for (; e + 4 <= e1; e += 4) {
+                const int k0 = d.Acol[e], k1 = d.Acol[e + 1], k2 = d.Acol[e + 2], k3 = d.Acol[e + 3];
+                ub += (long long)(d.Brp[k0 + 1] - d.Brp[k0]) + (d.Brp[k1 + 1] - d.Brp[k1]) +
+                      (d.Brp[k2 + 1] - d.Brp[k2]) + (d.Brp[k3 + 1] - d.Brp[k3]);
+            }
+            for (; e < e1; ++e) {
                 const int k = d.Acol[e];
                 ub += d.Brp[k + 1] - d.Brp[k];
             }
+        }
         // long rows: the whole wave sums each in turn
         unsigned long long todo = __ballot(valid && lng);
         while (todo) {
