@@ -366,7 +366,10 @@ __global__ __launch_bounds__(kWideThreads) void k_bsym_wide(const BatchDesc *__r
 // doubles indexed by column (occupancy marked by the -0.0 start value, as in
 // the dense chunks of single products), and each wave ranks its share of the
 // window with ballots and writes its entries in column order (dynamic LDS:
-// the kWideWin doubles).
+// the kWideWin doubles).  Each window enumerates only the B entries inside
+// it: a row with at most kWideThreads A entries keeps, per thread, a cursor
+// into its B row that the windows advance (one search per window); longer
+// rows search both window bounds in every B row they visit.
 template <typename V>
 __global__ __launch_bounds__(kWideThreads) void k_bnum_wide(const BatchDesc *__restrict__ desc,
                                                             const int *__restrict__ prob, const BatchHdr *bh,
@@ -395,22 +398,39 @@ __global__ __launch_bounds__(kWideThreads) void k_bnum_wide(const BatchDesc *__r
         const int arow = (int)(grow - d.row0);
         const long long rb = Crp[grow];
         const int nc = (int)(Crp[grow + 1] - rb);
+        const int e0 = d.Arp[arow], e1 = d.Arp[arow + 1];
+        const bool single = e1 - e0 <= kWideThreads;       // one A entry per thread at most
+        int cur = 0, bend = 0;                             // this thread's B row: next entry, end
+        if (single && gt < e1 - e0) {
+            const int k = Acol[e0 + gt];
+            cur = Brp[k];
+            bend = Brp[k + 1];
+        }
         int done = 0;
         for (int lo = 0; lo < d.cols; lo += kWideWin) {
+            const int hi = lo + kWideWin;
+            const int nxt = single && gt < e1 - e0 ? lower_bound_col(d.Bcol, cur, bend, hi) : 0;
             for (int t = gt; t < kWideWin; t += kWideThreads) acc[t] = -0.0;
             __syncthreads();
             group_products<V, true, kWideThreads, 4>(
-                d.Arp[arow], d.Arp[arow + 1], gt, S, d.Bcol, (const V *)d.Bval,
+                e0, e1, gt, S, d.Bcol, (const V *)d.Bval,
                 [&](int e, int &bs, int &bl, V &a) {
-                    const int k = Acol[e];
-                    bs = Brp[k];
-                    bl = Brp[k + 1] - bs;
+                    if (single) {                          // e is this thread's entry
+                        bs = cur;
+                        bl = nxt - cur;
+                    } else {
+                        const int k = Acol[e];
+                        const int b1 = Brp[k + 1];
+                        bs = lower_bound_col(d.Bcol, Brp[k], b1, lo);
+                        bl = lower_bound_col(d.Bcol, bs, b1, hi) - bs;
+                    }
                     a = Aval[e];
                 },
                 [&](int j, double p) {
                     const unsigned jl = (unsigned)(j - lo);
                     if (jl < (unsigned)kWideWin) atomicAdd(&acc[jl], p + 0.0);
                 });
+            cur = nxt;
             __syncthreads();
             double vr[ROUNDS];
             unsigned long long msk[ROUNDS];
