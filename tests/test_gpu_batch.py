@@ -117,6 +117,29 @@ def _zero_case():
     return A, B
 
 
+def test_batch_subnormal_wide_window(env, oracle_mod):
+    """FP64 heavy rows in the LDS windows (occupancy by leaving -0.0): a
+    negative subnormal sum and a cancelling sum keep their entries."""
+    torch, smash, ctx = env
+    n, width = 8192, 1500
+    cols = np.arange(width, dtype=np.int32)
+    b0, b1 = np.ones(width), np.ones(width)
+    b0[7], b1[7] = -1e-320, 0.0
+    b0[9], b1[9] = 1.0, -1.0
+    B = syn.CSR(2, n, np.array([0, width, 2 * width], np.int32), np.concatenate([cols, cols]),
+                np.concatenate([b0, b1]))
+    A = syn.CSR(1, 2, np.array([0, 2], np.int32), np.array([0, 1], np.int32), np.array([1.0, 1.0]))
+    probs = [(A, B), _problems(2, np.float64)[1]]
+    refs = [oracle_mod.spgemm(a, b) for a, b in probs]
+    plan = _make_plan(smash, ctx, probs, dict(lds_row_max=256, table_shift=1, wide_groups=0, blocks_per_cu=4))
+    plan.run()
+    _check_plan(plan, probs, refs, oracle_mod, "subnormal window")
+    C = plan.problem(0)
+    v = C.val.cpu().numpy()
+    assert v[7] == -1e-320 and v[9] == 0.0
+    plan.close()
+
+
 def test_batch_without_rows(env):
     torch, smash, ctx = env
     probs = [(syn.empty(0, 5, np.float32), syn.random_sparse(5, 5, 0.5, 1, np.float32))] * 3

@@ -187,6 +187,29 @@ def test_zero_products_keep_structure(sm, ctx, oracle_mod, dtype):
     assert np.all(val[: rp[2]] == 0.0)
 
 
+def test_dense_chunk_denormal_and_cancelling_sums(sm, ctx, oracle_mod):
+    """FP64 dense chunks mark occupancy by leaving -0.0: an entry whose sum
+    is a negative subnormal, or cancels to zero, must keep its place and
+    value (a flush of subnormals in the LDS add would drop it)."""
+    n, width = 8192, 1500
+    cols = np.arange(width, dtype=np.int32)
+    b0 = np.ones(width)
+    b1 = np.ones(width)
+    b0[7], b1[7] = -1e-320, 0.0            # product -1e-320 (subnormal); b1 adds an exact zero
+    b0[9], b1[9] = 1.0, -1.0               # cancels to +0.0
+    b0[11], b1[11] = -5e-324, -5e-324      # smallest subnormal, twice
+    B = syn.CSR(2, n, np.array([0, width, 2 * width], np.int32), np.concatenate([cols, cols]),
+                np.concatenate([b0, b1]))
+    A = syn.CSR(1, 2, np.array([0, 2], np.int32), np.array([0, 1], np.int32), np.array([1.0, 1.0]))
+    rp, col, val = run(sm, ctx, A, B, np.float64)
+    st = ctx.stats()
+    assert st["heavy_dense_chunks"] == 1, st
+    ref = oracle_mod.spgemm(A, B)
+    assert np.array_equal(col, ref["col"]) and rp[-1] == width
+    assert val[7] == -1e-320 and val[9] == 0.0 and val[11] == -1e-323
+    check_rows(rp, col, val, ref, np.float64, "subnormal dense chunk")
+
+
 def test_repeat_numeric_and_determinism(sm, ctx, oracle_mod, torch_mod):
     torch = torch_mod
     A = syn.rmat(14, 8, 0x99, np.float32)
