@@ -372,7 +372,8 @@ smash_status numeric_impl(smash_ctx c, hipStream_t s, const Plan &p, const V *Av
     const int H = p.hdr.sym.count[kBinHeavy];
     if (H == 0) return SMASH_OK;
     if (p.heavy_mode == 0) {
-        // segments of up to 128 and 512 entries: two waves each; up to 1024: four
+        // segments of up to 128 and 700 entries (tables of 256 and 1024 slots):
+        // two waves each; up to 1024 entries (2048 slots): four
         TRY(launch_seg_bin<V, 8, 128>(c, s, p, 0, Aval, Bval, crp, ccol, cval));
         TRY(launch_seg_bin<V, 10, 128>(c, s, p, 1, Aval, Bval, crp, ccol, cval));
         TRY(launch_seg_bin<V, 11, 256>(c, s, p, 2, Aval, Bval, crp, ccol, cval));

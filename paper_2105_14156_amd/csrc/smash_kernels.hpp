@@ -56,7 +56,7 @@ constexpr int kChunkWords = kChunkCols / 32;
 constexpr int kSymWinChunks = 16;       // symbolic heavy window: 16 chunks, 16 KiB bitmap
 constexpr int kSegCap = 1024;           // entries of one hashed segment (table of 2048 slots)
 constexpr int kSegMaxSpan = 8;          // chunks spanned by one hashed segment
-constexpr int kSegBins = 4;             // hashed segments with <=128, <=512, <=1024 entries; dense chunks
+constexpr int kSegBins = 4;             // hashed segments with <=128, <=700, <=1024 entries; dense chunks
 constexpr int kSegDense = 3;
 constexpr int kBinBlockRows = 1024;     // rows per block of the binning kernels
 
@@ -1190,7 +1190,7 @@ __global__ __launch_bounds__(256) void k_chunk_prefix(int nheavy, int nchunks, c
 // pass 1 writes them at offset[bin] + block base + rank in block.
 __device__ __forceinline__ int seg_bin(int count, bool dense)
 {
-    return dense ? kSegDense : (count <= 128 ? 0 : (count <= 512 ? 1 : 2));
+    return dense ? kSegDense : (count <= 128 ? 0 : (count <= 700 ? 1 : 2));
 }
 
 template <typename F>
