@@ -827,7 +827,7 @@ smash_status symbolic_impl(smash_ctx c, const smash_csr *A, const smash_csr *B, 
     if (H > 0 && !global) {
         const int nhb = (int)blocks_for(H, 256);
         TRY(launch(c, K_CHUNK_PREFIX, s, [&] {
-            k_chunk_prefix<<<nhb, 256, 0, s>>>(H, p.nchunks, p.wcnt, p.woff);
+            k_chunk_prefix<<<blocks_for(H, 4), 256, 0, s>>>(H, p.nchunks, p.wcnt, p.woff);
         }));
         TRY(launch(c, K_FILL, s, [&] {
             k_fill_i32<<<blocks_for(kSegBins * p.nchunks, 256), 256, 0, s>>>((long long)kSegBins * p.nchunks,

@@ -1169,17 +1169,22 @@ __global__ __launch_bounds__(kSymHeavyThreads) void k_sym_heavy(
 }
 
 // Exclusive prefix of the chunk counts of every heavy row (row-relative output
-// offsets of the chunks); one thread per heavy row.
+// offsets of the chunks); one wave per heavy row, 64 chunks per step
+// (coalesced).
 __global__ __launch_bounds__(256) void k_chunk_prefix(int nheavy, int nchunks, const int *__restrict__ wcnt,
                                                       int *__restrict__ woff)
 {
-    const int h = blockIdx.x * blockDim.x + threadIdx.x;
+    const int h = blockIdx.x * 4 + threadIdx.x / kWave;
     if (h >= nheavy) return;
+    const int lane = lane_id();
     const long long base = (long long)h * nchunks;
     int run = 0;
-    for (int c = 0; c < nchunks; ++c) {
-        woff[base + c] = run;
-        run += wcnt[base + c];
+    for (int c0 = 0; c0 < nchunks; c0 += kWave) {
+        const int c = c0 + lane;
+        const int v = c < nchunks ? wcnt[base + c] : 0;
+        const int incl = wave_incl_scan(v);
+        if (c < nchunks) woff[base + c] = run + incl - v;
+        run += __shfl(incl, kWave - 1, kWave);
     }
 }
 
