@@ -87,16 +87,58 @@ def committed_traffic(workload: str, kernel: str):
     return int(k["hbm_bytes_scaled"]) if k else None
 
 
+def copy_gbs(mib: int = 1024, reps: int = 5) -> float:
+    """Bandwidth of a plain device copy (read + write bytes per second), the
+    measured counterpart of the 8 TB/s peak."""
+    import torch
+    x = torch.ones(mib << 20, dtype=torch.uint8, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    del x, y
+    return 2.0 * (mib << 20) / dt / 1e9
+
+
+def predictor_report(ctx, smash, dA, dB, counts, fused):
+    """Quality of the shipped predictor on this product: log2 MAE of its
+    prediction against the exact row counts (rows with products), the
+    overflow rate and the LDS slots it reserves beyond the entries of the
+    rows it completed, and the end-to-end gain over exact upper-bound
+    sizing (T-gain)."""
+    import torch
+    from paper_2105_14156_amd import predictor
+    params, ms, _ = predictor.load(predictor.DEFAULT_PATH)
+    feats = ctx.features(dA, dB)
+    yhat = ctx.mlp_predict(feats, torch.from_numpy(params).cuda(), torch.from_numpy(ms).cuda())
+    keep = feats[:, 1] > 0
+    mae = (yhat[keep] - torch.log2(1.0 + counts[keep].double()).float()).abs().mean().item()
+    ln, ub = fused["learned"], fused["upper_bound"]
+    tried = ln["fused_rows"] + ln["overflow_rows"]
+    return {"log2_mae": round(mae, 4), "rows_with_products": int(keep.sum().item()),
+            "overflow_rate": round(ln["overflow_rows"] / max(1, tried), 5),
+            "reserved_slots": ln["reserved_slots"], "entries_of_fused_rows": ln["fused_entries"],
+            "wasted_slots": ln["reserved_slots"] - ln["fused_entries"],
+            "upper_bound_reserved_slots": ub["reserved_slots"],
+            "t_gain": round(ub["ms_per_step"] / ln["ms_per_step"], 4)}
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(A, B, target_s):
+def cpu_baseline(A, B, target_s, threads=None):
     """The oracle timed on a seeded row sample of the same product (all host
-    threads up to 16), scaled to GFLOP/s of 2 x products."""
+    threads up to 16, or `threads`), scaled to GFLOP/s of 2 x products."""
     import oracle
     ub = oracle.products_per_row(A, B)
-    threads = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()))
+    if threads is None:
+        threads = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity")
+                             else os.cpu_count()))
     # calibrate on a small sample, then size the timed sample to about target_s
     total = int(ub.sum())
     rng_rows = np.argsort(synthetic.uniform01(0xBA5E, 0, A.rows), kind="stable")
@@ -240,13 +282,17 @@ def main():
     ctx.set_option(smash.OPT_TIMING, 1)
     ctx.reset_kernel_times()
     torch.cuda.synchronize()
+    step_ms = []
     t0 = time.perf_counter()
     for i in range(args.steps):
+        ts = time.perf_counter()
         C = None
         C = run()
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        step_ms.append((time.perf_counter() - ts) * 1e3)
     elapsed = time.perf_counter() - t0
     log(f"timed {args.steps} steps in {elapsed:.3f} s")
+    counts = C.row_ptr[1:] - C.row_ptr[:-1]
     kt = ctx.kernel_times()
     ctx.set_option(smash.OPT_TIMING, 0)
     st = ctx.stats()
@@ -296,7 +342,16 @@ def main():
                      "alg_bytes_per_launch": int(per_launch_bytes), "c_entry_share": round(share, 4)},
         "kernel_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in kt.items() if v[0]},
         "stats": st,
+        "ms_median": round(float(np.median(step_ms)), 4),
+        "ms_min": round(float(np.min(step_ms)), 4),
+        # row-wise re-fetches of B (an entry per product) and the symbolic
+        # pass's index reads on top of the compulsory bytes; mostly L2/MALL
+        "streamed_gb_per_step": round((alg + products * (vbytes + 4) + products * 4) / 1e9, 3),
+        "streamed_gbs": round((alg + products * (vbytes + 4) + products * 4) / (elapsed / args.steps) / 1e9, 1),
     }
+    cg = copy_gbs()
+    out["copy_gbs_measured"] = round(cg, 1)
+    out["path_frac_of_copy"] = round(path_gbs / cg, 4)
     if not args.no_variants:
         # the fused pass on the same product, with the learned capacities and
         # with the exact upper bound min(products, cols) (no network), and the
@@ -323,7 +378,8 @@ def main():
             ctx.set_option(smash.OPT_FUSED_SIZING, sizing)
             ms_f, st_f = timed(lambda: ctx.spgemm_fused(dA, dB, stream))
             fused[name] = {"ms_per_step": round(ms_f, 4), "fused_rows": st_f["fused_rows"],
-                           "overflow_rows": st_f["fused_overflow"], "reserved_slots": st_f["fused_capacity"]}
+                           "overflow_rows": st_f["fused_overflow"], "reserved_slots": st_f["fused_capacity"],
+                           "fused_entries": st_f["fused_entries"]}
             log(f"fused ({name} capacities): {ms_f:.3f} ms per step")
         ctx.set_option(smash.OPT_FUSED_SIZING, 0)
         if args.path == "plain":
@@ -337,6 +393,7 @@ def main():
             "fused_speedup_vs_plain": round(ms_plain / fused["learned"]["ms_per_step"], 4),
             "network_speedup_vs_upper_bound": round(fused["upper_bound"]["ms_per_step"]
                                                     / fused["learned"]["ms_per_step"], 4),
+            "predictor": predictor_report(ctx, smash, dA, dB, counts, fused),
             "batch": {"workload": f"batch{b['count']}_rmat_x_uniform8", "graph_ms": round(b["graph_ms"], 4),
                       "plain_loop_ms": round(b["plain_loop_ms"], 3),
                       "speedup_vs_plain_loop": round(b["plain_loop_ms"] / b["graph_ms"], 2),
@@ -346,6 +403,8 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(A, B, args.cpu_seconds)
+        log("cpu baseline, one thread ...")
+        out["cpu_baseline_1thread"] = cpu_baseline(A, B, args.cpu_seconds / 3, threads=1)
     print(json.dumps(out), flush=True)
     ctx.close()
 

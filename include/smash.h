@@ -118,6 +118,7 @@ typedef struct {
     int64_t fused_capacity;     /* sum of the capacities the fused pass reserved (staging slots) */
     int64_t global_waves;       /* launches of global-mode row waves (symbolic + numeric) */
     int64_t global_pool;        /* slots of the global table pool used (the largest wave) */
+    int64_t fused_entries;      /* entries of the rows the fused pass completed */
 } smash_stats;
 
 /* Allocation callback of smash_spgemm: return device memory of at least

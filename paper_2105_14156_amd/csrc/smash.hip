@@ -489,7 +489,8 @@ smash_status fused_stage(smash_ctx c, hipStream_t s, Plan &p)
     if (p.fused_dtype == SMASH_F32) TRY(run_fused_bins<float>(c, s, p, fz));
     else TRY(run_fused_bins<double>(c, s, p, fz));
     TRY(launch(c, K_FUSED_AUX, s, [&] {
-        k_fused_mark<<<blocks_for(m, 256), 256, 0, s>>>(m, p.fbin, p.fstatus, p.sym_bin, &c->d_hdr->fused_ok);
+        k_fused_mark<<<blocks_for(m, 256), 256, 0, s>>>(m, p.fbin, p.fstatus, p.nnzc, p.sym_bin, &c->d_hdr->fused_ok,
+                                                        &c->d_hdr->fused_entries);
     }));
     return SMASH_OK;
 }
@@ -867,6 +868,7 @@ smash_status symbolic_impl(smash_ctx c, const smash_csr *A, const smash_csr *B, 
         c->stats.fused_rows = p.hdr.fused_ok;
         c->stats.fused_overflow = p.hdr.fz.offset[kLdsBins] - p.hdr.fused_ok;
         c->stats.fused_capacity = p.hdr.stage_total;
+        c->stats.fused_entries = (int64_t)p.hdr.fused_entries;
         c->stats.rows_empty -= p.hdr.fused_ok;
     }
     p.valid = true;

@@ -163,21 +163,33 @@ __global__ __launch_bounds__(kWave *WPR *RPW) void k_fused_rows(
 }
 
 // Rows completed by the fused pass leave the two-phase plan (one global
-// atomic per block for their count).
+// atomic per block for their number and one for their entries).
 __global__ __launch_bounds__(256) void k_fused_mark(int m, const unsigned char *__restrict__ fbin,
                                                     const unsigned char *__restrict__ status,
-                                                    unsigned char *__restrict__ sym_bin, int *fused_ok)
+                                                    const int *__restrict__ nnzc, unsigned char *__restrict__ sym_bin,
+                                                    int *fused_ok, unsigned long long *fused_entries)
 {
     __shared__ int s_ok;
-    if (threadIdx.x == 0) s_ok = 0;
+    __shared__ unsigned long long s_ent;
+    if (threadIdx.x == 0) {
+        s_ok = 0;
+        s_ent = 0;
+    }
     __syncthreads();
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const bool done = i < m && fbin[i] != kBinEmpty && status[i] == 1;
     if (done) sym_bin[i] = kBinEmpty;
     const unsigned long long b = __ballot(done);
-    if (lane_id() == 0 && b) atomicAdd(&s_ok, (int)__popcll(b));
+    const unsigned long long e = wave_sum((unsigned long long)(done ? nnzc[i] : 0));
+    if (lane_id() == 0 && b) {
+        atomicAdd(&s_ok, (int)__popcll(b));
+        atomicAdd(&s_ent, e);
+    }
     __syncthreads();
-    if (threadIdx.x == 0 && s_ok) atomicAdd(fused_ok, s_ok);
+    if (threadIdx.x == 0 && s_ok) {
+        atomicAdd(fused_ok, s_ok);
+        atomicAdd(fused_entries, s_ent);
+    }
 }
 
 // Copies the staged rows of the fused pass to their final offsets in C

@@ -88,6 +88,7 @@ struct DevHdr {
     SegHdr seg;
     int error;
     int fused_ok;                      // rows completed by the fused pass
+    unsigned long long fused_entries;  // their entries
 };
 
 // A column segment of a heavy row: the row, its A entries, the chunk range,

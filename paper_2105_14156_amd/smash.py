@@ -37,7 +37,7 @@ class Stats(ctypes.Structure):
                                                "rows_heavy", "heavy_segments", "heavy_dense_chunks",
                                                "global_slots", "nnz_heavy", "nnz_dense", "fused_rows",
                                                "fused_overflow", "fused_capacity", "global_waves",
-                                               "global_pool")]
+                                               "global_pool", "fused_entries")]
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}

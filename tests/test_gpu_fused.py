@@ -83,7 +83,12 @@ def test_fused_capacity_too_large(env, oracle_mod):
         st = fused_check(env, A, None, np.float32, oracle_mod, "fused delta +20")
         assert st["fused_overflow"] == 0
         ub = np.asarray(oracle_mod.products_per_row(A, A))
-        assert st["fused_rows"] == int(((ub > 0) & (np.minimum(ub, A.cols) <= 1024)).sum())
+        fused = (ub > 0) & (np.minimum(ub, A.cols) <= 1024)
+        assert st["fused_rows"] == int(fused.sum())
+        # entries of the fused rows (exact, from the oracle's row counts) and
+        # the capacity reserved for them: min(products, columns) per row
+        assert st["fused_entries"] == int(oracle_mod.row_nnz(A, A)[fused].sum())
+        assert st["fused_capacity"] == int(np.minimum(ub, A.cols)[fused].sum())
     finally:
         ctx.predictor_set(params, ms, delta)
 
