@@ -157,7 +157,18 @@ def cpu_baseline(A, B, target_s, threads=None):
     t = time.perf_counter() - t0
     return {"value": round(2.0 * prods / t / 1e9, 4), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
             "sample": f"{n_rows} seeded random rows of {A.rows} ({prods} of {total} products, "
-                      f"{prods / total:.1%}), {t:.1f} s wall"}
+                      f"{prods / total:.1%}), {t:.1f} s wall",
+            "cpu": cpu_model()}
+
+
+def cpu_model() -> str:
+    """The host CPU's model name and logical core count (/proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            names = [ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")]
+        return f"{names[0]} ({len(names)} logical cores)" if names else "unknown"
+    except OSError:
+        return "unknown"
 
 
 def products_of(A, B) -> int:
