@@ -138,3 +138,33 @@ def test_shipped_predictor_quality(env, oracle_mod):
     print(f"eligible {eligible} fused {st['fused_rows']} overflow {st['fused_overflow']}", flush=True)
     assert st["fused_rows"] >= 0.9 * eligible
     assert st["fused_overflow"] <= 0.05 * attempts
+
+
+def test_learned_sizing_gain(env, oracle_mod):
+    """What the trained network gains over the method without it (exact
+    upper-bound capacities min(products, columns)): on RMAT scale 16, edge
+    factor 16 some rows have more than 1024 products but at most 1024
+    entries; the upper bound sends them to the heavy-row path, the network
+    sizes them into LDS, so the learned pass completes more rows in one
+    pass.  Both passes give the exact C."""
+    torch, smash, ctx, _ = env
+    A = syn.rmat(16, 16, 0x5EED0607, np.float32)
+    dA = smash.to_device(A)
+    ub = np.asarray(oracle_mod.products_per_row(A, A))
+    nz = oracle_mod.row_nnz(A, A)
+    by_bound = int(((ub > 0) & (np.minimum(ub, A.cols) <= 1024)).sum())
+    recoverable = int(((np.minimum(ub, A.cols) > 1024) & (nz <= 1024)).sum())
+    got = {}
+    try:
+        for sizing in (1, 0):
+            ctx.set_option(smash.OPT_FUSED_SIZING, sizing)
+            C = ctx.spgemm_fused(dA, dA)
+            assert np.array_equal(np.diff(C.row_ptr.cpu().numpy()), nz)
+            got[sizing] = ctx.stats()
+    finally:
+        ctx.set_option(smash.OPT_FUSED_SIZING, 0)
+    ln, bd = got[0], got[1]
+    print(f"upper bound: fused {bd['fused_rows']} (of {by_bound} it may fuse); learned: fused {ln['fused_rows']}, "
+          f"overflow {ln['fused_overflow']}; rows only the network can fuse: {recoverable}", flush=True)
+    assert bd["fused_rows"] == by_bound and bd["fused_overflow"] == 0
+    assert ln["fused_rows"] > bd["fused_rows"]
