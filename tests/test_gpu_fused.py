@@ -60,6 +60,21 @@ def test_fused_rectangular(env, oracle_mod):
     fused_check(env, A, B, np.float32, oracle_mod, "fused rect")
 
 
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_fused_with_global_heavy_rows(env, oracle_mod, dtype):
+    """The fused pass beside the global-hash heavy-row path, its tables
+    processed in waves under a small pool."""
+    torch, smash, ctx, _ = env
+    ctx.set_option(smash.OPT_HEAVY_MODE, 1)
+    ctx.set_option(smash.OPT_GLOBAL_POOL, 1 << 14)
+    try:
+        st = fused_check(env, syn.rmat(13, 16, 0x5EED0608, np.float32), None, dtype, oracle_mod, "fused + global")
+        assert st["fused_rows"] > 0 and st["rows_heavy"] > 0 and st["global_waves"] > 2
+    finally:
+        ctx.set_option(smash.OPT_HEAVY_MODE, 0)
+        ctx.set_option(smash.OPT_GLOBAL_POOL, 0)
+
+
 def test_fused_capacity_too_small(env, oracle_mod):
     """delta = -6 shrinks every predicted capacity 64-fold: nearly every
     fused row overflows and goes through the exact path."""
