@@ -84,6 +84,7 @@ struct Plan {
     long long *bsum = nullptr, *gsz = nullptr, *goff_sym = nullptr, *goff_num = nullptr;
     int *bsplit = nullptr, *wcnt = nullptr, *woff = nullptr, *seg_bcount = nullptr;
     Seg *segs = nullptr;
+    int *queue = nullptr;                 // work-queue counter of the persistent dense kernel
     // global mode: waves of heavy rows (first row and table offset of each
     // wave, then the end) and the pool each pass needs
     std::vector<std::pair<int, long long>> sym_waves, num_waves;
@@ -121,6 +122,7 @@ struct smash_ctx_s {
     std::vector<Pending> pending;
     int64_t launches[K_COUNT] = {};
     double ms[K_COUNT] = {};
+    int cus = 256;                 // compute units of the device
 };
 
 namespace {
@@ -203,6 +205,18 @@ hipEvent_t take_event(smash_ctx c)
 
 // Launches `fn` (a lambda issuing one kernel) and, with timing on, brackets
 // it with events on the same stream.
+// Blocks of `kernel` (block size `threads`, `lds` bytes of dynamic LDS)
+// resident on the whole device at once: the grid of a persistent kernel.
+int resident_blocks(smash_ctx c, const void *kernel, int threads, size_t lds)
+{
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, lds) != hipSuccess || per_cu < 1) {
+        (void)hipGetLastError();
+        per_cu = 1;
+    }
+    return per_cu * c->cus;
+}
+
 template <typename F>
 smash_status launch(smash_ctx c, int kid, hipStream_t s, F fn)
 {
@@ -383,10 +397,14 @@ smash_status numeric_impl(smash_ctx c, hipStream_t s, const Plan &p, const V *Av
             (void)hipFuncSetAttribute((const void *)k_num_dense<V>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             const int *hrows = p.sym_perm + p.hdr.sym.offset[kBinHeavy];
             const Seg *segs = p.segs + p.hdr.seg.offset[kSegDense];
+            // persistent: as many blocks as are resident at once, fed by a queue
+            const int grid = std::min(nd, resident_blocks(c, (const void *)k_num_dense<V>, kDenseThreads, lds));
+            TRY(launch(c, K_FILL, s, [&] { k_fill_i32<<<1, kWave, 0, s>>>(1, p.queue, 0); }));
             TRY(launch(c, K_NUM_DENSE, s, [&] {
-                k_num_dense<V><<<nd, kDenseThreads, lds, s>>>(p.A.row_ptr, p.A.col_idx, Aval, p.B.col_idx, Bval,
-                                                             p.bsplit, (long long)(p.nchunks + 1), hrows, segs, p.nchunks, p.woff,
-                                                             (const long long *)crp, ccol, cval, &c->d_hdr->error);
+                k_num_dense<V><<<grid, kDenseThreads, lds, s>>>(p.A.row_ptr, p.A.col_idx, Aval, p.B.col_idx, Bval,
+                                                               p.bsplit, (long long)(p.nchunks + 1), hrows, segs, p.nchunks,
+                                                               p.woff, (const long long *)crp, ccol, cval,
+                                                               &c->d_hdr->error, nd, p.queue);
             }));
         }
         return SMASH_OK;
@@ -566,6 +584,9 @@ smash_status smash_create(smash_ctx *out, int device)
         return SMASH_ERR_OUT_OF_MEMORY;
     }
     memset(c->h_hdr, 0, sizeof(DevHdr));
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+        c->cus = cus;
     *out = c;
     return SMASH_OK;
 }
@@ -782,7 +803,7 @@ smash_status symbolic_impl(smash_ctx c, const smash_csr *A, const smash_csr *B, 
         const size_t cells = (size_t)H * p.nchunks;
         const size_t need = carve_size({(size_t)(kdim * (p.nchunks + 1)) * sizeof(int), cells * sizeof(int),
                                         cells * sizeof(int), (size_t)kSegBins * p.nchunks * sizeof(int),
-                                        cells * sizeof(Seg)});
+                                        cells * sizeof(Seg), 64 * sizeof(int)});
         TRY(ensure(c, c->heavy_mem, need, s));
         Carve cv{(char *)c->heavy_mem.ptr};
         p.bsplit = cv.take<int>((size_t)(kdim * (p.nchunks + 1)));
@@ -790,6 +811,7 @@ smash_status symbolic_impl(smash_ctx c, const smash_csr *A, const smash_csr *B, 
         p.woff = cv.take<int>(cells);
         p.seg_bcount = cv.take<int>((size_t)kSegBins * p.nchunks);
         p.segs = cv.take<Seg>(cells);
+        p.queue = cv.take<int>(64);
         TRY(launch(c, K_BSPLIT, s, [&] {
             k_bsplit<<<blocks_for(kdim * (p.nchunks + 1), 256), 256, 0, s>>>((int)kdim, p.nchunks, B->row_ptr,
                                                                             B->col_idx, p.bsplit);

@@ -1393,7 +1393,11 @@ __global__ __launch_bounds__(THREADS) void k_num_seg(
 // needs no bitmap: the array starts at -0.0 and every product is added as
 // p + 0.0, which is never -0.0, so a column was reached exactly when its sum
 // is no longer the bit pattern of -0.0 (a sum of terms that are not -0.0 is
-// never -0.0 under round-to-nearest, even when they cancel).
+// never -0.0 under round-to-nearest, even when they cancel).  The kernel is
+// persistent: a grid that fills the GPU once takes the dense chunks from a
+// global queue (one atomic per chunk), so that long and short chunks balance
+// across CUs, and each wave puts -0.0 back as it ranks its columns, so the
+// array is ready for the next chunk without a separate clearing pass.
 constexpr int kDenseThreads = 512;
 constexpr long long kNegZeroBits = (long long)0x8000000000000000ULL;
 
@@ -1403,7 +1407,7 @@ __global__ __launch_bounds__(kDenseThreads) void k_num_dense(
     const int *__restrict__ Bcol, const V *__restrict__ Bval, const int *__restrict__ Bsplit, long long per,
     const int *__restrict__ heavy_rows, const Seg *__restrict__ segs, int nchunks,
     const int *__restrict__ woff, const long long *__restrict__ Crp, int *__restrict__ Ccol,
-    V *__restrict__ Cval, int *err)
+    V *__restrict__ Cval, int *err, int nseg, int *queue)
 {
     constexpr int NW = kDenseThreads / kWave;
     constexpr int CPW = kChunkCols / NW;              // columns ranked by each wave
@@ -1412,13 +1416,17 @@ __global__ __launch_bounds__(kDenseThreads) void k_num_dense(
     double *acc = (double *)s_raw;                      // [kChunkCols]
     __shared__ EnumScratch<V, kDenseThreads> S;
     __shared__ int s_wt[NW];
-    const Seg sg = segs[blockIdx.x];
+    __shared__ int s_next;
     const int gt = threadIdx.x, lane = lane_id(), wg = gt / kWave;
+    for (int t = gt; t < kChunkCols; t += kDenseThreads) acc[t] = -0.0;
+    for (;;) {
+    if (gt == 0) s_next = atomicAdd(queue, 1);
+    __syncthreads();                                    // also: the previous chunk is fully written
+    if (s_next >= nseg) break;
+    const Seg sg = segs[s_next];
     const int lo = sg.c0 * kChunkCols;
     const int *__restrict__ split0 = Bsplit + sg.c0;
     const int *__restrict__ split1 = split0 + 1;
-    for (int t = gt; t < kChunkCols; t += kDenseThreads) acc[t] = -0.0;
-    __syncthreads();
     auto get = [&](int e, int &bs, int &bl, V &a) {
         const int k = Acol[e];
         bs = split0[k * per];
@@ -1436,6 +1444,7 @@ __global__ __launch_bounds__(kDenseThreads) void k_num_dense(
     for (int r = 0; r < ROUNDS; ++r) {
         const int jl = wg * CPW + r * kWave + lane;
         vr[r] = acc[jl];
+        acc[jl] = -0.0;                                 // cleared for the next chunk
         msk[r] = __ballot(__double_as_longlong(vr[r]) != kNegZeroBits);
         wcount += __popcll(msk[r]);
     }
@@ -1460,6 +1469,8 @@ __global__ __launch_bounds__(kDenseThreads) void k_num_dense(
             }
         }
         run += __popcll(msk[r]);
+    }
+    __syncthreads();                                    // s_wt and s_next are reused
     }
 }
 
