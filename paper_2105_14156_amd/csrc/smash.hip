@@ -1351,7 +1351,8 @@ void batch_numeric(const BPlan &p, hipStream_t s)
     if (p.cfg.wide_groups) bnum_bins<V, 1>(p, s);
     else bnum_bins<V, 0>(p, s);
     k_bnum_wide<V><<<bgrid(p, p.M), kWideThreads, kWideWin * sizeof(double), s>>>(
-        p.d_desc, p.prob, p.d_hdr, p.num_perm, p.ccap, p.crp, p.ccol, (V *)p.cval, &p.d_hdr->error);
+        p.d_desc, p.prob, p.d_hdr, p.num_perm, p.ccap, p.crp, p.ccol, (V *)p.cval, &p.d_hdr->error,
+        &p.d_hdr->wide_queue);
     if (p.any_global)
         k_bnum_global<V><<<bgrid(p, p.M), kGlobalThreads, kGlobalRankBits / 8, s>>>(
         p.d_desc, p.prob, p.d_hdr, p.num_perm, p.goff, p.gcap, p.gkeys, (V *)p.gvals, p.ccap, p.crp, p.ccol,

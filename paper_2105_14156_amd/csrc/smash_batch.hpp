@@ -35,7 +35,7 @@ struct BatchHdr {
     long long nnz_c;            // total entries of all C_p
     long long gneed;            // global table slots of the heavy rows
     int error;
-    int pad;
+    int wide_queue;             // next heavy row of the windowed numeric kernel
 };
 
 enum : int { kErrCapacity = 16 };
@@ -375,7 +375,7 @@ __global__ __launch_bounds__(kWideThreads) void k_bnum_wide(const BatchDesc *__r
                                                             const int *__restrict__ prob, const BatchHdr *bh,
                                                             const int *__restrict__ perm, long long ccap,
                                                             const long long *__restrict__ Crp, int *__restrict__ Ccol,
-                                                            V *__restrict__ Cval, int *err)
+                                                            V *__restrict__ Cval, int *err, int *queue)
 {
     constexpr int NW = kWideThreads / kWave;
     constexpr int CPW = kWideWin / NW;                  // columns ranked by each wave
@@ -384,12 +384,20 @@ __global__ __launch_bounds__(kWideThreads) void k_bnum_wide(const BatchDesc *__r
     double *acc = (double *)s_raw;                      // [kWideWin]
     __shared__ EnumScratch<V, kWideThreads> S;
     __shared__ int s_wt[NW];
+    __shared__ int s_r;
     if (bh->nnz_c > ccap) return;
     const int cnt = bh->num.count[kBinHeavy];
     const int *rows = perm + bh->num.offset[kBinHeavy];
     const int gt = threadIdx.x, lane = lane_id(), wg = gt / kWave;
     const unsigned long long below = (1ull << lane) - 1ull;
-    for (int r = blockIdx.x; r < cnt; r += gridDim.x) {
+    // heavy rows from a queue (one atomic per row): long and short rows
+    // balance across the persistent blocks
+    for (;;) {
+        __syncthreads();                                // the previous row is done with s_r and the window
+        if (gt == 0) s_r = atomicAdd(queue, 1);
+        __syncthreads();
+        const int r = s_r;
+        if (r >= cnt) break;
         const int grow = rows[r];
         const BatchDesc &d = desc[prob[grow]];
         if (d.cols > kWideMaxCols) continue;
