@@ -278,8 +278,10 @@ unsigned blocks_for(long long items, int per_block)
 
 template <int LOGT>
 struct BinShape {
-    static constexpr int WPR = LOGT <= 10 ? 1 : (1 << (LOGT - 9));   // 2048 slots -> 4 waves
-    static constexpr int RPW = LOGT <= 10 ? 4 : 1;
+    // up to 512 slots: a wave per row, four rows per block; 1024 slots: two
+    // waves; 2048 slots: four waves
+    static constexpr int WPR = LOGT <= 9 ? 1 : (1 << (LOGT - 9));
+    static constexpr int RPW = WPR == 1 ? 4 : 1;
     static constexpr int THREADS = kWave * WPR * RPW;
 };
 
