@@ -1,10 +1,13 @@
 """GPU predictor kernels (features, inference, gradients, Adam training)
-against the numpy FP64 oracle."""
+against the numpy FP64 oracle, and GPU training against a closed form (the
+least-squares fit of an affine target, reached in the network's linear
+regime)."""
 import numpy as np
 import pytest
 
 import synthetic as syn
 from oracle import mlp
+from tests._mlp_cases import AFFINE_SCHEDULE, affine_case
 
 pytestmark = pytest.mark.gpu
 
@@ -72,3 +75,21 @@ def test_training_parity(env):
     np.testing.assert_allclose(losses, rlosses, rtol=1e-3)
     assert _rel(p.cpu().numpy().astype(np.float64), rth) < 1e-4
     assert losses[-1] < losses[0]
+
+
+def test_training_affine_target_reaches_lstsq(env):
+    """smash_mlp_train (full-batch Adam, FP32) on an exact affine target from
+    the linear regime ends at numpy's least-squares fit."""
+    torch, smash, ctx = env
+    F, y, mean, std, th, fitted = affine_case()
+    n = len(y)
+    t = lambda a, dt=torch.float32: torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dt)
+    ms = t(np.concatenate([mean, std]))
+    p = t(th)
+    for lr, epochs in AFFINE_SCHEDULE:
+        losses = ctx.mlp_train(t(F), t(y), ms, p, t(syn.batch_orders(n, epochs, 3), torch.int32), batch=n, lr=lr)
+    yhat = ctx.mlp_predict(t(F), p, ms).cpu().numpy().astype(np.float64)
+    dev = float(np.max(np.abs(yhat - fitted)))
+    print(f"max |yhat - lstsq fit| = {dev:.2e} (fit spread {fitted.std():.2f}); final loss {losses[-1]:.2e}")
+    assert dev < 1e-2
+    assert losses[-1] < 1e-5 * y.var()

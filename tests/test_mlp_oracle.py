@@ -1,10 +1,13 @@
 """Pins for the predictor's CPU oracle: central finite differences, torch's
-autograd (an independent implementation) and torch.optim.Adam."""
+autograd (an independent implementation), torch.optim.Adam, a torch training
+loop that cuts its own batches, and the least-squares optimum of an affine
+target that the network reaches in its linear regime."""
 import numpy as np
 import torch
 
 import synthetic as syn
 from oracle import mlp
+from tests._mlp_cases import AFFINE_SCHEDULE, affine_case
 
 
 def _data(n=37, seed=5):
@@ -85,3 +88,56 @@ def test_training_reduces_loss():
     y = np.sin(X[:, 0]) + 0.5 * X[:, 1]
     th, losses = mlp.train(syn.mlp_init(1), X, y, np.zeros(6), np.ones(6), syn.batch_orders(512, 20), 64, lr=3e-3)
     assert losses[-1] < 0.2 * losses[0]
+
+
+def _torch_net(p, X):
+    sizes = [int(np.prod(s)) for _, s in syn.MLP_LAYOUT]
+    W1, b1, W2, b2, w3, b3 = torch.split(p, sizes)
+    h1 = torch.relu(X @ W1.view(64, 6).T + b1)
+    h2 = torch.relu(h1 @ W2.view(64, 64).T + b2)
+    return h2 @ w3 + b3
+
+
+def test_train_matches_torch_adam_loop():
+    """mlp.train against torch autograd + torch.optim.Adam over the same
+    epoch orders, with the batches cut by torch.split (300 samples in
+    batches of 64: the last batch of every epoch holds 44) and one Adam
+    state carried across epochs."""
+    n, batch, epochs, lr = 300, 64, 3, 2e-3
+    F = np.abs(syn.normal01(21, 0, n * 6).reshape(n, 6)) * 3
+    y = np.sin(F[:, 0]) + 0.3 * F[:, 2]
+    mean, std = F.mean(0), F.std(0)
+    th0 = syn.mlp_init(6)
+    orders = syn.batch_orders(n, epochs, 5)
+    th, losses = mlp.train(th0, F, y, mean, std, orders, batch, lr=lr)
+
+    p = torch.tensor(th0, dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([p], lr=lr, betas=(0.9, 0.999), eps=1e-8)
+    X = torch.tensor((F - mean) / std)
+    Y = torch.tensor(y)
+    ref_losses = []
+    for order in orders:
+        batch_losses = []
+        for idx in torch.split(torch.as_tensor(np.asarray(order), dtype=torch.long), batch):
+            loss = ((_torch_net(p, X[idx]) - Y[idx]) ** 2).mean()
+            opt.zero_grad()
+            loss.backward()
+            opt.step()
+            batch_losses.append(loss.item())
+        assert len(batch_losses) == 5 and len(idx) == 44
+        ref_losses.append(sum(batch_losses) / len(batch_losses))
+    np.testing.assert_allclose(losses, ref_losses, rtol=1e-11)
+    np.testing.assert_allclose(th, p.detach().numpy(), rtol=1e-9, atol=1e-12)
+
+
+def test_train_affine_target_reaches_lstsq():
+    """Closed form: from the linear regime, training on an exact affine target
+    ends at numpy's least-squares fit (predictions within 1e-4 of the fitted
+    values, whose spread is about 3)."""
+    F, y, mean, std, th, fitted = affine_case()
+    n = len(y)
+    for lr, epochs in AFFINE_SCHEDULE:
+        th, losses = mlp.train(th, F, y, mean, std, syn.batch_orders(n, epochs, 3), n, lr=lr)
+    yhat, _ = mlp.forward(th, (F - mean) / std)
+    assert np.max(np.abs(yhat - fitted)) < 1e-4
+    assert losses[-1] < 1e-9 * y.var()
