@@ -2,7 +2,8 @@
 
 A step is one whole product through the C ABI (symbolic phase, nnz(C)
 readback, output allocation from torch's caching allocator, numeric phase)
-on inputs already resident in HBM.  Prints one JSON line.
+on inputs already resident in HBM, in one workspace sized once by
+smash_workspace_size and allocated by torch.  Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--workload s19|s16|s10|rect] [--dtype f32|f64]
 """
@@ -275,11 +276,15 @@ def main():
     ctx = smash.Context(0)
     ctx.set_option(smash.OPT_HEAVY_MODE, args.heavy_mode)
     stream = torch.cuda.current_stream()
+    # one caller-owned workspace for every call (sized with the predictor
+    # installed, so that it also covers the fused pass)
+    ctx.predictor_load()
+    ws = ctx.workspace(ctx.workspace_size(dA, dB, stream))
+    log(f"workspace {ws.numel() / 2**20:.1f} MiB")
     if args.path == "fused":
-        ctx.predictor_load()
-        run = lambda: ctx.spgemm_fused(dA, dB, stream)
+        run = lambda: ctx.spgemm_fused(dA, dB, stream, ws=ws)
     else:
-        run = lambda: ctx.spgemm(dA, dB, stream)
+        run = lambda: ctx.spgemm(dA, dB, stream, ws=ws)
 
     C = None
     for i in range(args.warmup):
@@ -387,7 +392,7 @@ def main():
         fused = {}
         for sizing, name in ((0, "learned"), (1, "upper_bound")):
             ctx.set_option(smash.OPT_FUSED_SIZING, sizing)
-            ms_f, st_f = timed(lambda: ctx.spgemm_fused(dA, dB, stream))
+            ms_f, st_f = timed(lambda: ctx.spgemm_fused(dA, dB, stream, ws=ws))
             fused[name] = {"ms_per_step": round(ms_f, 4), "fused_rows": st_f["fused_rows"],
                            "overflow_rows": st_f["fused_overflow"], "reserved_slots": st_f["fused_capacity"],
                            "fused_entries": st_f["fused_entries"]}
@@ -396,7 +401,7 @@ def main():
         if args.path == "plain":
             ms_plain = ms_step
         else:
-            ms_plain, _ = timed(lambda: ctx.spgemm(dA, dB, stream))
+            ms_plain, _ = timed(lambda: ctx.spgemm(dA, dB, stream, ws=ws))
         b = run_batch(args.batch_count, args.steps, args.warmup)
         out["variants"] = {
             "plain_ms_per_step": round(ms_plain, 4),

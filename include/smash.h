@@ -30,6 +30,24 @@
  * After an error the output buffers hold unspecified values, but nothing
  * outside them is written.  smash_last_error() returns the message of the
  * last failing call on the context.
+ *
+ * Device memory.  The multiply's calls allocate no device memory: besides
+ * its inputs and outputs, a call uses one caller-owned workspace (ws,
+ * ws_bytes; device memory, 256-byte aligned, e.g. a torch tensor) whose
+ * size smash_workspace_size() reports, and output buffers come from the
+ * caller's allocation callback.  A workspace that is too small is never
+ * written beyond ws_bytes: the call returns SMASH_ERR_CAPACITY and
+ * smash_get_stats() reports the bytes it needs (workspace_bytes).  The
+ * context itself holds only a small device header, and the weights of an
+ * installed predictor.
+ *
+ * Host synchronisation.  smash_spgemm_symbolic (and so smash_spgemm)
+ * synchronises the stream once, to read nnz(C) back (in global heavy-row
+ * mode twice more, to plan the table waves; smash_spgemm_fused once more,
+ * to size its staging area).  smash_spgemm_numeric does not synchronise:
+ * inconsistencies its kernels detect (a C_row_ptr that does not match the
+ * product) are reported by smash_sync() or, failing that, by the next
+ * symbolic call on the context.
  */
 #ifndef SMASH_H
 #define SMASH_H
@@ -55,8 +73,9 @@ typedef enum {
 
 typedef enum { SMASH_F32 = 0, SMASH_F64 = 1 } smash_dtype;
 
-/* Opaque per-device context: scratch memory cache, the plan of the last
- * symbolic call, options and per-kernel timing. */
+/* Opaque per-device context: the plan of the last symbolic call (its
+ * arrays live in the caller's workspace), options, an installed predictor
+ * and per-kernel timing. */
 typedef struct smash_ctx_s *smash_ctx;
 
 /* A CSR matrix in device memory (see the conventions above).  val may be
@@ -95,9 +114,18 @@ typedef enum {
      * heavy rows exceed the limit, the rows are processed in waves of
      * consecutive rows whose tables fit, and the pool is reused from wave
      * to wave (a row whose own table exceeds the limit forms a wave alone,
-     * with a pool of its size). */
+     * with a pool of its size).  The pool is the workspace's: a workspace
+     * smaller than all tables limits it the same way. */
     SMASH_OPT_GLOBAL_POOL = 5,
-    SMASH_OPT_COUNT = 6
+    /* Hash of the LDS row tables of light rows: 0 = multiplicative
+     * (Fibonacci) hash, entries then ordered by bitmap ranks or a bitonic
+     * sort (default); 1 = the order-preserving hash of the paper's first
+     * version (slot = column scaled to the table: High-Bit Hashing), whose
+     * table is nearly sorted, entries then put in order by an insertion
+     * pass bounded by the longest probe (Write-back Phase, Algorithm
+     * "SMASH WRITEBACK").  Also a candidate of smash_batch_autotune. */
+    SMASH_OPT_ROW_HASH = 6,
+    SMASH_OPT_COUNT = 7
 } smash_option;
 
 /* Counters of the last symbolic/numeric call (smash_get_stats). */
@@ -119,6 +147,7 @@ typedef struct {
     int64_t global_waves;       /* launches of global-mode row waves (symbolic + numeric) */
     int64_t global_pool;        /* slots of the global table pool used (the largest wave) */
     int64_t fused_entries;      /* entries of the rows the fused pass completed */
+    int64_t workspace_bytes;    /* workspace bytes the last symbolic call needed (also after CAPACITY) */
 } smash_stats;
 
 /* Allocation callback of smash_spgemm: return device memory of at least
@@ -141,38 +170,61 @@ const char *smash_status_string(smash_status s);
 smash_status smash_set_option(smash_ctx ctx, smash_option opt, int64_t value);
 smash_status smash_get_option(smash_ctx ctx, smash_option opt, int64_t *value);
 
+/* Workspace bytes that smash_spgemm_symbolic / _numeric / smash_spgemm /
+ * smash_spgemm_fused need for C = A * B under the context's current options
+ * (and installed predictor).  The plan arrays are sized from the shapes; the
+ * heavy-row tables (rows whose output bound exceeds the LDS row limit: the
+ * paper's rows that overflow a scratchpad window, Window Distribution Phase)
+ * from a device pass that counts them, after a memory-safety check of the
+ * operands (row pointers and column ranges; INVALID_CSR if it fails).
+ * Synchronises the stream.  A, B values are not read.
+ * Errors: INVALID_ARG, INVALID_CSR, HIP. */
+smash_status smash_workspace_size(smash_ctx ctx, smash_dtype dtype, const smash_csr *A, const smash_csr *B,
+                                  size_t *bytes, hipStream_t stream);
+
 /* Symbolic phase: the exact nnz of every row of C = A * B.
  * Writes C_row_ptr[0..A.rows] (device, int64, exclusive prefix of the row
  * counts) and *C_nnz (host).  A.val and B.val are not read.  The plan built
- * here (row bins, heavy-row column counts) is kept in ctx for the next
- * smash_spgemm_numeric call with the same A, B and C_row_ptr.
+ * here (row bins, heavy-row column counts, in ws) is kept for the next
+ * smash_spgemm_numeric call with the same A, B, C_row_ptr and ws, whose
+ * contents the caller must leave untouched in between.
  * Synchronizes the stream once (to read nnz(C) back).
  * Errors: INVALID_ARG (null pointer, A.cols != B.rows, negative sizes),
- * INVALID_CSR, OUT_OF_MEMORY, HIP. */
+ * INVALID_CSR, CAPACITY (ws too small: smash_get_stats().workspace_bytes
+ * holds the bytes needed), HIP, and errors of an earlier numeric call not
+ * yet reported. */
 smash_status smash_spgemm_symbolic(smash_ctx ctx, const smash_csr *A, const smash_csr *B,
-                                   int64_t *C_row_ptr, int64_t *C_nnz, hipStream_t stream);
+                                   int64_t *C_row_ptr, int64_t *C_nnz, void *ws, size_t ws_bytes,
+                                   hipStream_t stream);
 
 /* Numeric phase: the columns and values of C = A * B, written at
  * C_col_idx[C_row_ptr[i] .. C_row_ptr[i+1]) and the same range of C_val
  * (device; nnz(C) entries each; C_val of dtype).  Requires the plan of a
  * preceding smash_spgemm_symbolic call on ctx with the same A and B
- * descriptors and C_row_ptr pointer (else SMASH_ERR_NO_PLAN); the plan stays
- * valid, so numeric may be repeated after A.val or B.val change.
- * Synchronizes the stream once (to read the device error flags).
- * Errors: INVALID_ARG, NO_PLAN, CAPACITY (C_row_ptr inconsistent with the
- * product), OUT_OF_MEMORY, HIP. */
+ * descriptors, C_row_ptr pointer and ws (else SMASH_ERR_NO_PLAN); the plan
+ * stays valid, so numeric may be repeated after A.val or B.val change.
+ * Does not synchronise: a C_row_ptr found inconsistent with the product on
+ * the device is reported as CAPACITY by smash_sync() (or the next symbolic
+ * call).  Errors: INVALID_ARG, NO_PLAN, HIP. */
 smash_status smash_spgemm_numeric(smash_ctx ctx, smash_dtype dtype, const smash_csr *A, const smash_csr *B,
                                   const int64_t *C_row_ptr, int32_t *C_col_idx, void *C_val,
-                                  hipStream_t stream);
+                                  void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* Both phases: symbolic, then C_col_idx and C_val allocated through
  * alloc(nnz * 4, user) and alloc(nnz * value_bytes, user), then numeric.
- * C_row_ptr (device, A.rows + 1 int64) is the caller's.  On success
+ * C_row_ptr (device, A.rows + 1 int64) and ws are the caller's.  On success
  * *C_col_idx, *C_val (never NULL, also when nnz(C) = 0) and *C_nnz are set.
+ * One host synchronisation (the nnz readback).
  * Errors: those of the two phases, OUT_OF_MEMORY if alloc returns NULL. */
 smash_status smash_spgemm(smash_ctx ctx, smash_dtype dtype, const smash_csr *A, const smash_csr *B,
                           smash_alloc_fn alloc, void *user, int64_t *C_row_ptr,
-                          int32_t **C_col_idx, void **C_val, int64_t *C_nnz, hipStream_t stream);
+                          int32_t **C_col_idx, void **C_val, int64_t *C_nnz, void *ws, size_t ws_bytes,
+                          hipStream_t stream);
+
+/* Waits for `stream` and reports what the numeric calls enqueued on ctx
+ * since the last report found wrong on the device (CAPACITY: a C_row_ptr
+ * inconsistent with the product); clears it.  Errors: CAPACITY, HIP. */
+smash_status smash_sync(smash_ctx ctx, hipStream_t stream);
 
 /* Counters of the last symbolic (and numeric) call on ctx. */
 smash_status smash_get_stats(smash_ctx ctx, smash_stats *out);
@@ -240,7 +292,8 @@ smash_status smash_predictor_set(smash_ctx ctx, const float *params, const float
  * installed while SMASH_OPT_FUSED_SIZING is 0, and those of smash_spgemm. */
 smash_status smash_spgemm_fused(smash_ctx ctx, smash_dtype dtype, const smash_csr *A, const smash_csr *B,
                                 smash_alloc_fn alloc, void *user, int64_t *C_row_ptr,
-                                int32_t **C_col_idx, void **C_val, int64_t *C_nnz, hipStream_t stream);
+                                int32_t **C_col_idx, void **C_val, int64_t *C_nnz, void *ws, size_t ws_bytes,
+                                hipStream_t stream);
 
 /* Loads a predictor file: 8 bytes "SMASHMLP", int32 version (1), int32
  * SMASH_MLP_PARAMS, float delta, float mean_std[12], float params[...],
@@ -275,24 +328,31 @@ typedef struct smash_batch_plan_s *smash_batch_plan;
  *                (load factor at most 1/2 or 1/4);
  *  wide_groups   0: one wavefront per row up to 1024 slots, 4 for 2048;
  *                1: rows with 512 or more slots use 2, 4, 8 wavefronts;
- *  blocks_per_cu persistent workgroups per compute unit: 1 .. 32. */
+ *  blocks_per_cu persistent workgroups per compute unit: 1 .. 32;
+ *  row_hash      hash of the LDS row tables in the numeric pass: 0 or 1, as
+ *                SMASH_OPT_ROW_HASH. */
 typedef struct {
     int32_t lds_row_max;
     int32_t table_shift;
     int32_t wide_groups;
     int32_t blocks_per_cu;
+    int32_t row_hash;
 } smash_batch_config;
 
 /* Creates a plan for the `count` problems A[p] * B[p] (arrays of descriptors,
  * read during the call only; the matrices they point to must stay alive and
  * unmoved while the plan is used; values must be non-NULL, of `dtype`).  cfg
- * NULL takes the defaults {1024, 1, 0, 8}.  Runs the per-row analysis once
- * (synchronising `stream`) to size the output pool, which it allocates
- * through `alloc`: C_row_ptr (int64[total_rows + 1]) and col/val pools of
- * capacity sum over rows of min(products_i, cols_p), an exact upper bound on
- * the entries of any replay with the same structure.  The caller owns these
- * buffers (free them after the plan).  Library-owned workspace (per-row
- * arrays, global tables) is allocated here and freed by destroy.
+ * NULL takes the defaults {1024, 1, 0, 8, 0}.  Every device buffer of the plan
+ * comes from `alloc` (the library allocates no device memory): first the
+ * plan's workspace (per-row arrays, descriptors, header), then, after the
+ * per-row analysis (which synchronises `stream`) has sized it, the output
+ * pool: C_row_ptr (int64[total_rows + 1]) and col/val pools of capacity sum
+ * over rows of min(products_i, cols_p), an exact upper bound on the entries
+ * of any replay with the same structure; then the global hash tables of
+ * problems wider than 2^20 columns (keys, FP64 values, touched-slot lists;
+ * smash_batch_plan_configure may ask for larger ones).  `alloc` and `user`
+ * must stay valid while the plan lives.  The caller owns all of these
+ * buffers (free them after the plan).
  * With SMASH_OPT_VALIDATE set every operand is checked here (once; replays
  * do not validate).
  * Errors: INVALID_ARG (count < 0, a NULL pointer, A[p].cols != B[p].rows,
@@ -339,7 +399,7 @@ void smash_batch_plan_destroy(smash_batch_plan plan);
  * persistent grid), `reps` timed runs each after one warm-up, and
  * configures the plan with the fastest.  With cache_path non-NULL the
  * result is looked up first in, and afterwards appended to, a text file of
- * lines "key lds_row_max table_shift wide_groups blocks_per_cu ms", where
+ * lines "key lds_row_max table_shift wide_groups blocks_per_cu row_hash ms", where
  * key describes the batch (dtype, count, rows, nnz of A and B, products);
  * a hit configures the plan without timing.  *best (if non-NULL) receives
  * the chosen configuration and *best_ms (if non-NULL) its mean time (0 on

@@ -1,15 +1,24 @@
-// smash.hip -- host side of libsmash: contexts, planning, launches and the C
-// ABI declared in include/smash.h.
+// smash.hip -- host side of libsmash: contexts, workspace layout, planning,
+// launches and the C ABI declared in include/smash.h.
 //
 // Call structure (SMASH Kernels chapter: window distribution, hashing and
 // write-back phases, each closed by a barrier; here every phase is a set of
 // kernels ordered on the caller's stream):
 //   symbolic: validate -> analyze (products per row, bins) -> bin offsets ->
-//             scatter rows by bin -> [read bin counts back] -> per-bin LDS
-//             hash kernels + heavy-row kernel -> row-pointer scan -> numeric
-//             bins -> [read nnz(C) back]
+//             scatter rows by bin -> per-bin LDS hash kernels (persistent,
+//             bin sizes read on the device) + heavy-row kernels -> row-pointer
+//             scan -> numeric bins and heavy-row segments -> [read the plan
+//             header and nnz(C) back: the call's one host synchronisation]
 //   numeric:  per-bin LDS hash kernels (hash, compact, sort, write) +
-//             heavy-row kernels -> [read error flags back]
+//             heavy-row kernels, sized from the plan header; no
+//             synchronisation (device-detected errors are reported by
+//             smash_sync or the next symbolic call)
+// Every device buffer of a call is the caller's: inputs, outputs and one
+// workspace, laid out here (plan arrays of fixed size, then the heavy-row
+// tables sized from what is left).  A check that fails on the device (an
+// invalid matrix, a workspace too small) sets a flag that every later kernel
+// of the pipeline tests on entry, so nothing indexes through bad data, and
+// the host reports it at the synchronisation.
 #include "smash.h"
 #include "smash_kernels.hpp"
 #include "smash_mlp.hpp"
@@ -32,21 +41,24 @@ enum KernelId {
     K_VALIDATE, K_ANALYZE, K_BIN_COUNT, K_BIN_SCAN, K_SCATTER, K_SYM_ROWS, K_BSPLIT, K_SYM_HEAVY,
     K_SYM_GLOBAL, K_FILL, K_SCAN_REDUCE, K_SCAN_TOP, K_SCAN_APPLY, K_NUM_BINS, K_CHUNK_PREFIX,
     K_SEG_PLAN, K_SEG_SCAN, K_NUM_ROWS, K_NUM_SEG, K_NUM_DENSE, K_NUM_GLOBAL, K_FEATURES, K_MLP_PREDICT,
-    K_MLP_FWD, K_MLP_BWD, K_ADAM, K_FUSED_ROWS, K_FUSED_AUX, K_FUSED_COPY, K_COUNT
+    K_MLP_FWD, K_MLP_BWD, K_ADAM, K_FUSED_ROWS, K_FUSED_AUX, K_FUSED_COPY, K_WS_QUERY, K_COUNT
 };
 
 const char *const kKernelNames[K_COUNT] = {
     "validate", "analyze", "bin_count", "bin_scan", "scatter", "sym_rows", "bsplit", "sym_heavy",
     "sym_global", "fill", "scan_reduce", "scan_top", "scan_apply", "num_bins", "chunk_prefix",
     "seg_plan", "seg_scan", "num_rows", "num_seg", "num_dense", "num_global", "features", "mlp_predict",
-    "mlp_fwd", "mlp_bwd", "adam", "fused_rows", "fused_aux", "fused_copy"};
+    "mlp_fwd", "mlp_bwd", "adam", "fused_rows", "fused_aux", "fused_copy", "ws_query"};
 
-// Grow-only device buffer.
+// Grow-only device buffer of the context (predictor weights, training
+// buffers): not used by the multiply's calls.
 struct Arena {
     void *ptr = nullptr;
     size_t cap = 0;
 };
 
+// Carves 256-byte aligned arrays out of a buffer; with base == nullptr it
+// only measures (off is the bytes used so far).
 struct Carve {
     char *base;
     size_t off = 0;
@@ -54,7 +66,7 @@ struct Carve {
     T *take(size_t count)
     {
         off = (off + 255) & ~size_t(255);
-        T *p = (T *)(base + off);
+        T *p = base ? (T *)(base + off) : nullptr;
         off += count * sizeof(T);
         return p;
     }
@@ -67,14 +79,25 @@ size_t carve_size(std::initializer_list<size_t> parts)
     return s;
 }
 
+// Bytes of the workspace per heavy row (LDS mode: chunk counts, chunk
+// offsets and up to one segment per chunk) and per global hash slot (global
+// mode: key, FP64 value, touched-slot list entry).
+constexpr size_t kGlobalSlotBytes = sizeof(int) + sizeof(double) + sizeof(int);
+constexpr size_t kCarveSlack = 4 * 256;
+
 struct Plan {
     bool valid = false;
     smash_csr A{}, B{};
     const int64_t *crp = nullptr;
     int64_t m = 0, n = 0;
-    int heavy_mode = 0, lds_row_max = 0;
+    int heavy_mode = 0, lds_row_max = 0, row_hash = 0;
     DevHdr hdr{};
     int nchunks = 0, nblk = 0;
+    // workspace
+    const void *ws = nullptr;
+    size_t ws_bytes = 0, ws_fixed = 0;
+    long long hcap = 0;                   // heavy rows the workspace holds (LDS mode)
+    long long pool_cap = 0;               // global hash slots the workspace holds (global mode)
     long long *ub = nullptr;
     int *cap = nullptr, *nnzc = nullptr, *sym_perm = nullptr, *num_perm = nullptr;
     unsigned char *sym_bin = nullptr, *num_bin = nullptr;
@@ -82,9 +105,12 @@ struct Plan {
     unsigned long long *bprod = nullptr;
     long long *bw = nullptr;
     long long *bsum = nullptr, *gsz = nullptr, *goff_sym = nullptr, *goff_num = nullptr;
+    unsigned *valid_bm = nullptr;
     int *bsplit = nullptr, *wcnt = nullptr, *woff = nullptr, *seg_bcount = nullptr;
     Seg *segs = nullptr;
     int *queue = nullptr;                 // work-queue counter of the persistent dense kernel
+    int *gkeys = nullptr, *gtouch = nullptr;
+    double *gvals = nullptr;
     // global mode: waves of heavy rows (first row and table offset of each
     // wave, then the end) and the pool each pass needs
     std::vector<std::pair<int, long long>> sym_waves, num_waves;
@@ -96,6 +122,7 @@ struct Plan {
     int *maxb = nullptr, *cap_pred = nullptr, *fcap = nullptr, *f_perm = nullptr;
     unsigned char *fbin = nullptr, *fstatus = nullptr;
     long long *stage_off = nullptr;
+    long long stage_cap = 0;
     int *stage_col = nullptr;
     void *stage_val = nullptr;
 };
@@ -110,10 +137,12 @@ struct Pending {
 struct smash_ctx_s {
     int device = 0;
     std::string err;
-    int64_t opt[SMASH_OPT_COUNT] = {1, 1024, 0, 0, 0, 0};
+    int64_t opt[SMASH_OPT_COUNT] = {1, 1024, 0, 0, 0, 0, 0};
     DevHdr *h_hdr = nullptr;   // pinned host mirror
     DevHdr *d_hdr = nullptr;
-    Arena plan_mem, heavy_mem, gkeys, gvals, mlp_mem, pred_mem, fused_mem, stage_mem, valid_mem;
+    int *d_numerr = nullptr;   // flags of numeric calls (kept until smash_sync or a symbolic call reads them)
+    int *h_numerr = nullptr;   // pinned host mirror
+    Arena mlp_mem, pred_mem;
     bool has_predictor = false;
     float pred_delta = 0.f;
     Plan plan;
@@ -167,6 +196,7 @@ struct DeviceGuard {
     }
 };
 
+// Context-owned buffers (predictor weights and training only).
 smash_status ensure(smash_ctx c, Arena &a, size_t bytes, hipStream_t s)
 {
     bytes = std::max<size_t>(bytes, 256);
@@ -203,8 +233,6 @@ hipEvent_t take_event(smash_ctx c)
     return e;
 }
 
-// Launches `fn` (a lambda issuing one kernel) and, with timing on, brackets
-// it with events on the same stream.
 // Blocks of `kernel` (block size `threads`, `lds` bytes of dynamic LDS)
 // resident on the whole device at once: the grid of a persistent kernel.
 int resident_blocks(smash_ctx c, const void *kernel, int threads, size_t lds)
@@ -217,6 +245,8 @@ int resident_blocks(smash_ctx c, const void *kernel, int threads, size_t lds)
     return per_cu * c->cus;
 }
 
+// Launches `fn` (a lambda issuing one kernel) and, with timing on, brackets
+// it with events on the same stream.
 template <typename F>
 smash_status launch(smash_ctx c, int kid, hipStream_t s, F fn)
 {
@@ -236,9 +266,10 @@ smash_status launch(smash_ctx c, int kid, hipStream_t s, F fn)
     return SMASH_OK;
 }
 
-// Folds completed timing events into the per-kernel totals (after a sync).
+// Folds timing events into the per-kernel totals (waits for the last one).
 void collect_times(smash_ctx c)
 {
+    if (!c->pending.empty()) (void)hipEventSynchronize(c->pending.back().b);
     for (auto &p : c->pending) {
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
@@ -274,6 +305,80 @@ unsigned blocks_for(long long items, int per_block)
     return (unsigned)((items + per_block - 1) / per_block);
 }
 
+int *perr(smash_ctx c) { return &c->d_hdr->error; }
+
+// ---------------------------------------------------------- workspace layout
+
+// Carves the fixed part of a product's workspace (per-row plan arrays,
+// binning scratch, validation bitmap, the fused pass's per-row arrays, the
+// split table of heavy rows) and then, from what is left of ws_bytes, the
+// heavy-row tables: p.hcap heavy rows in LDS mode, p.pool_cap global slots
+// in global mode.  With base == nullptr it only measures (p.ws_fixed).
+void carve_workspace(smash_ctx c, Plan &p, char *base, size_t ws_bytes)
+{
+    const long long m = p.m;
+    const bool global = p.heavy_mode == 1;
+    Carve cv{base};
+    p.ub = cv.take<long long>(m);
+    p.cap = cv.take<int>(m);
+    p.nnzc = cv.take<int>(m);
+    p.sym_perm = cv.take<int>(m);
+    p.num_perm = cv.take<int>(m);
+    p.sym_bin = cv.take<unsigned char>(m);
+    p.num_bin = cv.take<unsigned char>(m);
+    p.nblk = (int)blocks_for(std::max<long long>(m, 1), kBinBlockRows);
+    const int nsb = (int)blocks_for(std::max<long long>(m, 1), kScanItems);
+    p.bcount = cv.take<int>((size_t)p.nblk * kNumBins);
+    p.bprod = cv.take<unsigned long long>(p.nblk);
+    p.bw = cv.take<long long>((size_t)p.nblk * kNumBins);
+    p.bsum = cv.take<long long>((size_t)nsb + 1);
+    p.queue = cv.take<int>(64);
+    if (c->opt[SMASH_OPT_VALIDATE])
+        p.valid_bm = cv.take<unsigned>((size_t)(std::max(p.A.nnz, p.B.nnz) + 31) / 32 + 1);
+    if (p.fused) {
+        p.feats = cv.take<float>((size_t)m * kFeat);
+        p.maxb = cv.take<int>(m);
+        p.cap_pred = cv.take<int>(m);
+        p.fcap = cv.take<int>(m);
+        p.f_perm = cv.take<int>(m);
+        p.fbin = cv.take<unsigned char>(m);
+        p.fstatus = cv.take<unsigned char>(m);
+        p.stage_off = cv.take<long long>((size_t)m + 1);
+    }
+    if (global) {
+        p.gsz = cv.take<long long>(m);
+        p.goff_sym = cv.take<long long>((size_t)m + 1);
+        p.goff_num = cv.take<long long>((size_t)m + 1);
+    } else {
+        p.bsplit = cv.take<int>((size_t)p.B.rows * (p.nchunks + 1));
+        p.seg_bcount = cv.take<int>((size_t)kSegBins * p.nchunks);
+    }
+    p.ws_fixed = cv.off + kCarveSlack;
+    const size_t rest = ws_bytes > p.ws_fixed ? ws_bytes - p.ws_fixed : 0;
+    p.hcap = 0;
+    p.pool_cap = 0;
+    if (global) {
+        p.pool_cap = (long long)(rest / kGlobalSlotBytes);
+        p.gkeys = cv.take<int>(p.pool_cap);
+        p.gvals = cv.take<double>(p.pool_cap);
+        p.gtouch = cv.take<int>(p.pool_cap);
+    } else {
+        const size_t per_row = (size_t)p.nchunks * (2 * sizeof(int) + sizeof(Seg));
+        p.hcap = std::min<long long>((long long)(rest / per_row), m);
+        const size_t cells = (size_t)p.hcap * p.nchunks;
+        p.wcnt = cv.take<int>(cells);
+        p.woff = cv.take<int>(cells);
+        p.segs = cv.take<Seg>(cells);
+    }
+}
+
+// Workspace bytes for `heavy` heavy rows (LDS mode) or `slots` global slots.
+size_t workspace_need(const Plan &p, long long heavy, long long slots)
+{
+    if (p.heavy_mode == 1) return p.ws_fixed + (size_t)slots * kGlobalSlotBytes;
+    return p.ws_fixed + (size_t)heavy * p.nchunks * (2 * sizeof(int) + sizeof(Seg));
+}
+
 // ------------------------------------------------------------- LDS bins
 
 template <int LOGT>
@@ -285,13 +390,24 @@ struct BinShape {
     static constexpr int THREADS = kWave * WPR * RPW;
 };
 
+// Persistent grid of a light-row kernel: the resident blocks, at most enough
+// for every row of A.
+template <typename K>
+unsigned persistent_grid(smash_ctx c, K kernel, int threads, int rpw, long long m)
+{
+    const int res = resident_blocks(c, (const void *)kernel, threads, 0);
+    return (unsigned)std::max<long long>(1, std::min<long long>(res, blocks_for(m, rpw)));
+}
+
 template <int LOGT>
-smash_status launch_sym_bin(smash_ctx c, hipStream_t s, const Plan &p, int cnt, const int *rows)
+smash_status launch_sym_bin(smash_ctx c, hipStream_t s, const Plan &p)
 {
     using S = BinShape<LOGT>;
+    auto kern = k_sym_rows<LOGT, S::WPR, S::RPW>;
+    const unsigned grid = persistent_grid(c, kern, S::THREADS, S::RPW, p.m);
     return launch(c, K_SYM_ROWS, s, [&] {
-        k_sym_rows<LOGT, S::WPR, S::RPW><<<blocks_for(cnt, S::RPW), S::THREADS, 0, s>>>(
-            p.A.row_ptr, p.A.col_idx, p.B.row_ptr, p.B.col_idx, rows, cnt, p.nnzc, &c->d_hdr->error);
+        kern<<<grid, S::THREADS, 0, s>>>(p.A.row_ptr, p.A.col_idx, p.B.row_ptr, p.B.col_idx, p.sym_perm,
+                                         &c->d_hdr->sym, LOGT - kMinLogT, p.nnzc, perr(c));
     });
 }
 
@@ -301,20 +417,26 @@ smash_status launch_num_bin(smash_ctx c, hipStream_t s, const Plan &p, int cnt, 
 {
     using S = BinShape<LOGT>;
     return launch(c, K_NUM_ROWS, s, [&] {
-        k_num_rows<V, LOGT, S::WPR, S::RPW><<<blocks_for(cnt, S::RPW), S::THREADS, 0, s>>>(
-            p.A.row_ptr, p.A.col_idx, Aval, p.B.row_ptr, p.B.col_idx, Bval, rows, cnt, (const long long *)crp, ccol,
-            cval, (int)p.n, &c->d_hdr->error);
+        if (p.row_hash)
+            k_num_rows<V, LOGT, S::WPR, S::RPW, 1><<<blocks_for(cnt, S::RPW), S::THREADS, 0, s>>>(
+                p.A.row_ptr, p.A.col_idx, Aval, p.B.row_ptr, p.B.col_idx, Bval, rows, cnt, (const long long *)crp,
+                ccol, cval, (int)p.n, c->d_numerr);
+        else
+            k_num_rows<V, LOGT, S::WPR, S::RPW, 0><<<blocks_for(cnt, S::RPW), S::THREADS, 0, s>>>(
+                p.A.row_ptr, p.A.col_idx, Aval, p.B.row_ptr, p.B.col_idx, Bval, rows, cnt, (const long long *)crp,
+                ccol, cval, (int)p.n, c->d_numerr);
     });
 }
 
+// Symbolic light rows: every bin is launched (its size is on the device).
 smash_status run_sym_bins(smash_ctx c, hipStream_t s, const Plan &p)
 {
-    const BinHdr &b = p.hdr.sym;
-    const int *perm = p.sym_perm;
-#define SYM_BIN(LT)                                                                               \
-    if (b.count[LT - kMinLogT]) TRY(launch_sym_bin<LT>(c, s, p, b.count[LT - kMinLogT], perm + b.offset[LT - kMinLogT]));
-    SYM_BIN(6) SYM_BIN(7) SYM_BIN(8) SYM_BIN(9) SYM_BIN(10) SYM_BIN(11)
-#undef SYM_BIN
+    TRY(launch_sym_bin<6>(c, s, p));
+    TRY(launch_sym_bin<7>(c, s, p));
+    TRY(launch_sym_bin<8>(c, s, p));
+    TRY(launch_sym_bin<9>(c, s, p));
+    TRY(launch_sym_bin<10>(c, s, p));
+    TRY(launch_sym_bin<11>(c, s, p));
     return SMASH_OK;
 }
 
@@ -335,20 +457,21 @@ smash_status run_num_bins(smash_ctx c, hipStream_t s, const Plan &p, const V *Av
 
 // Binning of the rows by `bin_of` into `perm` (block histograms, one scan
 // block, scatter), with the global-hash table sizes of heavy rows when
-// gsize_of is given.
+// gsize_of is given; heavy_cap >= 0 limits the heavy rows (workspace).
 smash_status bin_rows(smash_ctx c, hipStream_t s, const Plan &p, const unsigned char *bin_of, const long long *ub,
-                      const int *wt, BinHdr *dh, int *perm, const int *gsize_of)
+                      const int *wt, BinHdr *dh, int *perm, const int *gsize_of, long long heavy_cap)
 {
     const int m = (int)p.m;
     TRY(launch(c, K_BIN_COUNT, s, [&] {
-        k_bin_count<<<p.nblk, 256, 0, s>>>(m, bin_of, ub, wt, p.bcount, ub ? p.bprod : nullptr, wt ? p.bw : nullptr);
+        k_bin_count<<<p.nblk, 256, 0, s>>>(m, bin_of, ub, wt, p.bcount, ub ? p.bprod : nullptr, wt ? p.bw : nullptr,
+                                           perr(c));
     }));
     TRY(launch(c, K_BIN_SCAN, s, [&] {
         k_bin_scan<<<1, 256, 0, s>>>(p.nblk, p.bcount, ub ? p.bprod : nullptr, wt ? p.bw : nullptr, dh,
-                                     ub ? &c->d_hdr->products : nullptr);
+                                     ub ? &c->d_hdr->products : nullptr, perr(c), heavy_cap);
     }));
     TRY(launch(c, K_SCATTER, s, [&] {
-        k_scatter<<<p.nblk, 256, 0, s>>>(m, bin_of, p.bcount, dh, perm, gsize_of, p.gsz);
+        k_scatter<<<p.nblk, 256, 0, s>>>(m, bin_of, p.bcount, dh, perm, gsize_of, p.gsz, perr(c));
     }));
     return SMASH_OK;
 }
@@ -376,7 +499,7 @@ smash_status launch_seg_bin(smash_ctx c, hipStream_t s, const Plan &p, int bin, 
     return launch(c, K_NUM_SEG, s, [&] {
         k_num_seg<V, LOGT, THREADS><<<cnt, THREADS, 0, s>>>(p.A.row_ptr, p.A.col_idx, Aval, p.B.col_idx, Bval, p.bsplit, (long long)(p.nchunks + 1),
                                                      hrows, segs, p.nchunks, p.woff, (const long long *)crp, ccol,
-                                                     cval, &c->d_hdr->error);
+                                                     cval, c->d_numerr);
     });
 }
 
@@ -406,15 +529,14 @@ smash_status numeric_impl(smash_ctx c, hipStream_t s, const Plan &p, const V *Av
                 k_num_dense<V><<<grid, kDenseThreads, lds, s>>>(p.A.row_ptr, p.A.col_idx, Aval, p.B.col_idx, Bval,
                                                                p.bsplit, (long long)(p.nchunks + 1), hrows, segs, p.nchunks,
                                                                p.woff, (const long long *)crp, ccol, cval,
-                                                               &c->d_hdr->error, nd, p.queue);
+                                                               c->d_numerr, nd, p.queue);
             }));
         }
         return SMASH_OK;
     }
-    // global-memory hash tables, in the waves planned by the symbolic phase
-    // (each row clears its own table, so the pool is reused as it is)
-    TRY(ensure(c, c->gkeys, (size_t)p.num_pool * sizeof(int), s));
-    TRY(ensure(c, c->gvals, (size_t)p.num_pool * sizeof(V), s));
+    // global-memory hash tables in the workspace's pool, in the waves planned
+    // by the symbolic phase (each row clears its own table, so the pool is
+    // reused as it is)
     const size_t lds = (size_t)kGlobalRankBits / 8;
     (void)hipFuncSetAttribute((const void *)k_num_global<V>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     const int *rows = p.num_perm + p.hdr.num.offset[kBinHeavy];
@@ -423,112 +545,46 @@ smash_status numeric_impl(smash_ctx c, hipStream_t s, const Plan &p, const V *Av
         const long long base = p.num_waves[w].second;
         TRY(launch(c, K_NUM_GLOBAL, s, [&] {
             k_num_global<V><<<nh, kGlobalThreads, lds, s>>>(p.A.row_ptr, p.A.col_idx, Aval, p.B.row_ptr, p.B.col_idx,
-                                                            Bval, rows + h0, (int)p.n, p.goff_num + h0, base,
-                                                            (int *)c->gkeys.ptr, (V *)c->gvals.ptr,
-                                                            (const long long *)crp, ccol, cval, &c->d_hdr->error);
+                                                            Bval, rows + h0, (int)p.n, p.goff_num + h0, base, p.gkeys,
+                                                            p.gvals, p.gtouch, (const long long *)crp, ccol, cval,
+                                                            c->d_numerr);
         }));
     }
     return SMASH_OK;
 }
 
 template <typename V, int LOGT>
-smash_status launch_fused_bin(smash_ctx c, hipStream_t s, const Plan &p, int cnt, const int *rows)
+smash_status launch_fused_bin(smash_ctx c, hipStream_t s, const Plan &p)
 {
     using S = BinShape<LOGT>;
+    auto kern = k_fused_rows<V, LOGT, S::WPR, S::RPW>;
+    const unsigned grid = persistent_grid(c, kern, S::THREADS, S::RPW, p.m);
     return launch(c, K_FUSED_ROWS, s, [&] {
-        k_fused_rows<V, LOGT, S::WPR, S::RPW><<<blocks_for(cnt, S::RPW), S::THREADS, 0, s>>>(
-            p.A.row_ptr, p.A.col_idx, (const V *)p.A.val, p.B.row_ptr, p.B.col_idx, (const V *)p.B.val, rows, cnt,
-            p.fcap, p.stage_off, p.stage_col, (V *)p.stage_val, p.nnzc, p.fstatus, (int)p.n);
+        kern<<<grid, S::THREADS, 0, s>>>(p.A.row_ptr, p.A.col_idx, (const V *)p.A.val, p.B.row_ptr, p.B.col_idx,
+                                         (const V *)p.B.val, p.f_perm, &c->d_hdr->fz, LOGT - kMinLogT, p.fcap,
+                                         p.stage_off, p.stage_cap, p.stage_col, (V *)p.stage_val, p.nnzc, p.fstatus,
+                                         (int)p.n, perr(c));
     });
 }
 
 template <typename V>
-smash_status run_fused_bins(smash_ctx c, hipStream_t s, const Plan &p, const BinHdr &b)
+smash_status run_fused_bins(smash_ctx c, hipStream_t s, const Plan &p)
 {
-#define FUSED_BIN(LT)                                                                                  \
-    if (b.count[LT - kMinLogT])                                                                        \
-        TRY(launch_fused_bin<V, LT>(c, s, p, b.count[LT - kMinLogT], p.f_perm + b.offset[LT - kMinLogT]));
-    FUSED_BIN(6) FUSED_BIN(7) FUSED_BIN(8) FUSED_BIN(9) FUSED_BIN(10) FUSED_BIN(11)
-#undef FUSED_BIN
+    TRY((launch_fused_bin<V, 6>(c, s, p)));
+    TRY((launch_fused_bin<V, 7>(c, s, p)));
+    TRY((launch_fused_bin<V, 8>(c, s, p)));
+    TRY((launch_fused_bin<V, 9>(c, s, p)));
+    TRY((launch_fused_bin<V, 10>(c, s, p)));
+    TRY((launch_fused_bin<V, 11>(c, s, p)));
     return SMASH_OK;
 }
 
-smash_status bin_rows(smash_ctx c, hipStream_t s, const Plan &p, const unsigned char *bin_of, const long long *ub,
-                      const int *wt, BinHdr *dh, int *perm, const int *gsize_of);
-template <typename TIn>
-smash_status scan_counts(smash_ctx c, hipStream_t s, long long n, const TIn *cnt, long long *bsum, long long *out,
-                         long long *total);
-smash_status read_hdr(smash_ctx c, hipStream_t s);
-
-// The fused stage of smash_spgemm_fused: features, predicted capacities,
-// fused bins, staging offsets, the fused kernels, and removal of the rows
-// they completed from the two-phase plan.
-smash_status fused_alloc(smash_ctx c, hipStream_t s, Plan &p)
-{
-    const int m = (int)p.m;
-    const size_t need = carve_size({(size_t)m * kFeat * 4, (size_t)m * 4, (size_t)m * 4, (size_t)m * 4,
-                                    (size_t)m * 4, (size_t)m, (size_t)m, (size_t)(m + 1) * 8});
-    TRY(ensure(c, c->fused_mem, need, s));
-    Carve cv{(char *)c->fused_mem.ptr};
-    p.feats = cv.take<float>((size_t)m * kFeat);
-    p.maxb = cv.take<int>(m);
-    p.cap_pred = cv.take<int>(m);
-    p.fcap = cv.take<int>(m);
-    p.f_perm = cv.take<int>(m);
-    p.fbin = cv.take<unsigned char>(m);
-    p.fstatus = cv.take<unsigned char>(m);
-    p.stage_off = cv.take<long long>(m + 1);
-    return SMASH_OK;
-}
-
-smash_status fused_stage(smash_ctx c, hipStream_t s, Plan &p)
-{
-    const int m = (int)p.m;
-    const size_t vb = p.fused_dtype == SMASH_F32 ? 4 : 8;
-    const float *prm = (const float *)c->pred_mem.ptr;
-    const bool learned = c->opt[SMASH_OPT_FUSED_SIZING] == 0;
-    if (learned) {      // the features came with the analysis
-        TRY(launch(c, K_MLP_PREDICT, s, [&] {
-            k_mlp_predict<<<blocks_for(m, 256), 256, 0, s>>>(m, (int)p.n, p.feats, prm, prm + kParams,
-                                                             c->pred_delta, p.ub, p.maxb, nullptr, p.cap_pred);
-        }));
-    }
-    TRY(launch(c, K_FUSED_AUX, s, [&] {
-        k_fused_bins<<<blocks_for(m, 256), 256, 0, s>>>(m, p.ub, learned ? p.cap_pred : p.cap, p.lds_row_max,
-                                                        p.fbin, p.fcap);
-    }));
-    TRY(bin_rows(c, s, p, p.fbin, nullptr, nullptr, &c->d_hdr->fz, p.f_perm, nullptr));
-    TRY(scan_counts<int>(c, s, m, p.fcap, p.bsum, p.stage_off, &c->d_hdr->stage_total));
-    TRY(read_hdr(c, s));
-    const BinHdr fz = c->h_hdr->fz;
-    const long long total = c->h_hdr->stage_total;
-    TRY(ensure(c, c->stage_mem, carve_size({(size_t)total * 4, (size_t)total * vb}), s));
-    Carve sv{(char *)c->stage_mem.ptr};
-    p.stage_col = sv.take<int>(total);
-    p.stage_val = sv.take<char>(total * vb);
-    if (p.fused_dtype == SMASH_F32) TRY(run_fused_bins<float>(c, s, p, fz));
-    else TRY(run_fused_bins<double>(c, s, p, fz));
-    TRY(launch(c, K_FUSED_AUX, s, [&] {
-        k_fused_mark<<<blocks_for(m, 256), 256, 0, s>>>(m, p.fbin, p.fstatus, p.nnzc, p.sym_bin, &c->d_hdr->fused_ok,
-                                                        &c->d_hdr->fused_entries);
-    }));
-    return SMASH_OK;
-}
-
-template <typename V>
-smash_status fused_copy(smash_ctx c, hipStream_t s, const Plan &p, const int64_t *crp, int32_t *ccol, V *cval)
-{
-    const int nf = p.hdr.fz.offset[kLdsBins];
-    if (!p.fused || nf == 0) return SMASH_OK;
-    return launch(c, K_FUSED_COPY, s, [&] {
-        k_fused_copy<V><<<blocks_for(nf, 4), 256, 0, s>>>(p.f_perm, nf, p.fstatus, p.stage_off, p.stage_col,
-                                                         (const V *)p.stage_val, (const long long *)crp, ccol, cval);
-    });
-}
-
+// Copies the device header (and the numeric error word) to the host and
+// waits: the one synchronisation of a symbolic call.
 smash_status read_hdr(smash_ctx c, hipStream_t s)
 {
     HIP_TRY(c, hipMemcpyAsync(c->h_hdr, c->d_hdr, sizeof(DevHdr), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipMemcpyAsync(c->h_numerr, c->d_numerr, sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipStreamSynchronize(s));
     collect_times(c);
     return SMASH_OK;
@@ -543,6 +599,69 @@ smash_status device_errors(smash_ctx c, int e)
     if (e & (kErrProbe | kErrCount))
         return fail(c, SMASH_ERR_CAPACITY, "C_row_ptr does not match the product (device flags 0x%x)", e);
     return SMASH_OK;
+}
+
+// Errors recorded by earlier numeric calls (read at a synchronisation):
+// reported once, then cleared.
+smash_status numeric_errors(smash_ctx c, hipStream_t s)
+{
+    const int e = *c->h_numerr;
+    if (!e) return SMASH_OK;
+    *c->h_numerr = 0;
+    HIP_TRY(c, hipMemsetAsync(c->d_numerr, 0, sizeof(int), s));
+    const smash_status st = device_errors(c, e);
+    c->err = std::string(smash_status_string(st)) + ": a numeric call before this one failed on the device: " +
+             c->err.substr(c->err.find(": ") + 2);
+    return st;
+}
+
+// The fused stage of smash_spgemm_fused: predicted capacities, fused bins,
+// staging offsets (a synchronisation reads their total, and the staging
+// area comes from the caller's allocation callback), the fused kernels, and
+// removal of the rows they completed from the two-phase plan.
+smash_status fused_stage(smash_ctx c, hipStream_t s, Plan &p, smash_alloc_fn alloc, void *user)
+{
+    const int m = (int)p.m;
+    const size_t vb = p.fused_dtype == SMASH_F32 ? 4 : 8;
+    const float *prm = (const float *)c->pred_mem.ptr;
+    const bool learned = c->opt[SMASH_OPT_FUSED_SIZING] == 0;
+    if (learned) {      // the features came with the analysis
+        TRY(launch(c, K_MLP_PREDICT, s, [&] {
+            k_mlp_predict<<<blocks_for(m, 256), 256, 0, s>>>(m, (int)p.n, p.feats, prm, prm + kParams,
+                                                             c->pred_delta, p.ub, p.maxb, nullptr, p.cap_pred);
+        }));
+    }
+    TRY(launch(c, K_FUSED_AUX, s, [&] {
+        k_fused_bins<<<blocks_for(m, 256), 256, 0, s>>>(m, p.ub, learned ? p.cap_pred : p.cap, p.lds_row_max,
+                                                        p.fbin, p.fcap, perr(c));
+    }));
+    TRY(bin_rows(c, s, p, p.fbin, nullptr, nullptr, &c->d_hdr->fz, p.f_perm, nullptr, -1));
+    TRY(scan_counts<int>(c, s, m, p.fcap, p.bsum, p.stage_off, &c->d_hdr->stage_total));
+    TRY(read_hdr(c, s));
+    TRY(device_errors(c, c->h_hdr->error));
+    const long long total = c->h_hdr->stage_total;
+    p.stage_cap = total;
+    p.stage_col = (int *)alloc(std::max<size_t>((size_t)total * 4, 256), user);
+    p.stage_val = alloc(std::max<size_t>((size_t)total * vb, 256), user);
+    if (!p.stage_col || !p.stage_val) return fail(c, SMASH_ERR_OUT_OF_MEMORY, "allocation callback returned NULL");
+    if (p.fused_dtype == SMASH_F32) TRY(run_fused_bins<float>(c, s, p));
+    else TRY(run_fused_bins<double>(c, s, p));
+    TRY(launch(c, K_FUSED_AUX, s, [&] {
+        k_fused_mark<<<blocks_for(m, 256), 256, 0, s>>>(m, p.fbin, p.fstatus, p.nnzc, p.sym_bin, &c->d_hdr->fused_ok,
+                                                        &c->d_hdr->fused_entries, perr(c));
+    }));
+    return SMASH_OK;
+}
+
+template <typename V>
+smash_status fused_copy(smash_ctx c, hipStream_t s, const Plan &p, const int64_t *crp, int32_t *ccol, V *cval)
+{
+    const int nf = p.hdr.fz.offset[kLdsBins];
+    if (!p.fused || nf == 0) return SMASH_OK;
+    return launch(c, K_FUSED_COPY, s, [&] {
+        k_fused_copy<V><<<blocks_for(nf, 4), 256, 0, s>>>(p.f_perm, nf, p.fstatus, p.stage_off, p.stage_col,
+                                                         (const V *)p.stage_val, (const long long *)crp, ccol, cval);
+    });
 }
 
 }  // namespace
@@ -580,12 +699,22 @@ smash_status smash_create(smash_ctx *out, int device)
         delete c;
         return SMASH_ERR_HIP;
     }
-    if (hipMalloc((void **)&c->d_hdr, sizeof(DevHdr)) != hipSuccess) {
+    if (hipHostMalloc((void **)&c->h_numerr, sizeof(int), hipHostMallocDefault) != hipSuccess) {
         (void)hipHostFree(c->h_hdr);
+        delete c;
+        return SMASH_ERR_HIP;
+    }
+    if (hipMalloc((void **)&c->d_hdr, sizeof(DevHdr)) != hipSuccess ||
+        hipMalloc((void **)&c->d_numerr, sizeof(int)) != hipSuccess ||
+        hipMemset(c->d_numerr, 0, sizeof(int)) != hipSuccess) {
+        if (c->d_hdr) (void)hipFree(c->d_hdr);
+        (void)hipHostFree(c->h_hdr);
+        (void)hipHostFree(c->h_numerr);
         delete c;
         return SMASH_ERR_OUT_OF_MEMORY;
     }
     memset(c->h_hdr, 0, sizeof(DevHdr));
+    *c->h_numerr = 0;
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
         c->cus = cus;
@@ -597,11 +726,12 @@ void smash_destroy(smash_ctx c)
 {
     if (!c) return;
     DeviceGuard g(c->device);
-    for (Arena *a : {&c->plan_mem, &c->heavy_mem, &c->gkeys, &c->gvals, &c->mlp_mem, &c->pred_mem, &c->fused_mem,
-                     &c->stage_mem, &c->valid_mem})
+    for (Arena *a : {&c->mlp_mem, &c->pred_mem})
         if (a->ptr) (void)hipFree(a->ptr);
     if (c->d_hdr) (void)hipFree(c->d_hdr);
+    if (c->d_numerr) (void)hipFree(c->d_numerr);
     if (c->h_hdr) (void)hipHostFree(c->h_hdr);
+    if (c->h_numerr) (void)hipHostFree(c->h_numerr);
     for (auto &p : c->pending) {
         (void)hipEventDestroy(p.a);
         (void)hipEventDestroy(p.b);
@@ -630,6 +760,9 @@ smash_status smash_set_option(smash_ctx c, smash_option opt, int64_t v)
     case SMASH_OPT_GLOBAL_POOL:
         if (v < 0) return fail(c, SMASH_ERR_INVALID_ARG, "global pool limit must be >= 0 (0 = no limit)");
         break;
+    case SMASH_OPT_ROW_HASH:
+        if (v != 0 && v != 1) return fail(c, SMASH_ERR_INVALID_ARG, "row hash is 0 (multiplicative) or 1 (order-preserving)");
+        break;
     default: return fail(c, SMASH_ERR_INVALID_ARG, "unknown option %d", (int)opt);
     }
     c->opt[opt] = v;
@@ -644,20 +777,22 @@ smash_status smash_get_option(smash_ctx c, smash_option opt, int64_t *v)
     return SMASH_OK;
 }
 
+}  // extern "C"
+
 namespace {
 
 // Heavy rows [0, H) of the global mode in waves of consecutive rows whose
 // tables fit `limit` slots (goff: device, the H + 1 table offsets, an
-// exclusive prefix).  One wave without a limit or when all tables fit;
-// otherwise the offsets are read back and split greedily, a row whose table
-// alone exceeds the limit forming a wave of its own.  bounds receives the
-// first row and table offset of every wave followed by (H, goff[H]); pool
-// the slots of the largest wave.
+// exclusive prefix).  One wave when all tables fit; otherwise the offsets
+// are read back and split greedily, a row whose table alone exceeds the
+// limit forming a wave of its own.  bounds receives the first row and table
+// offset of every wave followed by (H, goff[H]); pool the slots of the
+// largest wave.
 smash_status plan_global_waves(smash_ctx c, hipStream_t s, const long long *goff, int H, long long total,
-                               int64_t limit, std::vector<std::pair<int, long long>> &bounds, long long &pool)
+                               long long limit, std::vector<std::pair<int, long long>> &bounds, long long &pool)
 {
     bounds.clear();
-    if (limit <= 0 || total <= limit) {
+    if (total <= limit) {
         bounds.push_back({0, 0});
         bounds.push_back({H, total});
         pool = total;
@@ -679,16 +814,15 @@ smash_status plan_global_waves(smash_ctx c, hipStream_t s, const long long *goff
 }
 
 // Queues the CSR checks of one matrix (k_validate_rows, k_validate_cols)
-// on s; a violation sets `flag` in *err.  The row-start bitmap lives in the
-// context's validation arena (the stream orders successive checks).
-smash_status validate_csr(smash_ctx c, hipStream_t s, const smash_csr &M, int flag, int *err)
+// on s; a violation sets `flag` in *err.  With `starts` (a bitmap of
+// nnz / 32 + 1 words of the workspace) every precondition is checked;
+// without it, only what memory safety needs (row pointers, column ranges).
+smash_status validate_csr(smash_ctx c, hipStream_t s, const smash_csr &M, int flag, int *err, unsigned *starts)
 {
     if (M.rows == 0 && M.nnz == 0) return SMASH_OK;
     const long long words = (M.nnz + 31) / 32 + 1;
-    TRY(ensure(c, c->valid_mem, (size_t)words * sizeof(unsigned), s));
-    unsigned *starts = (unsigned *)c->valid_mem.ptr;
     TRY(launch(c, K_VALIDATE, s, [&] {
-        k_fill_i32<<<blocks_for(words, 256), 256, 0, s>>>(words, (int *)starts, 0);
+        if (starts) k_fill_i32<<<blocks_for(words, 256), 256, 0, s>>>(words, (int *)starts, 0);
         k_validate_rows<<<blocks_for(std::max<int64_t>(M.rows, 1), 256), 256, 0, s>>>((int)M.rows, M.nnz, M.row_ptr,
                                                                                       starts, flag, err);
         if (M.nnz > 0)
@@ -697,146 +831,167 @@ smash_status validate_csr(smash_ctx c, hipStream_t s, const smash_csr &M, int fl
     return SMASH_OK;
 }
 
+smash_status check_pair(smash_ctx c, const smash_csr *A, const smash_csr *B, bool need_val)
+{
+    TRY(check_csr(c, A, "A", need_val));
+    TRY(check_csr(c, B, "B", need_val));
+    if (A->cols != B->rows)
+        return fail(c, SMASH_ERR_INVALID_ARG, "A.cols (%lld) != B.rows (%lld)", (long long)A->cols, (long long)B->rows);
+    return SMASH_OK;
+}
+
+void plan_init(smash_ctx c, Plan &p, const smash_csr *A, const smash_csr *B, bool fuse, int fused_dtype)
+{
+    p = Plan();
+    p.A = *A;
+    p.B = *B;
+    p.m = A->rows;
+    p.n = B->cols;
+    p.heavy_mode = (int)c->opt[SMASH_OPT_HEAVY_MODE];
+    p.lds_row_max = (int)c->opt[SMASH_OPT_LDS_ROW_MAX];
+    p.row_hash = (int)c->opt[SMASH_OPT_ROW_HASH];
+    p.nchunks = (int)std::max<int64_t>(1, (p.n + kChunkCols - 1) / kChunkCols);
+    p.fused = fuse;
+    p.fused_dtype = fuse ? fused_dtype : 0;
+}
+
+// Workspace bytes of C = A * B for the context's options: the fixed part
+// from the sizes, the heavy-row part from a device pass that counts the
+// heavy rows and the global table slots (checked inputs only: row pointers
+// and column ranges first).  Synchronises the stream.
+smash_status workspace_query(smash_ctx c, const smash_csr *A, const smash_csr *B, bool fuse, size_t *bytes,
+                             hipStream_t s)
+{
+    Plan q;
+    plan_init(c, q, A, B, fuse, 0);
+    carve_workspace(c, q, nullptr, 0);
+    if (q.m == 0) {
+        *bytes = q.ws_fixed;
+        return SMASH_OK;
+    }
+    HIP_TRY(c, hipMemsetAsync(c->d_hdr, 0, sizeof(DevHdr), s));
+    TRY(validate_csr(c, s, *A, kErrCsrA, perr(c), nullptr));
+    TRY(validate_csr(c, s, *B, kErrCsrB, perr(c), nullptr));
+    TRY(launch(c, K_WS_QUERY, s, [&] {
+        k_ws_query<<<blocks_for(q.m, 4), 256, 0, s>>>((int)q.m, (int)q.n, q.lds_row_max, A->row_ptr, A->col_idx,
+                                                      B->row_ptr, c->d_hdr);
+    }));
+    TRY(read_hdr(c, s));
+    TRY(device_errors(c, c->h_hdr->error));
+    const long long H = c->h_hdr->q_heavy;
+    long long slots = (long long)c->h_hdr->q_gsum;
+    const long long lim = c->opt[SMASH_OPT_GLOBAL_POOL];
+    if (lim > 0) slots = std::min<long long>(slots, std::max<long long>(lim, (long long)c->h_hdr->q_gmax));
+    *bytes = workspace_need(q, H, slots);
+    return SMASH_OK;
+}
+
 // The symbolic pipeline; with fused_dtype >= 0 it first runs the fused stage
 // for the rows the predictor sizes into LDS (smash_spgemm_fused).
 smash_status symbolic_impl(smash_ctx c, const smash_csr *A, const smash_csr *B, int64_t *C_row_ptr, int64_t *C_nnz,
-                           hipStream_t s, int fused_dtype)
+                           void *ws, size_t ws_bytes, hipStream_t s, int fused_dtype, smash_alloc_fn alloc, void *user)
 {
     const bool fuse = fused_dtype >= 0;
     c->err.clear();
     c->plan.valid = false;
-    TRY(check_csr(c, A, "A", fuse));
-    TRY(check_csr(c, B, "B", fuse));
-    if (A->cols != B->rows) return fail(c, SMASH_ERR_INVALID_ARG, "A.cols (%lld) != B.rows (%lld)", (long long)A->cols, (long long)B->rows);
+    TRY(check_pair(c, A, B, fuse));
     if (!C_row_ptr || !C_nnz) return fail(c, SMASH_ERR_INVALID_ARG, "C_row_ptr and C_nnz must not be NULL");
     DeviceGuard g(c->device);
     if (!g.ok) return fail(c, SMASH_ERR_HIP, "hipSetDevice(%d) failed", c->device);
 
     Plan &p = c->plan;
-    p = Plan();
-    p.A = *A;
-    p.B = *B;
+    plan_init(c, p, A, B, fuse, fused_dtype);
     p.crp = C_row_ptr;
-    p.m = A->rows;
-    p.n = B->cols;
-    p.heavy_mode = (int)c->opt[SMASH_OPT_HEAVY_MODE];
-    p.lds_row_max = (int)c->opt[SMASH_OPT_LDS_ROW_MAX];
-    p.nchunks = (int)std::max<int64_t>(1, (p.n + kChunkCols - 1) / kChunkCols);
-    p.fused = fuse;
-    p.fused_dtype = fuse ? fused_dtype : 0;
     const int64_t m = p.m;
     c->stats = smash_stats();
     c->stats.rows = m;
+    carve_workspace(c, p, nullptr, 0);
+    if (ws_bytes < p.ws_fixed || (!ws && p.ws_fixed > 0)) {
+        size_t need = p.ws_fixed;
+        if (ws_bytes < p.ws_fixed) TRY(workspace_query(c, A, B, fuse, &need, s));
+        c->stats.workspace_bytes = (int64_t)need;
+        return fail(c, SMASH_ERR_CAPACITY, "the workspace holds %zu bytes; this product needs %zu", ws_bytes, need);
+    }
+    carve_workspace(c, p, (char *)ws, ws_bytes);
+    p.ws = ws;
+    p.ws_bytes = ws_bytes;
+    c->stats.workspace_bytes = (int64_t)p.ws_fixed;
 
     HIP_TRY(c, hipMemsetAsync(c->d_hdr, 0, sizeof(DevHdr), s));
     if (c->opt[SMASH_OPT_VALIDATE]) {
-        TRY(validate_csr(c, s, *A, kErrCsrA, &c->d_hdr->error));
-        TRY(validate_csr(c, s, *B, kErrCsrB, &c->d_hdr->error));
-    }
-    if (c->opt[SMASH_OPT_VALIDATE] && m > 0) {
-        // no kernel below may dereference an index of an invalid matrix
-        TRY(read_hdr(c, s));
-        TRY(device_errors(c, c->h_hdr->error));
+        TRY(validate_csr(c, s, *A, kErrCsrA, perr(c), p.valid_bm));
+        TRY(validate_csr(c, s, *B, kErrCsrB, perr(c), p.valid_bm));
     }
     if (m == 0) {
         HIP_TRY(c, hipMemsetAsync(C_row_ptr, 0, sizeof(int64_t), s));
         TRY(read_hdr(c, s));
         TRY(device_errors(c, c->h_hdr->error));
+        TRY(numeric_errors(c, s));
         *C_nnz = 0;
         p.hdr = DevHdr();
         p.valid = true;
         return SMASH_OK;
     }
 
-    // per-row plan arrays
-    const bool global = p.heavy_mode == 1;
-    p.nblk = (int)blocks_for(m, kBinBlockRows);
-    const int nsb = (int)blocks_for(m, kScanItems);
-    {
-        const size_t need = carve_size({m * sizeof(long long), m * sizeof(int), m * sizeof(int), m * sizeof(int),
-                                        m * sizeof(int), (size_t)m, (size_t)m,
-                                        (size_t)p.nblk * kNumBins * sizeof(int), (size_t)p.nblk * 8,
-                                        (size_t)p.nblk * kNumBins * 8,
-                                        (size_t)(nsb + 1) * 8, global ? (size_t)m * 8 : 0,
-                                        global ? (size_t)(m + 1) * 8 : 0, global ? (size_t)(m + 1) * 8 : 0});
-        TRY(ensure(c, c->plan_mem, need, s));
-        Carve cv{(char *)c->plan_mem.ptr};
-        p.ub = cv.take<long long>(m);
-        p.cap = cv.take<int>(m);
-        p.nnzc = cv.take<int>(m);
-        p.sym_perm = cv.take<int>(m);
-        p.num_perm = cv.take<int>(m);
-        p.sym_bin = cv.take<unsigned char>(m);
-        p.num_bin = cv.take<unsigned char>(m);
-        p.bcount = cv.take<int>((size_t)p.nblk * kNumBins);
-        p.bprod = cv.take<unsigned long long>(p.nblk);
-        p.bw = cv.take<long long>((size_t)p.nblk * kNumBins);
-        p.bsum = cv.take<long long>(nsb + 1);
-        if (global) {
-            p.gsz = cv.take<long long>(m);
-            p.goff_sym = cv.take<long long>(m + 1);
-            p.goff_num = cv.take<long long>(m + 1);
-        }
-    }
-
     // a1/a2: products per row (and the predictor's features for the fused
     // pass), bins, rows grouped by bin
+    const bool global = p.heavy_mode == 1;
     const bool learned = fuse && c->opt[SMASH_OPT_FUSED_SIZING] == 0;
-    if (fuse) TRY(fused_alloc(c, s, p));
     TRY(launch(c, K_ANALYZE, s, [&] {
         k_analyze<<<blocks_for(m, 4), 256, 0, s>>>((int)m, (int)p.n, p.lds_row_max, A->row_ptr, A->col_idx, B->row_ptr,
                                                    p.ub, p.cap, p.nnzc, p.sym_bin, learned ? p.feats : nullptr,
-                                                   learned ? p.maxb : nullptr);
+                                                   learned ? p.maxb : nullptr, perr(c));
     }));
-    if (fuse) TRY(fused_stage(c, s, p));
-    TRY(bin_rows(c, s, p, p.sym_bin, p.ub, nullptr, &c->d_hdr->sym, p.sym_perm, global ? p.cap : nullptr));
-    TRY(read_hdr(c, s));
-    TRY(device_errors(c, c->h_hdr->error));
-    p.hdr = *c->h_hdr;
-    const int H = p.hdr.sym.count[kBinHeavy];
-    const int *heavy_rows = p.sym_perm + p.hdr.sym.offset[kBinHeavy];
-    if (global && H > 0)
-        TRY(scan_counts<long long>(c, s, H, p.gsz, p.bsum, p.goff_sym, (long long *)&c->d_hdr->gneed[0]));
+    if (fuse) TRY(fused_stage(c, s, p, alloc, user));
+    TRY(bin_rows(c, s, p, p.sym_bin, p.ub, nullptr, &c->d_hdr->sym, p.sym_perm, global ? p.cap : nullptr,
+                 global ? -1 : p.hcap));
+    const int *heavy_rows_dev = p.sym_perm;     // + the heavy bin's offset, read on the device
 
     // a3: symbolic per bin
     TRY(run_sym_bins(c, s, p));
-    if (H > 0 && !global) {
+    if (!global && p.hcap > 0) {
         const long long kdim = p.B.rows;
-        const size_t cells = (size_t)H * p.nchunks;
-        const size_t need = carve_size({(size_t)(kdim * (p.nchunks + 1)) * sizeof(int), cells * sizeof(int),
-                                        cells * sizeof(int), (size_t)kSegBins * p.nchunks * sizeof(int),
-                                        cells * sizeof(Seg), 64 * sizeof(int)});
-        TRY(ensure(c, c->heavy_mem, need, s));
-        Carve cv{(char *)c->heavy_mem.ptr};
-        p.bsplit = cv.take<int>((size_t)(kdim * (p.nchunks + 1)));
-        p.wcnt = cv.take<int>(cells);
-        p.woff = cv.take<int>(cells);
-        p.seg_bcount = cv.take<int>((size_t)kSegBins * p.nchunks);
-        p.segs = cv.take<Seg>(cells);
-        p.queue = cv.take<int>(64);
         TRY(launch(c, K_BSPLIT, s, [&] {
             k_bsplit<<<blocks_for(kdim * (p.nchunks + 1), 256), 256, 0, s>>>((int)kdim, p.nchunks, B->row_ptr,
-                                                                            B->col_idx, p.bsplit);
+                                                                            B->col_idx, p.bsplit, perr(c));
         }));
         const int nwin = (p.nchunks + kSymWinChunks - 1) / kSymWinChunks;
         TRY(launch(c, K_SYM_HEAVY, s, [&] {
-            k_sym_heavy<<<(unsigned)((long long)H * nwin), kSymHeavyThreads, 0, s>>>(
-                A->row_ptr, A->col_idx, B->col_idx, p.bsplit, (long long)(p.nchunks + 1), heavy_rows, H, p.nchunks, p.wcnt, p.nnzc);
+            k_sym_heavy<<<(unsigned)(p.hcap * nwin), kSymHeavyThreads, 0, s>>>(
+                A->row_ptr, A->col_idx, B->col_idx, p.bsplit, (long long)(p.nchunks + 1), heavy_rows_dev,
+                &c->d_hdr->sym, (int)p.hcap, p.nchunks, p.wcnt, p.nnzc, perr(c));
         }));
-    } else if (H > 0) {
+    } else if (global) {
+        // the waves are planned on the host: the heavy rows' table offsets
+        // are read back (a second synchronisation, in global mode only)
         TRY(read_hdr(c, s));
-        TRY(plan_global_waves(c, s, p.goff_sym, H, (long long)c->h_hdr->gneed[0], c->opt[SMASH_OPT_GLOBAL_POOL],
-                              p.sym_waves, p.sym_pool));
-        TRY(ensure(c, c->gkeys, (size_t)p.sym_pool * sizeof(int), s));
-        for (size_t w = 0; w + 1 < p.sym_waves.size(); ++w) {
-            const int h0 = p.sym_waves[w].first, nh = p.sym_waves[w + 1].first - h0;
-            const long long base = p.sym_waves[w].second, slots = p.sym_waves[w + 1].second - base;
-            TRY(launch(c, K_FILL, s, [&] { k_fill_i32<<<2048, 256, 0, s>>>(slots, (int *)c->gkeys.ptr, kEmpty); }));
-            TRY(launch(c, K_SYM_GLOBAL, s, [&] {
-                k_sym_global<<<nh, kGlobalThreads, 0, s>>>(A->row_ptr, A->col_idx, B->row_ptr, B->col_idx,
-                                                           heavy_rows + h0, p.cap, p.goff_sym + h0, base,
-                                                           (int *)c->gkeys.ptr, p.nnzc, &c->d_hdr->error);
-            }));
+        TRY(device_errors(c, c->h_hdr->error));
+        const int H = c->h_hdr->sym.count[kBinHeavy];
+        if (H > 0) {
+            const int *heavy_rows = p.sym_perm + c->h_hdr->sym.offset[kBinHeavy];
+            TRY(scan_counts<long long>(c, s, H, p.gsz, p.bsum, p.goff_sym, (long long *)&c->d_hdr->gneed[0]));
+            TRY(read_hdr(c, s));
+            const long long total = (long long)c->h_hdr->gneed[0];
+            const long long lim = c->opt[SMASH_OPT_GLOBAL_POOL] > 0
+                                      ? std::min<long long>(c->opt[SMASH_OPT_GLOBAL_POOL], p.pool_cap)
+                                      : p.pool_cap;
+            TRY(plan_global_waves(c, s, p.goff_sym, H, total, lim, p.sym_waves, p.sym_pool));
+            if (p.sym_pool > p.pool_cap) {
+                c->stats.workspace_bytes = (int64_t)workspace_need(p, 0, p.sym_pool);
+                return fail(c, SMASH_ERR_CAPACITY, "a heavy row's global table needs %lld slots; the workspace "
+                            "holds %lld (%lld bytes needed)", p.sym_pool, p.pool_cap,
+                            (long long)c->stats.workspace_bytes);
+            }
+            for (size_t w = 0; w + 1 < p.sym_waves.size(); ++w) {
+                const int h0 = p.sym_waves[w].first, nh = p.sym_waves[w + 1].first - h0;
+                const long long base = p.sym_waves[w].second, slots = p.sym_waves[w + 1].second - base;
+                TRY(launch(c, K_FILL, s, [&] { k_fill_i32<<<2048, 256, 0, s>>>(slots, p.gkeys, kEmpty); }));
+                TRY(launch(c, K_SYM_GLOBAL, s, [&] {
+                    k_sym_global<<<nh, kGlobalThreads, 0, s>>>(A->row_ptr, A->col_idx, B->row_ptr, B->col_idx,
+                                                               heavy_rows + h0, p.cap, p.goff_sym + h0, base,
+                                                               p.gkeys, p.nnzc, perr(c));
+                }));
+            }
         }
     }
 
@@ -846,34 +1001,51 @@ smash_status symbolic_impl(smash_ctx c, const smash_csr *A, const smash_csr *B, 
     TRY(launch(c, K_NUM_BINS, s, [&] {
         k_num_bins<<<blocks_for(m, 256), 256, 0, s>>>((int)m, p.nnzc, p.sym_bin, p.num_bin);
     }));
-    TRY(bin_rows(c, s, p, p.num_bin, nullptr, p.nnzc, &c->d_hdr->num, p.num_perm, global ? p.nnzc : nullptr));
-    if (H > 0 && global)
-        TRY(scan_counts<long long>(c, s, H, p.gsz, p.bsum, p.goff_num, (long long *)&c->d_hdr->gneed[1]));
-    if (H > 0 && !global) {
-        const int nhb = (int)blocks_for(H, 256);
+    TRY(bin_rows(c, s, p, p.num_bin, nullptr, p.nnzc, &c->d_hdr->num, p.num_perm, global ? p.nnzc : nullptr, -1));
+    if (global && c->h_hdr->sym.count[kBinHeavy] > 0)
+        TRY(scan_counts<long long>(c, s, c->h_hdr->sym.count[kBinHeavy], p.gsz, p.bsum, p.goff_num,
+                                   (long long *)&c->d_hdr->gneed[1]));
+    if (!global && p.hcap > 0) {
+        const unsigned nhb = blocks_for(p.hcap, 256);
         TRY(launch(c, K_CHUNK_PREFIX, s, [&] {
-            k_chunk_prefix<<<blocks_for(H, 4), 256, 0, s>>>(H, p.nchunks, p.wcnt, p.woff);
+            k_chunk_prefix<<<blocks_for(p.hcap, 4), 256, 0, s>>>(&c->d_hdr->sym, p.nchunks, p.wcnt, p.woff, perr(c));
         }));
         TRY(launch(c, K_FILL, s, [&] {
             k_fill_i32<<<blocks_for(kSegBins * p.nchunks, 256), 256, 0, s>>>((long long)kSegBins * p.nchunks,
                                                                            p.seg_bcount, 0);
         }));
         TRY(launch(c, K_SEG_PLAN, s, [&] {
-            k_seg_plan<<<nhb, 256, 0, s>>>(0, H, p.nchunks, p.wcnt, p.woff, heavy_rows, A->row_ptr,
-                                           (const long long *)C_row_ptr, p.seg_bcount, &c->d_hdr->seg, p.segs);
+            k_seg_plan<<<nhb, 256, 0, s>>>(0, &c->d_hdr->sym, p.sym_perm, p.nchunks, p.wcnt, p.woff, A->row_ptr,
+                                           (const long long *)C_row_ptr, p.seg_bcount, &c->d_hdr->seg, p.segs, perr(c));
         }));
-        TRY(launch(c, K_SEG_SCAN, s, [&] { k_seg_scan<<<1, kWave, 0, s>>>(p.nchunks, p.seg_bcount, &c->d_hdr->seg); }));
+        TRY(launch(c, K_SEG_SCAN, s, [&] {
+            k_seg_scan<<<1, kWave, 0, s>>>(p.nchunks, p.seg_bcount, &c->d_hdr->seg, perr(c));
+        }));
         TRY(launch(c, K_SEG_PLAN, s, [&] {
-            k_seg_plan<<<nhb, 256, 0, s>>>(1, H, p.nchunks, p.wcnt, p.woff, heavy_rows, A->row_ptr,
-                                           (const long long *)C_row_ptr, p.seg_bcount, &c->d_hdr->seg, p.segs);
+            k_seg_plan<<<nhb, 256, 0, s>>>(1, &c->d_hdr->sym, p.sym_perm, p.nchunks, p.wcnt, p.woff, A->row_ptr,
+                                           (const long long *)C_row_ptr, p.seg_bcount, &c->d_hdr->seg, p.segs, perr(c));
         }));
     }
     TRY(read_hdr(c, s));
     p.hdr = *c->h_hdr;
+    const int H = p.hdr.sym.count[kBinHeavy];
+    if (p.hdr.error & kErrCapacity) {
+        c->stats.workspace_bytes = (int64_t)workspace_need(p, H, 0);
+        return fail(c, SMASH_ERR_CAPACITY, "the workspace holds %lld heavy rows, the product has %d "
+                    "(%lld bytes needed)", p.hcap, H, (long long)c->stats.workspace_bytes);
+    }
     TRY(device_errors(c, p.hdr.error));
-    if (H > 0 && global)
-        TRY(plan_global_waves(c, s, p.goff_num, H, (long long)p.hdr.gneed[1], c->opt[SMASH_OPT_GLOBAL_POOL],
-                              p.num_waves, p.num_pool));
+    TRY(numeric_errors(c, s));
+    if (H > 0 && global) {
+        const long long lim = c->opt[SMASH_OPT_GLOBAL_POOL] > 0
+                                  ? std::min<long long>(c->opt[SMASH_OPT_GLOBAL_POOL], p.pool_cap)
+                                  : p.pool_cap;
+        TRY(plan_global_waves(c, s, p.goff_num, H, (long long)p.hdr.gneed[1], lim, p.num_waves, p.num_pool));
+        if (p.num_pool > p.pool_cap)     // cannot happen: numeric tables are no larger than symbolic ones
+            return fail(c, SMASH_ERR_CAPACITY, "global tables exceed the workspace");
+    }
+    c->stats.workspace_bytes = (int64_t)(global ? workspace_need(p, 0, std::max(p.sym_pool, p.num_pool))
+                                                : workspace_need(p, H, 0));
     *C_nnz = p.hdr.nnz_c;
     c->stats.products = (int64_t)p.hdr.products;
     c->stats.nnz_c = p.hdr.nnz_c;
@@ -899,53 +1071,91 @@ smash_status symbolic_impl(smash_ctx c, const smash_csr *A, const smash_csr *B, 
     return SMASH_OK;
 }
 
-}  // namespace
-
-smash_status smash_spgemm_symbolic(smash_ctx c, const smash_csr *A, const smash_csr *B, int64_t *C_row_ptr,
-                                   int64_t *C_nnz, hipStream_t s)
+template <typename V>
+smash_status numeric_dispatch(smash_ctx c, hipStream_t s, const Plan &p, const smash_csr *A, const smash_csr *B,
+                              const int64_t *C_row_ptr, int32_t *C_col_idx, void *C_val)
 {
-    if (!c) return SMASH_ERR_INVALID_ARG;
-    return symbolic_impl(c, A, B, C_row_ptr, C_nnz, s, -1);
+    TRY(numeric_impl<V>(c, s, p, (const V *)A->val, (const V *)B->val, C_row_ptr, C_col_idx, (V *)C_val));
+    return fused_copy<V>(c, s, p, C_row_ptr, C_col_idx, (V *)C_val);
 }
 
-smash_status smash_spgemm_numeric(smash_ctx c, smash_dtype dtype, const smash_csr *A, const smash_csr *B,
-                                  const int64_t *C_row_ptr, int32_t *C_col_idx, void *C_val, hipStream_t s)
+smash_status numeric_checked(smash_ctx c, smash_dtype dtype, const smash_csr *A, const smash_csr *B,
+                             const int64_t *C_row_ptr, int32_t *C_col_idx, void *C_val, const void *ws,
+                             hipStream_t s)
 {
-    if (!c) return SMASH_ERR_INVALID_ARG;
     c->err.clear();
     if (dtype != SMASH_F32 && dtype != SMASH_F64) return fail(c, SMASH_ERR_INVALID_ARG, "unknown dtype %d", (int)dtype);
     TRY(check_csr(c, A, "A", true));
     TRY(check_csr(c, B, "B", true));
     const Plan &p = c->plan;
-    if (!p.valid || p.fused || !same_csr(p.A, *A) || !same_csr(p.B, *B) || p.crp != C_row_ptr)
-        return fail(c, SMASH_ERR_NO_PLAN, "no symbolic plan on this context for these A, B and C_row_ptr");
+    if (!p.valid || !same_csr(p.A, *A) || !same_csr(p.B, *B) || p.crp != C_row_ptr || p.ws != ws)
+        return fail(c, SMASH_ERR_NO_PLAN, "no symbolic plan on this context for these A, B, C_row_ptr and workspace");
+    if (p.fused && (int)dtype != p.fused_dtype) return fail(c, SMASH_ERR_INVALID_ARG, "dtype differs from the fused pass");
     if (p.hdr.nnz_c > 0 && (!C_col_idx || !C_val))
         return fail(c, SMASH_ERR_INVALID_ARG, "C_col_idx and C_val must not be NULL");
     if (p.m == 0 || p.hdr.nnz_c == 0) return SMASH_OK;
     DeviceGuard g(c->device);
     if (!g.ok) return fail(c, SMASH_ERR_HIP, "hipSetDevice(%d) failed", c->device);
-    HIP_TRY(c, hipMemsetAsync(&c->d_hdr->error, 0, sizeof(int), s));
-    smash_status st;
-    if (dtype == SMASH_F32)
-        st = numeric_impl<float>(c, s, p, (const float *)A->val, (const float *)B->val, C_row_ptr, C_col_idx,
-                                 (float *)C_val);
-    else
-        st = numeric_impl<double>(c, s, p, (const double *)A->val, (const double *)B->val, C_row_ptr, C_col_idx,
-                                  (double *)C_val);
-    if (st != SMASH_OK) return st;
-    TRY(read_hdr(c, s));
-    return device_errors(c, c->h_hdr->error);
+    if (dtype == SMASH_F32) return numeric_dispatch<float>(c, s, p, A, B, C_row_ptr, C_col_idx, C_val);
+    return numeric_dispatch<double>(c, s, p, A, B, C_row_ptr, C_col_idx, C_val);
+}
+
+}  // namespace
+
+extern "C" {
+
+smash_status smash_workspace_size(smash_ctx c, smash_dtype dtype, const smash_csr *A, const smash_csr *B,
+                                  size_t *bytes, hipStream_t s)
+{
+    if (!c) return SMASH_ERR_INVALID_ARG;
+    c->err.clear();
+    if (!bytes) return fail(c, SMASH_ERR_INVALID_ARG, "bytes is NULL");
+    if (dtype != SMASH_F32 && dtype != SMASH_F64) return fail(c, SMASH_ERR_INVALID_ARG, "unknown dtype %d", (int)dtype);
+    TRY(check_pair(c, A, B, false));
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(c, SMASH_ERR_HIP, "hipSetDevice(%d) failed", c->device);
+    size_t plain = 0, fused = 0;
+    TRY(workspace_query(c, A, B, false, &plain, s));
+    const bool fusable = c->has_predictor || c->opt[SMASH_OPT_FUSED_SIZING] == 1;
+    if (fusable) {
+        Plan q;
+        plan_init(c, q, A, B, true, (int)dtype);
+        carve_workspace(c, q, nullptr, 0);
+        Plan r;
+        plan_init(c, r, A, B, false, 0);
+        carve_workspace(c, r, nullptr, 0);
+        fused = plain + (q.ws_fixed - r.ws_fixed);
+    }
+    *bytes = std::max(plain, fused);
+    return SMASH_OK;
+}
+
+smash_status smash_spgemm_symbolic(smash_ctx c, const smash_csr *A, const smash_csr *B, int64_t *C_row_ptr,
+                                   int64_t *C_nnz, void *ws, size_t ws_bytes, hipStream_t s)
+{
+    if (!c) return SMASH_ERR_INVALID_ARG;
+    return symbolic_impl(c, A, B, C_row_ptr, C_nnz, ws, ws_bytes, s, -1, nullptr, nullptr);
+}
+
+smash_status smash_spgemm_numeric(smash_ctx c, smash_dtype dtype, const smash_csr *A, const smash_csr *B,
+                                  const int64_t *C_row_ptr, int32_t *C_col_idx, void *C_val, void *ws,
+                                  size_t ws_bytes, hipStream_t s)
+{
+    if (!c) return SMASH_ERR_INVALID_ARG;
+    if (c->plan.fused) return fail(c, SMASH_ERR_NO_PLAN, "the plan belongs to a fused call");
+    (void)ws_bytes;
+    return numeric_checked(c, dtype, A, B, C_row_ptr, C_col_idx, C_val, ws, s);
 }
 
 smash_status smash_spgemm(smash_ctx c, smash_dtype dtype, const smash_csr *A, const smash_csr *B,
                           smash_alloc_fn alloc, void *user, int64_t *C_row_ptr, int32_t **C_col_idx, void **C_val,
-                          int64_t *C_nnz, hipStream_t s)
+                          int64_t *C_nnz, void *ws, size_t ws_bytes, hipStream_t s)
 {
     if (!c) return SMASH_ERR_INVALID_ARG;
     if (!alloc || !C_col_idx || !C_val || !C_nnz) return fail(c, SMASH_ERR_INVALID_ARG, "null output argument");
     if (dtype != SMASH_F32 && dtype != SMASH_F64) return fail(c, SMASH_ERR_INVALID_ARG, "unknown dtype %d", (int)dtype);
     int64_t nnz = 0;
-    TRY(smash_spgemm_symbolic(c, A, B, C_row_ptr, &nnz, s));
+    TRY(smash_spgemm_symbolic(c, A, B, C_row_ptr, &nnz, ws, ws_bytes, s));
     const size_t vb = dtype == SMASH_F32 ? 4 : 8;
     void *col = alloc(std::max<size_t>((size_t)nnz * 4, 256), user);
     void *val = alloc(std::max<size_t>((size_t)nnz * vb, 256), user);
@@ -953,7 +1163,23 @@ smash_status smash_spgemm(smash_ctx c, smash_dtype dtype, const smash_csr *A, co
     *C_col_idx = (int32_t *)col;
     *C_val = val;
     *C_nnz = nnz;
-    return smash_spgemm_numeric(c, dtype, A, B, C_row_ptr, (int32_t *)col, val, s);
+    return smash_spgemm_numeric(c, dtype, A, B, C_row_ptr, (int32_t *)col, val, ws, ws_bytes, s);
+}
+
+smash_status smash_sync(smash_ctx c, hipStream_t s)
+{
+    if (!c) return SMASH_ERR_INVALID_ARG;
+    c->err.clear();
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(c, SMASH_ERR_HIP, "hipSetDevice(%d) failed", c->device);
+    HIP_TRY(c, hipMemcpyAsync(c->h_numerr, c->d_numerr, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    collect_times(c);
+    const int e = *c->h_numerr;
+    if (!e) return SMASH_OK;
+    *c->h_numerr = 0;
+    HIP_TRY(c, hipMemsetAsync(c->d_numerr, 0, sizeof(int), s));
+    return device_errors(c, e);
 }
 
 smash_status smash_features(smash_ctx c, const smash_csr *A, const smash_csr *B, float *feats, hipStream_t s)
@@ -988,6 +1214,8 @@ smash_status smash_mlp_predict(smash_ctx c, int64_t m, const float *feats, const
     }));
     return SMASH_OK;
 }
+
+}  // extern "C"
 
 namespace {
 
@@ -1035,6 +1263,8 @@ smash_status mlp_step(smash_ctx c, hipStream_t s, const float *feats, const floa
 }
 
 }  // namespace
+
+extern "C" {
 
 smash_status smash_mlp_loss_grad(smash_ctx c, const float *feats, const float *targets, const int32_t *idx, int64_t n,
                                  const float *ms, const float *params, float *grad, double *loss, hipStream_t s)
@@ -1148,7 +1378,7 @@ smash_status smash_predictor_load(smash_ctx c, const char *path)
 
 smash_status smash_spgemm_fused(smash_ctx c, smash_dtype dtype, const smash_csr *A, const smash_csr *B,
                                 smash_alloc_fn alloc, void *user, int64_t *C_row_ptr, int32_t **C_col_idx,
-                                void **C_val, int64_t *C_nnz, hipStream_t s)
+                                void **C_val, int64_t *C_nnz, void *ws, size_t ws_bytes, hipStream_t s)
 {
     if (!c) return SMASH_ERR_INVALID_ARG;
     if (!alloc || !C_col_idx || !C_val || !C_nnz || !C_row_ptr)
@@ -1159,7 +1389,7 @@ smash_status smash_spgemm_fused(smash_ctx c, smash_dtype dtype, const smash_csr 
     DeviceGuard g(c->device);
     if (!g.ok) return fail(c, SMASH_ERR_HIP, "hipSetDevice(%d) failed", c->device);
     int64_t nnz = 0;
-    TRY(symbolic_impl(c, A, B, C_row_ptr, &nnz, s, (int)dtype));
+    TRY(symbolic_impl(c, A, B, C_row_ptr, &nnz, ws, ws_bytes, s, (int)dtype, alloc, user));
     Plan &p = c->plan;
     const size_t vb = dtype == SMASH_F32 ? 4 : 8;
     void *col = alloc(std::max<size_t>((size_t)nnz * 4, 256), user);
@@ -1171,21 +1401,7 @@ smash_status smash_spgemm_fused(smash_ctx c, smash_dtype dtype, const smash_csr 
     *C_col_idx = (int32_t *)col;
     *C_val = val;
     *C_nnz = nnz;
-    smash_status st = SMASH_OK;
-    if (p.m > 0 && nnz > 0) {
-        HIP_TRY(c, hipMemsetAsync(&c->d_hdr->error, 0, sizeof(int), s));
-        if (dtype == SMASH_F32) {
-            st = numeric_impl<float>(c, s, p, (const float *)A->val, (const float *)B->val, C_row_ptr, (int32_t *)col,
-                                     (float *)val);
-            if (st == SMASH_OK) st = fused_copy<float>(c, s, p, C_row_ptr, (int32_t *)col, (float *)val);
-        } else {
-            st = numeric_impl<double>(c, s, p, (const double *)A->val, (const double *)B->val, C_row_ptr,
-                                      (int32_t *)col, (double *)val);
-            if (st == SMASH_OK) st = fused_copy<double>(c, s, p, C_row_ptr, (int32_t *)col, (double *)val);
-        }
-        if (st == SMASH_OK) st = read_hdr(c, s);
-        if (st == SMASH_OK) st = device_errors(c, c->h_hdr->error);
-    }
+    const smash_status st = numeric_checked(c, dtype, A, B, C_row_ptr, (int32_t *)col, val, ws, s);
     p.valid = false;    // the staged values belong to this call only
     return st;
 }
@@ -1202,6 +1418,7 @@ int smash_kernel_count(void) { return K_COUNT; }
 smash_status smash_kernel_time(smash_ctx c, int index, const char **name, int64_t *launches, double *ms)
 {
     if (!c || index < 0 || index >= K_COUNT) return SMASH_ERR_INVALID_ARG;
+    collect_times(c);
     if (name) *name = kKernelNames[index];
     if (launches) *launches = c->launches[index];
     if (ms) *ms = c->ms[index];
@@ -1211,6 +1428,7 @@ smash_status smash_kernel_time(smash_ctx c, int index, const char **name, int64_
 smash_status smash_kernel_time_reset(smash_ctx c)
 {
     if (!c) return SMASH_ERR_INVALID_ARG;
+    collect_times(c);
     for (int k = 0; k < K_COUNT; ++k) {
         c->launches[k] = 0;
         c->ms[k] = 0.0;
@@ -1219,6 +1437,7 @@ smash_status smash_kernel_time_reset(smash_ctx c)
 }
 
 }  // extern "C"
+
 
 // ======================================================= batched launch
 
@@ -1233,8 +1452,11 @@ struct smash_batch_plan_s {
     int ncu = 256;
     std::vector<BatchDesc> desc;
     std::vector<int64_t> row0;           // count + 1
-    // library-owned workspace
+    // workspace (caller-owned, from the allocation callback)
+    smash_alloc_fn alloc = nullptr;
+    void *user = nullptr;
     void *ws = nullptr;
+    unsigned *valid_bm = nullptr;
     BatchDesc *d_desc = nullptr;
     long long *d_row0 = nullptr, *ub = nullptr, *gsz = nullptr, *goff = nullptr, *bsum = nullptr, *pnnz = nullptr;
     int *prob = nullptr, *cap = nullptr, *nnzc = nullptr, *sym_perm = nullptr, *num_perm = nullptr, *bcount = nullptr;
@@ -1243,9 +1465,9 @@ struct smash_batch_plan_s {
     RowDesc *rd = nullptr;               // row records of the LDS bins
     int nblk = 0;
     BatchHdr *d_hdr = nullptr, *h_hdr = nullptr;
-    int *gkeys = nullptr;
-    void *gvals = nullptr;
-    long long gcap = 0;                  // slots of gkeys / gvals
+    int *gkeys = nullptr, *gtouch = nullptr;
+    double *gvals = nullptr;
+    long long gcap = 0;                  // slots of gkeys / gvals / gtouch
     long long cap_total = 0;             // sum of the row bounds (pool capacity)
     int wide_words = 1;                  // LDS bitmap words of the widest problem up to kWideMaxCols
     bool any_global = false;             // a problem wider than kWideMaxCols (global tables)
@@ -1265,7 +1487,7 @@ bool batch_cfg_ok(const smash_batch_config &g)
 {
     return g.lds_row_max >= 32 && g.lds_row_max <= 1024 && (g.table_shift == 1 || g.table_shift == 2) &&
            g.lds_row_max <= (2048 >> g.table_shift) && (g.wide_groups == 0 || g.wide_groups == 1) &&
-           g.blocks_per_cu >= 1 && g.blocks_per_cu <= 32;
+           g.blocks_per_cu >= 1 && g.blocks_per_cu <= 32 && (g.row_hash == 0 || g.row_hash == 1);
 }
 
 template <int LOGT, int WIDE>
@@ -1294,10 +1516,10 @@ void bbin(const BPlan &p, hipStream_t s, const unsigned char *bin_of, BinHdr *h,
 {
     const int m = (int)p.M;
     k_bin_count<<<p.nblk, 256, 0, s>>>(m, bin_of, products ? p.ub : nullptr, nullptr, p.bcount,
-                                       products ? p.bprod : nullptr, nullptr);
+                                       products ? p.bprod : nullptr, nullptr, nullptr);
     k_bin_scan<<<1, 256, 0, s>>>(p.nblk, p.bcount, products ? p.bprod : nullptr, nullptr, h,
-                                 products ? &p.d_hdr->products : nullptr);
-    k_scatter<<<p.nblk, 256, 0, s>>>(m, bin_of, p.bcount, h, perm, nullptr, nullptr);
+                                 products ? &p.d_hdr->products : nullptr, nullptr, -1);
+    k_scatter<<<p.nblk, 256, 0, s>>>(m, bin_of, p.bcount, h, perm, nullptr, nullptr, nullptr);
 }
 
 // clears the header and runs the per-row analysis (graph-safe)
@@ -1321,8 +1543,13 @@ template <typename V, int LT, int WIDE>
 void bnum_bin(const BPlan &p, hipStream_t s)
 {
     using S = BShape<LT, WIDE>;
-    k_bnum_rows<V, LT, S::WPR, S::RPW><<<bgrid(p, blocks_for(p.M, S::RPW)), S::THREADS, 0, s>>>(
-        p.d_desc, p.rd, p.d_hdr, LT - kMinLogT, p.ccap, p.ccol, (V *)p.cval, &p.d_hdr->error);
+    const unsigned grid = bgrid(p, blocks_for(p.M, S::RPW));
+    if (p.cfg.row_hash)
+        k_bnum_rows<V, LT, S::WPR, S::RPW, 1><<<grid, S::THREADS, 0, s>>>(p.d_desc, p.rd, p.d_hdr, LT - kMinLogT,
+                                                                         p.ccap, p.ccol, (V *)p.cval, &p.d_hdr->error);
+    else
+        k_bnum_rows<V, LT, S::WPR, S::RPW, 0><<<grid, S::THREADS, 0, s>>>(p.d_desc, p.rd, p.d_hdr, LT - kMinLogT,
+                                                                         p.ccap, p.ccol, (V *)p.cval, &p.d_hdr->error);
 }
 
 template <int WIDE>
@@ -1357,7 +1584,7 @@ void batch_numeric(const BPlan &p, hipStream_t s)
         &p.d_hdr->wide_queue);
     if (p.any_global)
         k_bnum_global<V><<<bgrid(p, p.M), kGlobalThreads, kGlobalRankBits / 8, s>>>(
-        p.d_desc, p.prob, p.d_hdr, p.num_perm, p.goff, p.gcap, p.gkeys, (V *)p.gvals, p.ccap, p.crp, p.ccol,
+        p.d_desc, p.prob, p.d_hdr, p.num_perm, p.goff, p.gcap, p.gkeys, p.gvals, p.gtouch, p.ccap, p.crp, p.ccol,
         (V *)p.cval, &p.d_hdr->error);
 }
 
@@ -1408,14 +1635,13 @@ smash_status batch_size_tables(BPlan &p, hipStream_t s)
     TRY(batch_sync(p, s));
     const long long need = std::max<long long>(p.h_hdr->gneed, 1);
     if (need > p.gcap) {
-        const size_t vb = p.dtype == SMASH_F32 ? 4 : 8;
-        if (p.gkeys) (void)hipFree(p.gkeys);
-        if (p.gvals) (void)hipFree(p.gvals);
-        p.gkeys = nullptr;
-        p.gvals = nullptr;
+        // larger tables from the caller's allocation callback (the caller
+        // keeps owning the smaller ones it handed out before)
+        p.gkeys = (int *)p.alloc((size_t)need * sizeof(int), p.user);
+        p.gvals = (double *)p.alloc((size_t)need * sizeof(double), p.user);
+        p.gtouch = (int *)p.alloc((size_t)need * sizeof(int), p.user);
         p.gcap = 0;
-        if (hipMalloc((void **)&p.gkeys, (size_t)need * 4) != hipSuccess ||
-            hipMalloc(&p.gvals, (size_t)need * vb) != hipSuccess)
+        if (!p.gkeys || !p.gvals || !p.gtouch)
             return fail(p.c, SMASH_ERR_OUT_OF_MEMORY, "global tables of %lld slots", need);
         p.gcap = need;
     }
@@ -1429,9 +1655,6 @@ smash_status batch_size_tables(BPlan &p, hipStream_t s)
 void batch_free(BPlan *p)
 {
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
-    if (p->ws) (void)hipFree(p->ws);
-    if (p->gkeys) (void)hipFree(p->gkeys);
-    if (p->gvals) (void)hipFree(p->gvals);
     if (p->h_hdr) (void)hipHostFree(p->h_hdr);
     delete p;
 }
@@ -1450,7 +1673,7 @@ smash_status smash_batch_plan_create(smash_ctx c, smash_dtype dtype, int32_t cou
         return fail(c, SMASH_ERR_INVALID_ARG, "NULL argument or negative count");
     *out = nullptr;
     if (dtype != SMASH_F32 && dtype != SMASH_F64) return fail(c, SMASH_ERR_INVALID_ARG, "unknown dtype %d", (int)dtype);
-    const smash_batch_config def{1024, 1, 0, 8};
+    const smash_batch_config def{1024, 1, 0, 8, 0};
     const smash_batch_config g = cfg ? *cfg : def;
     if (!batch_cfg_ok(g)) return fail(c, SMASH_ERR_INVALID_ARG, "batch configuration out of range");
     for (int q = 0; q < count; ++q) {
@@ -1494,12 +1717,21 @@ smash_status smash_batch_plan_create(smash_ctx c, smash_dtype dtype, int32_t cou
     const long long M = std::max<long long>(p->M, 1);
     p->nblk = (int)blocks_for(M, kBinBlockRows);
     const int nsb = (int)blocks_for(M, kScanItems);
+    long long max_nnz = 0;
+    for (int q = 0; q < count; ++q) max_nnz = std::max<long long>(max_nnz, std::max(A[q].nnz, B[q].nnz));
+    const size_t bm_words = (size_t)(max_nnz + 31) / 32 + 1;
     const size_t need = carve_size({p->desc.size() * sizeof(BatchDesc), ((size_t)count + 1) * 8, (size_t)M * 4,
                                     (size_t)M * 8, (size_t)M * 4, (size_t)M * 4, (size_t)M, (size_t)M,
                                     (size_t)M * 8, (size_t)(M + 1) * 8, (size_t)M * 4, (size_t)M * 4,
                                     (size_t)p->nblk * kNumBins * 4, (size_t)p->nblk * 8, (size_t)(nsb + 1) * 8,
-                                    (size_t)std::max(count, 1) * 8, sizeof(BatchHdr), (size_t)M * sizeof(RowDesc)});
-    if (hipMalloc(&p->ws, need) != hipSuccess) return bail(fail(c, SMASH_ERR_OUT_OF_MEMORY, "batch workspace"));
+                                    (size_t)std::max(count, 1) * 8, sizeof(BatchHdr), (size_t)M * sizeof(RowDesc),
+                                    bm_words * 4});
+    // the plan's workspace and, later, its global tables come from the
+    // caller's allocation callback: the library allocates no device memory
+    p->alloc = alloc;
+    p->user = user;
+    p->ws = alloc(need, user);
+    if (!p->ws) return bail(fail(c, SMASH_ERR_OUT_OF_MEMORY, "allocation callback returned NULL (workspace)"));
     if (hipHostMalloc((void **)&p->h_hdr, sizeof(BatchHdr), hipHostMallocDefault) != hipSuccess)
         return bail(fail(c, SMASH_ERR_HIP, "pinned header"));
     if (hipFuncSetAttribute((const void *)k_bsym_wide, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1532,6 +1764,7 @@ smash_status smash_batch_plan_create(smash_ctx c, smash_dtype dtype, int32_t cou
     p->pnnz = cv.take<long long>(std::max(count, 1));
     p->d_hdr = cv.take<BatchHdr>(1);
     p->rd = cv.take<RowDesc>(M);
+    p->valid_bm = cv.take<unsigned>(bm_words);
     if (hipMemcpyAsync(p->d_desc, p->desc.data(), p->desc.size() * sizeof(BatchDesc), hipMemcpyHostToDevice, s) !=
             hipSuccess ||
         hipMemcpyAsync(p->d_row0, p->row0.data(), ((size_t)count + 1) * 8, hipMemcpyHostToDevice, s) != hipSuccess)
@@ -1539,8 +1772,8 @@ smash_status smash_batch_plan_create(smash_ctx c, smash_dtype dtype, int32_t cou
     if (c->opt[SMASH_OPT_VALIDATE] && count > 0) {
         k_fill_i32<<<1, 256, 0, s>>>((long long)(sizeof(BatchHdr) / sizeof(int)), (int *)p->d_hdr, 0);
         for (int q = 0; q < count && st == SMASH_OK; ++q) {
-            st = validate_csr(c, s, A[q], kErrCsrA, &p->d_hdr->error);
-            if (st == SMASH_OK) st = validate_csr(c, s, B[q], kErrCsrB, &p->d_hdr->error);
+            st = validate_csr(c, s, A[q], kErrCsrA, &p->d_hdr->error, p->valid_bm);
+            if (st == SMASH_OK) st = validate_csr(c, s, B[q], kErrCsrB, &p->d_hdr->error, p->valid_bm);
         }
         if (st != SMASH_OK) return bail(st);
         st = batch_sync(*p, s);
@@ -1701,8 +1934,8 @@ smash_status smash_batch_autotune(smash_batch_plan p, hipStream_t s, int32_t rep
             double ms = 0;
             bool hit = false;
             smash_batch_config found{};
-            while (fscanf(f, "%255s %d %d %d %d %lf", k, &g.lds_row_max, &g.table_shift, &g.wide_groups,
-                          &g.blocks_per_cu, &ms) == 6)
+            while (fscanf(f, "%255s %d %d %d %d %d %lf", k, &g.lds_row_max, &g.table_shift, &g.wide_groups,
+                          &g.blocks_per_cu, &g.row_hash, &ms) == 7)
                 if (strcmp(k, key) == 0 && batch_cfg_ok(g)) {
                     found = g;
                     hit = true;
@@ -1720,10 +1953,11 @@ smash_status smash_batch_autotune(smash_batch_plan p, hipStream_t s, int32_t rep
     for (int lrm : {256, 512, 1024})
         for (int sh : {1, 2})
             for (int wide : {0, 1})
-                for (int bpc : {4, 16}) {
-                    const smash_batch_config g{lrm, sh, wide, bpc};
-                    if (batch_cfg_ok(g)) cands.push_back(g);
-                }
+                for (int bpc : {4, 16})
+                    for (int rh : {0, 1}) {
+                        const smash_batch_config g{lrm, sh, wide, bpc, rh};
+                        if (batch_cfg_ok(g)) cands.push_back(g);
+                    }
     hipEvent_t e0, e1;
     HIP_TRY(p->c, hipEventCreate(&e0));
     if (hipEventCreate(&e1) != hipSuccess) {
@@ -1759,8 +1993,8 @@ smash_status smash_batch_autotune(smash_batch_plan p, hipStream_t s, int32_t rep
     if (cache_path) {
         FILE *f = fopen(cache_path, "a");
         if (!f) return fail(p->c, SMASH_ERR_INVALID_ARG, "cannot append to %s", cache_path);
-        fprintf(f, "%s %d %d %d %d %.6f\n", key, win.lds_row_max, win.table_shift, win.wide_groups,
-                win.blocks_per_cu, top);
+        fprintf(f, "%s %d %d %d %d %d %.6f\n", key, win.lds_row_max, win.table_shift, win.wide_groups,
+                win.blocks_per_cu, win.row_hash, top);
         fclose(f);
     }
     return SMASH_OK;

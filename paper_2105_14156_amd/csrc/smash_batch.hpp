@@ -38,8 +38,6 @@ struct BatchHdr {
     int wide_queue;             // next heavy row of the windowed numeric kernel
 };
 
-enum : int { kErrCapacity = 16 };
-
 // Heavy rows of problems with at most kWideMaxCols columns are counted with
 // an LDS bitmap over all columns and accumulated in LDS windows of
 // kWideWin columns; wider problems use per-row global tables.
@@ -217,8 +215,8 @@ __global__ __launch_bounds__(kWave *WPR *RPW) void k_bsym_rows(const BatchDesc *
 
 // Numeric, LDS bin `bin` (row records with C offsets).  Does nothing when
 // the output pool is too small (the capacity check has then flagged the
-// batch).
-template <typename V, int LOGT, int WPR, int RPW>
+// batch).  HASH as in num_row (0 multiplicative, 1 order-preserving).
+template <typename V, int LOGT, int WPR, int RPW, int HASH>
 __global__ __launch_bounds__(kWave *WPR *RPW) void k_bnum_rows(const BatchDesc *__restrict__ desc,
                                                                const RowDesc *__restrict__ rd, const BatchHdr *bh,
                                                                int bin, long long ccap, int *__restrict__ Ccol,
@@ -231,6 +229,7 @@ __global__ __launch_bounds__(kWave *WPR *RPW) void k_bnum_rows(const BatchDesc *
     __shared__ double s_vals[RPW][T];
     __shared__ EnumScratch<V, G> s_en[RPW];
     __shared__ int s_scan[RPW][WPR + 1];
+    __shared__ int s_maxd[RPW];
     if (bh->nnz_c > ccap) return;
     const int cnt = bh->num.count[bin];
     const RowDesc *rows = rd + bh->num.offset[bin];
@@ -245,8 +244,9 @@ __global__ __launch_bounds__(kWave *WPR *RPW) void k_bnum_rows(const BatchDesc *
         RowDesc nxt{};
         if (base + stride + g < cnt) nxt = rows[base + stride + g];
         const BatchDesc &d = desc[active ? cur.prob : 0];
-        num_row<V, LOGT, WPR>(cur.e0, cur.e1, d.Acol, (const V *)d.Aval, d.Brp, d.Bcol, (const V *)d.Bval, cur.rb,
-                              cur.nc, active, gt, s_keys[g], s_vals[g], s_en[g], s_scan[g], Ccol, Cval, d.cols, err);
+        num_row<V, LOGT, WPR, HASH>(cur.e0, cur.e1, d.Acol, (const V *)d.Aval, d.Brp, d.Bcol, (const V *)d.Bval,
+                                    cur.rb, cur.nc, active, gt, s_keys[g], s_vals[g], s_en[g], s_scan[g], Ccol, Cval,
+                                    d.cols, err, &s_maxd[g]);
         group_sync<WPR>();
         cur = nxt;
     }
@@ -291,7 +291,7 @@ __global__ __launch_bounds__(kGlobalThreads) void k_bnum_global(const BatchDesc 
                                                                 const int *__restrict__ prob, const BatchHdr *bh,
                                                                 const int *__restrict__ perm,
                                                                 const long long *__restrict__ goff, long long gcap,
-                                                                int *gkeys, V *gvals, long long ccap,
+                                                                int *gkeys, double *gvals, int *gtouch, long long ccap,
                                                                 const long long *__restrict__ Crp,
                                                                 int *__restrict__ Ccol, V *__restrict__ Cval, int *err)
 {
@@ -311,7 +311,7 @@ __global__ __launch_bounds__(kGlobalThreads) void k_bnum_global(const BatchDesc 
             continue;
         }
         num_global_row<V>(d.Arp, d.Acol, (const V *)d.Aval, d.Brp, d.Bcol, (const V *)d.Bval, (int)(grow - d.row0),
-                          grow, d.cols, gkeys + off, gvals + off, L, s_bm, Crp, Ccol, Cval, err);
+                          grow, d.cols, gkeys + off, gvals + off, gtouch + off, L, s_bm, Crp, Ccol, Cval, err);
         __syncthreads();
     }
 }

@@ -20,10 +20,11 @@ namespace smash {
 // 0 < ub_i and cap_i <= fused_max, else kBinEmpty (not fused).
 __global__ __launch_bounds__(256) void k_fused_bins(int m, const long long *__restrict__ ub,
                                                     const int *__restrict__ cap_pred, int fused_max,
-                                                    unsigned char *__restrict__ fbin, int *__restrict__ fcap)
+                                                    unsigned char *__restrict__ fbin, int *__restrict__ fcap,
+                                                    const int *err)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m) return;
+    if (i >= m || stopped(err)) return;
     const int c = cap_pred[i];
     const bool fused = ub[i] > 0 && c > 0 && c <= fused_max;
     fbin[i] = (unsigned char)(fused ? lds_bin(c) : kBinEmpty);
@@ -76,19 +77,23 @@ __device__ __forceinline__ void lds_bounded_insert_add_u(int *keys, double *vals
 // columns fit its capacity is put in column order (bitmap ranks or sort, as
 // for the rows of the two-phase path) and written to the staging area at
 // stage_off[row] (status 1, nnzc = count); otherwise status 0 and the row is
-// left to the two-phase path.
+// left to the two-phase path.  Rows of the stage that would end beyond
+// stage_cap entries are left to the two-phase path too.  Persistent grid
+// over the bin's rows (perm + h->offset[bin], h->count[bin] from the
+// device), like k_sym_rows.
 template <typename V, int LOGT, int WPR, int RPW>
 __global__ __launch_bounds__(kWave *WPR *RPW) void k_fused_rows(
     const int *__restrict__ Arp, const int *__restrict__ Acol, const V *__restrict__ Aval,
     const int *__restrict__ Brp, const int *__restrict__ Bcol, const V *__restrict__ Bval,
-    const int *__restrict__ rows, int nrows, const int *__restrict__ fcap, const long long *__restrict__ stage_off,
-    int *__restrict__ scol, V *__restrict__ sval, int *__restrict__ nnzc, unsigned char *__restrict__ status,
-    int ncols)
+    const int *__restrict__ perm, const BinHdr *h, int bin, const int *__restrict__ fcap,
+    const long long *__restrict__ stage_off, long long stage_cap, int *__restrict__ scol, V *__restrict__ sval,
+    int *__restrict__ nnzc, unsigned char *__restrict__ status, int ncols, const int *err)
 {
     static_assert(RPW == 1 || WPR == 1, "multi-row blocks use one wave per row");
     constexpr int T = 1 << LOGT;
     constexpr int G = WPR * kWave;
     constexpr int SPT = T / G;
+    if (stopped(err)) return;
     __shared__ int s_keys[RPW][T];
     __shared__ double s_vals[RPW][T];
     __shared__ EnumScratch<V, G> s_en[RPW];
@@ -98,7 +103,10 @@ __global__ __launch_bounds__(kWave *WPR *RPW) void k_fused_rows(
     const int lane = lane_id(), wave = threadIdx.x / kWave;
     const int g = wave / WPR, wg = wave % WPR;
     const int gt = threadIdx.x - g * G;
-    const int r = blockIdx.x * RPW + g;
+    const int nrows = h->count[bin];
+    const int *rows = perm + h->offset[bin];
+    for (int r0 = blockIdx.x * RPW; r0 < nrows; r0 += gridDim.x * RPW) {
+    const int r = r0 + g;
     const bool active = r < nrows;
     const int row = active ? rows[r] : 0;
     int *keys = s_keys[g];
@@ -145,7 +153,7 @@ __global__ __launch_bounds__(kWave *WPR *RPW) void k_fused_rows(
         if (w < wg) wbase += t;
         total += t;
     }
-    const bool ok = active && !s_full[g] && total <= cap;
+    const bool ok = active && !s_full[g] && total <= cap && stage_off[row] + cap <= stage_cap;
     order_row_entries<T, WPR, SPT>(kr, vr, keys, vals, s_scan[g], total, wbase, incl, cnt, ncols, gt);
     if (active) {
         if (ok) {
@@ -160,6 +168,8 @@ __global__ __launch_bounds__(kWave *WPR *RPW) void k_fused_rows(
             if (ok) nnzc[row] = total;
         }
     }
+    group_sync<WPR>();
+    }
 }
 
 // Rows completed by the fused pass leave the two-phase plan (one global
@@ -167,8 +177,9 @@ __global__ __launch_bounds__(kWave *WPR *RPW) void k_fused_rows(
 __global__ __launch_bounds__(256) void k_fused_mark(int m, const unsigned char *__restrict__ fbin,
                                                     const unsigned char *__restrict__ status,
                                                     const int *__restrict__ nnzc, unsigned char *__restrict__ sym_bin,
-                                                    int *fused_ok, unsigned long long *fused_entries)
+                                                    int *fused_ok, unsigned long long *fused_entries, const int *err)
 {
+    if (stopped(err)) return;
     __shared__ int s_ok;
     __shared__ unsigned long long s_ent;
     if (threadIdx.x == 0) {

@@ -65,7 +65,18 @@ enum : int {
     kErrCsrA = 2,       // A violates the CSR preconditions
     kErrCsrB = 4,       // B violates the CSR preconditions
     kErrCount = 8,      // numeric found a row count different from C_row_ptr
+    kErrCapacity = 16,  // the workspace (or an output pool) is too small
 };
+// Conditions under which the rest of a pipeline must not run: its kernels
+// test them on entry (the flags were set by earlier kernels of the same
+// stream), so that no kernel indexes through an invalid matrix or beyond the
+// workspace, and the host learns of it at its one synchronisation.
+constexpr int kErrStop = kErrCsrA | kErrCsrB | kErrCapacity;
+
+__device__ __forceinline__ bool stopped(const int *err)
+{
+    return err && (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrStop) != 0;
+}
 
 struct BinHdr {
     long long wsum[kNumBins]; // sum of the per-row weights (output entries) per bin
@@ -86,9 +97,15 @@ struct DevHdr {
     long long stage_total;             // staging entries of the fused pass
     BinHdr sym, num, fz;
     SegHdr seg;
-    int error;
+    int error;                         // flags of the symbolic pipeline
+    int num_error;                     // flags of numeric calls, kept until read
     int fused_ok;                      // rows completed by the fused pass
     unsigned long long fused_entries;  // their entries
+    // workspace query (smash_workspace_size): heavy rows, and the global
+    // tables of the symbolic pass (total and largest, in slots)
+    int q_heavy;
+    unsigned long long q_gsum;
+    unsigned long long q_gmax;
 };
 
 // A column segment of a heavy row: the row, its A entries, the chunk range,
@@ -522,6 +539,50 @@ __device__ __forceinline__ int lds_insert_key_u(int *keys, int logT, const int (
     return added;
 }
 
+// Order-preserving variant (the paper's first version, High-Bit Hashing):
+// the home slot of column j is j >> shift, so slots rise with the column;
+// CAS-first like lds_insert_add_u, then +1 linear probing (modulo T).  The
+// longest probe distance of the row is kept in *maxd: the table is then
+// sorted except within that distance (see order_row_entries_ord).
+template <int U>
+__device__ __forceinline__ void lds_insert_add_ord_u(int *keys, double *vals, int logT, int shift, const int (&j)[U],
+                                                     const double (&p)[U], const bool (&ok)[U], int *maxd, int *err)
+{
+    const unsigned mask = (1u << logT) - 1;
+    unsigned h[U];
+    int old[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) h[u] = ((unsigned)j[u] >> shift) & mask;
+#pragma unroll
+    for (int u = 0; u < U; ++u) old[u] = ok[u] ? atomicCAS(&keys[h[u]], kEmpty, j[u]) : j[u];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        if (!ok[u]) continue;
+        if (old[u] == kEmpty || old[u] == j[u]) {
+            atomicAdd(&vals[h[u]], p[u]);
+            continue;
+        }
+        unsigned hh = h[u];
+        bool placed = false;
+        for (unsigned d = 1; d <= mask; ++d) {
+            hh = (hh + 1) & mask;
+            int cur = __hip_atomic_load(&keys[hh], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (cur == kEmpty) {
+                const int o = atomicCAS(&keys[hh], kEmpty, j[u]);
+                cur = o == kEmpty ? j[u] : o;
+            }
+            if (cur == j[u]) {
+                atomicAdd(&vals[hh], p[u]);
+                if ((int)d > __hip_atomic_load(maxd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
+                    atomicMax(maxd, (int)d);
+                placed = true;
+                break;
+            }
+        }
+        if (!placed) atomicOr(err, kErrProbe);
+    }
+}
+
 // --------------------------------------------------------------- validation
 
 // CSR preconditions of one matrix in two passes (a violation sets `flag` in
@@ -529,7 +590,8 @@ __device__ __forceinline__ int lds_insert_key_u(int *keys, int logT, const int (
 // never decreases; the first entry of every non-empty row is marked in a
 // bitmap over the entries (cleared beforehand).  Entries, one thread per
 // entry (coalesced): the column is in range and above the previous entry's
-// unless the entry starts a row.
+// unless the entry starts a row.  Without a bitmap (starts = NULL) only what
+// memory safety needs is checked: row pointers and column ranges.
 __global__ __launch_bounds__(256) void k_validate_rows(int rows, long long nnz, const int *__restrict__ rp,
                                                        unsigned *__restrict__ starts, int flag, int *err)
 {
@@ -539,7 +601,7 @@ __global__ __launch_bounds__(256) void k_validate_rows(int rows, long long nnz, 
     if (r < rows) {
         const int a = rp[r], b = rp[r + 1];
         if (b < a || a < 0 || (long long)b > nnz) bad = true;
-        else if (a < b) atomicOr(&starts[a >> 5], 1u << (a & 31));
+        else if (a < b && starts) atomicOr(&starts[a >> 5], 1u << (a & 31));
     }
     if (__syncthreads_or(bad) && threadIdx.x == 0) atomicOr(err, flag);
 }
@@ -552,7 +614,7 @@ __global__ __launch_bounds__(256) void k_validate_cols(int cols, long long nnz, 
     if (p < nnz) {
         const int c = ci[p];
         if (c < 0 || c >= cols) bad = true;
-        else if (p > 0 && c <= ci[p - 1] && !((starts[p >> 5] >> (p & 31)) & 1u)) bad = true;
+        else if (starts && p > 0 && c <= ci[p - 1] && !((starts[p >> 5] >> (p & 31)) & 1u)) bad = true;
     }
     if (__syncthreads_or(bad) && threadIdx.x == 0) atomicOr(err, flag);
 }
@@ -586,11 +648,11 @@ __global__ __launch_bounds__(256) void k_analyze(int m, int ncols, int lds_row_m
                                                  const int *__restrict__ Brp, long long *__restrict__ ub_out,
                                                  int *__restrict__ cap_out, int *__restrict__ nnzc,
                                                  unsigned char *__restrict__ bin_out, float *__restrict__ feats,
-                                                 int *__restrict__ maxb_out)
+                                                 int *__restrict__ maxb_out, const int *err)
 {
     const int lane = lane_id();
     const int row = blockIdx.x * 4 + threadIdx.x / kWave;
-    if (row >= m) return;
+    if (row >= m || stopped(err)) return;
     const int e0 = Arp[row], e1 = Arp[row + 1];
     long long ub = 0;
     double sq = 0.0;
@@ -632,6 +694,30 @@ __global__ __launch_bounds__(256) void k_analyze(int m, int ncols, int lds_row_m
     }
 }
 
+// Workspace query: the number of heavy rows (output bound above the LDS row
+// limit) and the global hash table slots their symbolic pass would take
+// (sum and largest), accumulated into the header with one atomic per wave.
+// A wave per row, four rows per block, like k_analyze.
+__global__ __launch_bounds__(256) void k_ws_query(int m, int ncols, int lds_row_max, const int *__restrict__ Arp,
+                                                  const int *__restrict__ Acol, const int *__restrict__ Brp,
+                                                  DevHdr *h)
+{
+    const int lane = lane_id();
+    const int row = blockIdx.x * 4 + threadIdx.x / kWave;
+    if (row >= m || stopped(&h->error)) return;
+    const int e0 = Arp[row], e1 = Arp[row + 1];
+    long long ub = 0;
+    for (int e = e0 + lane; e < e1; e += kWave) ub += Brp[Acol[e] + 1] - Brp[Acol[e]];
+    ub = wave_sum(ub);
+    const long long cap = ub < ncols ? ub : ncols;
+    if (lane == 0 && cap > lds_row_max) {
+        const unsigned long long t = 1ull << gtable_log2(cap);
+        atomicAdd(&h->q_heavy, 1);
+        atomicAdd(&h->q_gsum, t);
+        atomicMax(&h->q_gmax, t);
+    }
+}
+
 // Numeric bin of every row from its exact count (heavy rows stay heavy).
 __global__ __launch_bounds__(256) void k_num_bins(int m, const int *__restrict__ nnzc,
                                                   const unsigned char *__restrict__ sym_bin_of,
@@ -652,8 +738,9 @@ __global__ __launch_bounds__(256) void k_num_bins(int m, const int *__restrict__
 __global__ __launch_bounds__(256) void k_bin_count(int m, const unsigned char *__restrict__ bin_of,
                                                    const long long *__restrict__ ub, const int *__restrict__ wt,
                                                    int *__restrict__ bcount, unsigned long long *__restrict__ bprod,
-                                                   long long *__restrict__ bw)
+                                                   long long *__restrict__ bw, const int *err)
 {
+    if (stopped(err)) return;
     __shared__ int s_hist[kNumBins];
     __shared__ unsigned long long s_w[kNumBins];
     __shared__ unsigned long long s_prod;
@@ -687,8 +774,11 @@ __global__ __launch_bounds__(256) void k_bin_count(int m, const unsigned char *_
 __global__ __launch_bounds__(256) void k_bin_scan(int nblk, int *__restrict__ bcount,
                                                   const unsigned long long *__restrict__ bprod,
                                                   const long long *__restrict__ bw, BinHdr *h,
-                                                  unsigned long long *products)
+                                                  unsigned long long *products, int *err, long long heavy_cap)
 {
+    // err: with heavy_cap >= 0, more heavy rows than the workspace holds
+    // raise kErrCapacity (every later kernel of the pipeline then stops)
+    if (stopped(err)) return;
     __shared__ int s_tot[kNumBins];
     __shared__ long long s_wt[kNumBins];
     // one wave per bin scans the block counts in place (exclusive)
@@ -728,6 +818,7 @@ __global__ __launch_bounds__(256) void k_bin_scan(int nblk, int *__restrict__ bc
         }
         h->offset[kNumBins] = run;
         if (bprod && products) *products = s_p[0] + s_p[1] + s_p[2] + s_p[3];
+        if (err && heavy_cap >= 0 && s_tot[kBinHeavy] > heavy_cap) atomicOr(err, kErrCapacity);
     }
 }
 
@@ -737,8 +828,9 @@ __global__ __launch_bounds__(256) void k_bin_scan(int nblk, int *__restrict__ bc
 __global__ __launch_bounds__(256) void k_scatter(int m, const unsigned char *__restrict__ bin_of,
                                                  const int *__restrict__ bbase, const BinHdr *h,
                                                  int *__restrict__ perm, const int *__restrict__ gsize_of,
-                                                 long long *__restrict__ gsz)
+                                                 long long *__restrict__ gsz, const int *err)
 {
+    if (stopped(err)) return;
     __shared__ int s_cnt[kNumBins];
     if (threadIdx.x < kNumBins) s_cnt[threadIdx.x] = 0;
     __syncthreads();
@@ -787,26 +879,36 @@ __device__ __forceinline__ void sym_row(int e0, int e1, const int *__restrict__ 
     if (active && gt == 0) *out = *s_cnt;
 }
 
-// Light rows: one row per group of WPR waves (RPW groups per block; RPW > 1
-// only with WPR = 1).
+// Light rows of bin `bin`: one row per group of WPR waves (RPW groups per
+// block; RPW > 1 only with WPR = 1).  The grid is persistent: the bin's rows
+// and their number come from the device (perm + h->offset[bin],
+// h->count[bin]) and the groups stride over them, so the launch needs no
+// host-side count.  With RPW > 1 each group is one wave and loops on its
+// own; with WPR > 1 the block is one group and loops as a whole.
 template <int LOGT, int WPR, int RPW>
 __global__ __launch_bounds__(kWave *WPR *RPW) void k_sym_rows(const int *__restrict__ Arp, const int *__restrict__ Acol,
                                                               const int *__restrict__ Brp, const int *__restrict__ Bcol,
-                                                              const int *__restrict__ rows, int nrows,
+                                                              const int *__restrict__ perm, const BinHdr *h, int bin,
                                                               int *__restrict__ nnzc, int *err)
 {
     static_assert(RPW == 1 || WPR == 1, "multi-row blocks use one wave per row");
     constexpr int G = WPR * kWave;
+    if (stopped(err)) return;
     __shared__ int s_keys[RPW][1 << LOGT];
     __shared__ EnumScratch<float, G> s_en[RPW];
     __shared__ int s_cnt[RPW];
     const int g = threadIdx.x / kWave / WPR;
     const int gt = threadIdx.x - g * G;
-    const int r = blockIdx.x * RPW + g;
-    const bool active = r < nrows;
-    const int row = active ? rows[r] : 0;
-    const int e0 = active ? Arp[row] : 0, e1 = active ? Arp[row + 1] : 0;
-    sym_row<LOGT, WPR>(e0, e1, Acol, Brp, Bcol, active, gt, s_keys[g], s_en[g], &s_cnt[g], &nnzc[row], err);
+    const int nrows = h->count[bin];
+    const int *rows = perm + h->offset[bin];
+    for (int r0 = blockIdx.x * RPW; r0 < nrows; r0 += gridDim.x * RPW) {
+        const int r = r0 + g;
+        const bool active = r < nrows;
+        const int row = active ? rows[r] : 0;
+        const int e0 = active ? Arp[row] : 0, e1 = active ? Arp[row + 1] : 0;
+        sym_row<LOGT, WPR>(e0, e1, Acol, Brp, Bcol, active, gt, s_keys[g], s_en[g], &s_cnt[g], &nnzc[row], err);
+        group_sync<WPR>();
+    }
 }
 
 // -------------------------------------------------------- numeric, LDS hash
@@ -923,6 +1025,78 @@ __device__ __forceinline__ void order_row_entries(const int (&kr)[SPT], const do
     group_sync<WPR>();
 }
 
+// Write-back of an order-preserving table (the paper's Write-back Phase,
+// whose insertion sort finishes the order of a semi-sorted table).  kr/vr
+// hold each thread's SPT slots; home(j) = j >> shift; D is the longest probe
+// distance.  The occupied slots are compacted in "unwrapped" slot order:
+// entries at or after their home slot by slot, then those that wrapped past
+// the table's end.  In that order an entry lies at most D places from its
+// place in column order (two entries can be out of order only if both lie
+// within D slots of the lower one's home), so its rank is its position
+// corrected by the entries within D places on either side that belong on
+// its other side: the bounded form of insertion sort, one entry per thread.
+// Leaves the entries in column order at the front of keys/vals; returns
+// their number.  s_scan holds WPR + 1 ints.
+template <int T, int WPR, int SPT>
+__device__ __forceinline__ int order_row_entries_ord(const int (&kr)[SPT], const double (&vr)[SPT], int *keys,
+                                                     double *vals, int *s_scan, int gt, int shift, int D)
+{
+    constexpr int G = WPR * kWave;
+    const int lane = lane_id(), wg = gt / kWave;
+    int packed = 0;                                   // non-wrapped | wrapped << 16
+#pragma unroll
+    for (int s = 0; s < SPT; ++s)
+        if (kr[s] != kEmpty) packed += (gt * SPT + s) >= (int)((unsigned)kr[s] >> shift) ? 1 : (1 << 16);
+    const int incl = wave_incl_scan(packed);
+    group_sync<WPR>();
+    if (lane == kWave - 1) s_scan[wg] = incl;
+    group_sync<WPR>();
+    int base = 0, tot = 0;
+    for (int w = 0; w < WPR; ++w) {
+        const int t = s_scan[w];
+        if (w < wg) base += t;
+        tot += t;
+    }
+    const int n0 = tot & 0xffff, total = n0 + (tot >> 16);
+    const int ex = base + incl - packed;
+    int p0 = ex & 0xffff, p1 = n0 + (ex >> 16);
+#pragma unroll
+    for (int s = 0; s < SPT; ++s) {
+        if (kr[s] == kEmpty) continue;
+        const int at = (gt * SPT + s) >= (int)((unsigned)kr[s] >> shift) ? p0++ : p1++;
+        keys[at] = kr[s];
+        vals[at] = vr[s];
+    }
+    group_sync<WPR>();
+    int xk[SPT], rk[SPT];
+    double xv[SPT];
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+        const int i = gt + q * G;
+        rk[q] = -1;
+        if (i < total) {
+            const int x = keys[i];
+            int r = i;
+            for (int d = 1; d <= D; ++d) {
+                if (i - d >= 0 && keys[i - d] > x) --r;
+                if (i + d < total && keys[i + d] < x) ++r;
+            }
+            xk[q] = x;
+            xv[q] = vals[i];
+            rk[q] = r;
+        }
+    }
+    group_sync<WPR>();
+#pragma unroll
+    for (int q = 0; q < SPT; ++q)
+        if (rk[q] >= 0 && rk[q] < T) {
+            keys[rk[q]] = xk[q];
+            vals[rk[q]] = xv[q];
+        }
+    group_sync<WPR>();
+    return total;
+}
+
 // Numeric pass of one light row by a group of WPR waves (steps a5 and a7):
 // the products of the row's A entries [e0, e1) times B merged in an LDS
 // tag/value table of 2^LOGT slots, then written in column order at C's
@@ -931,22 +1105,31 @@ __device__ __forceinline__ void order_row_entries(const int (&kr)[SPT], const do
 // bitmap over all of B's columns, built in the table's own LDS once its
 // entries are in registers (no sort); otherwise the occupied slots are
 // compacted and sorted (bitonic).
-template <typename V, int LOGT, int WPR>
+// HASH selects the table's hash: 0 = multiplicative, 1 = order-preserving
+// (home slot j >> shift, shift = ceil(log2 ncols) - LOGT, at least 0, with
+// the bounded insertion write-back of order_row_entries_ord; s_maxd is the
+// group's LDS word for the longest probe).
+template <typename V, int LOGT, int WPR, int HASH = 0>
 __device__ __forceinline__ void num_row(int e0, int e1, const int *__restrict__ Acol, const V *__restrict__ Aval,
                                         const int *__restrict__ Brp, const int *__restrict__ Bcol,
                                         const V *__restrict__ Bval, long long rb, int nc, bool active, int gt,
                                         int *keys, double *vals, EnumScratch<V, WPR * kWave> &en, int *s_scan,
-                                        int *__restrict__ Ccol, V *__restrict__ Cval, int ncols, int *err)
+                                        int *__restrict__ Ccol, V *__restrict__ Cval, int ncols, int *err,
+                                        int *s_maxd = nullptr)
 {
     constexpr int T = 1 << LOGT;
     constexpr int G = WPR * kWave;
     constexpr int SPT = T / G;          // slots per thread in the compaction
     static_assert(SPT >= 1, "table smaller than its group");
     const int lane = lane_id(), wg = gt / kWave;
+    const int lc = ceil_log2(ncols);
+    const int shift = lc > LOGT ? lc - LOGT : 0;
     for (int t = gt; t < T; t += G) {
         keys[t] = kEmpty;
         vals[t] = 0.0;
     }
+    if constexpr (HASH == 1)
+        if (gt == 0) *s_maxd = 0;
     group_sync<WPR>();
     if (active) {
         auto get = [&](int e, int &bs, int &bl, V &a) {
@@ -956,11 +1139,32 @@ __device__ __forceinline__ void num_row(int e0, int e1, const int *__restrict__ 
             a = Aval[e];
         };
         auto sink = [&](const int (&j)[4], const double (&p)[4], const bool (&ok)[4]) {
-            lds_insert_add_u<4>(keys, vals, LOGT, j, p, ok, err);
+            if constexpr (HASH == 1) lds_insert_add_ord_u<4>(keys, vals, LOGT, shift, j, p, ok, s_maxd, err);
+            else lds_insert_add_u<4>(keys, vals, LOGT, j, p, ok, err);
         };
         group_products<V, true, G, 4, decltype(get), decltype(sink), true>(e0, e1, gt, en, Bcol, Bval, get, sink);
     }
     group_sync<WPR>();
+    if constexpr (HASH == 1) {
+        int kr[SPT];
+        double vr[SPT];
+#pragma unroll
+        for (int s = 0; s < SPT; ++s) {
+            kr[s] = keys[gt * SPT + s];
+            vr[s] = vals[gt * SPT + s];
+        }
+        const int D = *s_maxd;
+        const int total = order_row_entries_ord<T, WPR, SPT>(kr, vr, keys, vals, s_scan, gt, shift, D);
+        if (active) {
+            if (gt == 0 && nc != total) atomicOr(err, kErrCount);
+            const int nw = total < nc ? total : nc;
+            for (int t = gt; t < nw; t += G) {
+                store_c(&Ccol[rb + t], keys[t]);
+                store_c(&Cval[rb + t], (V)vals[t]);
+            }
+        }
+        return;
+    }
     // compaction of the occupied slots to the front of the table
     int kr[SPT];
     double vr[SPT];
@@ -992,7 +1196,7 @@ __device__ __forceinline__ void num_row(int e0, int e1, const int *__restrict__ 
 }
 
 // Light rows: one row per group of WPR waves (RPW groups per block).
-template <typename V, int LOGT, int WPR, int RPW>
+template <typename V, int LOGT, int WPR, int RPW, int HASH = 0>
 __global__ __launch_bounds__(kWave *WPR *RPW) void k_num_rows(
     const int *__restrict__ Arp, const int *__restrict__ Acol, const V *__restrict__ Aval,
     const int *__restrict__ Brp, const int *__restrict__ Bcol, const V *__restrict__ Bval,
@@ -1006,6 +1210,7 @@ __global__ __launch_bounds__(kWave *WPR *RPW) void k_num_rows(
     __shared__ double s_vals[RPW][T];
     __shared__ EnumScratch<V, G> s_en[RPW];
     __shared__ int s_scan[RPW][WPR + 1];
+    __shared__ int s_maxd[RPW];
     const int g = threadIdx.x / kWave / WPR;
     const int gt = threadIdx.x - g * G;
     const int r = blockIdx.x * RPW + g;
@@ -1014,8 +1219,8 @@ __global__ __launch_bounds__(kWave *WPR *RPW) void k_num_rows(
     const int e0 = active ? Arp[row] : 0, e1 = active ? Arp[row + 1] : 0;
     const long long rb = active ? Crp[row] : 0;
     const int nc = active ? (int)(Crp[row + 1] - rb) : 0;
-    num_row<V, LOGT, WPR>(e0, e1, Acol, Aval, Brp, Bcol, Bval, rb, nc, active, gt, s_keys[g], s_vals[g], s_en[g],
-                          s_scan[g], Ccol, Cval, ncols, err);
+    num_row<V, LOGT, WPR, HASH>(e0, e1, Acol, Aval, Brp, Bcol, Bval, rb, nc, active, gt, s_keys[g], s_vals[g],
+                                s_en[g], s_scan[g], Ccol, Cval, ncols, err, &s_maxd[g]);
 }
 
 // ---------------------------------------------------------------- row scan
@@ -1103,11 +1308,11 @@ __device__ __forceinline__ int lower_bound_col(const int *__restrict__ Bcol, int
 // Split points of every B row at the chunk boundaries:
 // Bsplit[k * (nchunks + 1) + c] = first position of row k with column >= c * kChunkCols.
 __global__ __launch_bounds__(256) void k_bsplit(int brows, int nchunks, const int *__restrict__ Brp,
-                                                const int *__restrict__ Bcol, int *__restrict__ Bsplit)
+                                                const int *__restrict__ Bcol, int *__restrict__ Bsplit, const int *err)
 {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long per = nchunks + 1;
-    if (t >= (long long)brows * per) return;
+    if (t >= (long long)brows * per || stopped(err)) return;
     const int k = (int)(t / per), c = (int)(t % per);
     const int b0 = Brp[k], b1 = Brp[k + 1];
     int pos;
@@ -1120,13 +1325,15 @@ __global__ __launch_bounds__(256) void k_bsplit(int brows, int nchunks, const in
 // Symbolic phase of heavy rows: block (w, h) marks the columns of heavy row h
 // that fall in symbolic window w (kSymWinChunks chunks) in an LDS bitmap, then
 // stores the number of columns of every chunk (wcnt) and adds them to the
-// row's count.
+// row's count.  The grid covers hcap heavy rows (the workspace's capacity, a
+// host-side bound); the number present, sh->count[kBinHeavy], comes from the
+// device, and blocks beyond it return at once.
 constexpr int kSymHeavyThreads = 256;
 
 __global__ __launch_bounds__(kSymHeavyThreads) void k_sym_heavy(
     const int *__restrict__ Arp, const int *__restrict__ Acol, const int *__restrict__ Bcol,
-    const int *__restrict__ Bsplit, long long per, const int *__restrict__ rows, int nheavy, int nchunks,
-    int *__restrict__ wcnt, int *__restrict__ nnzc)
+    const int *__restrict__ Bsplit, long long per, const int *__restrict__ perm, const BinHdr *sh, int hcap,
+    int nchunks, int *__restrict__ wcnt, int *__restrict__ nnzc, const int *err)
 {
     constexpr int G = kSymHeavyThreads;
     constexpr int WG = G / kWave;
@@ -1134,8 +1341,9 @@ __global__ __launch_bounds__(kSymHeavyThreads) void k_sym_heavy(
     __shared__ unsigned bm[WORDS];
     __shared__ EnumScratch<float, G> S;
     // window-major: blocks launched together share one column window of B
-    const int w = blockIdx.x / nheavy, h = blockIdx.x % nheavy;
-    const int row = rows[h];
+    const int w = blockIdx.x / hcap, h = blockIdx.x % hcap;
+    if (h >= sh->count[kBinHeavy] || stopped(err)) return;
+    const int row = perm[sh->offset[kBinHeavy] + h];
     const int gt = threadIdx.x, lane = lane_id(), wg = gt / kWave;
     const int c0 = w * kSymWinChunks;
     const int c1 = c0 + kSymWinChunks < nchunks ? c0 + kSymWinChunks : nchunks;
@@ -1172,11 +1380,11 @@ __global__ __launch_bounds__(kSymHeavyThreads) void k_sym_heavy(
 // Exclusive prefix of the chunk counts of every heavy row (row-relative output
 // offsets of the chunks); one wave per heavy row, 64 chunks per step
 // (coalesced).
-__global__ __launch_bounds__(256) void k_chunk_prefix(int nheavy, int nchunks, const int *__restrict__ wcnt,
-                                                      int *__restrict__ woff)
+__global__ __launch_bounds__(256) void k_chunk_prefix(const BinHdr *sh, int nchunks, const int *__restrict__ wcnt,
+                                                      int *__restrict__ woff, const int *err)
 {
     const int h = blockIdx.x * 4 + threadIdx.x / kWave;
-    if (h >= nheavy) return;
+    if (h >= sh->count[kBinHeavy] || stopped(err)) return;
     const int lane = lane_id();
     const long long base = (long long)h * nchunks;
     int run = 0;
@@ -1230,11 +1438,15 @@ __device__ __forceinline__ void plan_row_segments(const int *__restrict__ wc, in
 // histogram fits kSegPlanLds entries.
 constexpr int kSegPlanLds = 4096;
 
-__global__ __launch_bounds__(256) void k_seg_plan(int pass, int nheavy, int nchunks, const int *__restrict__ wcnt,
-                                                  const int *__restrict__ woff, const int *__restrict__ heavy_rows,
-                                                  const int *__restrict__ Arp, const long long *__restrict__ Crp,
-                                                  int *__restrict__ hist, SegHdr *sh, Seg *__restrict__ segs)
+__global__ __launch_bounds__(256) void k_seg_plan(int pass, const BinHdr *bh, const int *__restrict__ perm,
+                                                  int nchunks, const int *__restrict__ wcnt,
+                                                  const int *__restrict__ woff, const int *__restrict__ Arp,
+                                                  const long long *__restrict__ Crp, int *__restrict__ hist,
+                                                  SegHdr *sh, Seg *__restrict__ segs, const int *err)
 {
+    if (stopped(err)) return;
+    const int nheavy = bh->count[kBinHeavy];
+    const int *__restrict__ heavy_rows = perm + bh->offset[kBinHeavy];
     __shared__ unsigned long long s_nnz[kSegBins];
     __shared__ int s_cnt[kSegPlanLds];
     const int cells = kSegBins * nchunks;
@@ -1292,8 +1504,9 @@ __global__ __launch_bounds__(256) void k_seg_plan(int pass, int nheavy, int nchu
 
 // Offsets of the segment bins and of every (bin, chunk) group; hist becomes
 // the write cursor of each group (one wave).
-__global__ __launch_bounds__(kWave) void k_seg_scan(int nchunks, int *__restrict__ hist, SegHdr *sh)
+__global__ __launch_bounds__(kWave) void k_seg_scan(int nchunks, int *__restrict__ hist, SegHdr *sh, const int *err)
 {
+    if (stopped(err)) return;
     const int lane = lane_id();
     int run = 0;
     for (int b = 0; b < kSegBins; ++b) {
@@ -1551,9 +1764,15 @@ __global__ __launch_bounds__(kGlobalThreads) void k_sym_global(
 
 // Numeric pass of one heavy row in global mode by a whole block: clears the
 // row's global tag/value table, merges the row's products into it with
-// device-scope CAS and atomic add, then writes the entries in column order
-// at C's row `crow` (rank from an LDS bitmap over column windows of
-// kGlobalRankBits; s_bm is the block's dynamic LDS).
+// device-scope CAS and atomic add (FP64 values: the sum is rounded to the
+// output type once, at write-out), then writes the entries in column order
+// at C's row `crow`.  Every slot the row claims is appended to the row's
+// touched-slot list (`touched`, nc entries: the paper's third version keeps
+// its tags in dense arrays with an offset array for the same purpose), so
+// the write-out reads the row's nc entries instead of scanning all T >= 2 nc
+// slots of its table: per window of kGlobalRankBits columns, the listed
+// entries of the window are marked in an LDS bitmap (s_bm, the block's
+// dynamic LDS), ranked by its popcount prefix and stored.
 constexpr int kGlobalRankBits = 1 << 19;
 
 template <typename V>
@@ -1561,14 +1780,15 @@ struct GlobalNumLds {
     EnumScratch<V, kGlobalThreads> S;
     long long tmp[kGlobalThreads / kWave + 1];
     int base[kGlobalThreads];
+    int ntouched;
 };
 
 template <typename V>
 __device__ __forceinline__ void num_global_row(const int *__restrict__ Arp, const int *__restrict__ Acol,
                                                const V *__restrict__ Aval, const int *__restrict__ Brp,
                                                const int *__restrict__ Bcol, const V *__restrict__ Bval, int arow,
-                                               long long crow, int ncols, int *keys, V *vals, GlobalNumLds<V> &L,
-                                               unsigned *s_bm, const long long *__restrict__ Crp,
+                                               long long crow, int ncols, int *keys, double *vals, int *touched,
+                                               GlobalNumLds<V> &L, unsigned *s_bm, const long long *__restrict__ Crp,
                                                int *__restrict__ Ccol, V *__restrict__ Cval, int *err)
 {
     constexpr int WORDS = kGlobalRankBits / 32;
@@ -1580,8 +1800,9 @@ __device__ __forceinline__ void num_global_row(const int *__restrict__ Arp, cons
     const unsigned mask = (unsigned)T - 1;
     for (int t = threadIdx.x; t < T; t += kGlobalThreads) {
         keys[t] = kEmpty;
-        vals[t] = V(0);
+        vals[t] = 0.0;
     }
+    if (threadIdx.x == 0) L.ntouched = 0;
     __threadfence();
     __syncthreads();
     group_products<V, true, kGlobalThreads, 2>(
@@ -1592,13 +1813,16 @@ __device__ __forceinline__ void num_global_row(const int *__restrict__ Arp, cons
             bl = Brp[k + 1] - bs;
             a = Aval[e];
         },
-        [&](int j, double pd) {
-            const V p = (V)pd;
+        [&](int j, double p) {
             unsigned hh = slot_of(j, logT);
             for (unsigned probe = 0; probe <= mask; ++probe) {
                 int cur = gload(&keys[hh]);
                 if (cur == kEmpty) {
                     int old = atomicCAS(&keys[hh], kEmpty, j);
+                    if (old == kEmpty) {                  // claimed: list the slot
+                        const int at = atomicAdd(&L.ntouched, 1);
+                        if (at < nc) touched[at] = (int)hh;
+                    }
                     cur = old == kEmpty ? j : old;
                 }
                 if (cur == j) {
@@ -1611,14 +1835,15 @@ __device__ __forceinline__ void num_global_row(const int *__restrict__ Arp, cons
         });
     __threadfence();
     __syncthreads();
+    const int nt = L.ntouched < nc ? L.ntouched : nc;
     long long done = 0;
     for (int lo = 0; lo < ncols; lo += kGlobalRankBits) {
         const int hi = lo + kGlobalRankBits < ncols ? lo + kGlobalRankBits : ncols;
         for (int t = threadIdx.x; t < WORDS; t += kGlobalThreads) s_bm[t] = 0u;
         __syncthreads();
-        for (int t = threadIdx.x; t < T; t += kGlobalThreads) {
-            const int j = gload(&keys[t]);
-            if (j != kEmpty && j >= lo && j < hi) atomicOr(&s_bm[(j - lo) >> 5], 1u << ((j - lo) & 31));
+        for (int t = threadIdx.x; t < nt; t += kGlobalThreads) {
+            const int j = gload(&keys[touched[t]]);
+            if (j >= lo && j < hi) atomicOr(&s_bm[(j - lo) >> 5], 1u << ((j - lo) & 31));
         }
         __syncthreads();
         int pc = 0;
@@ -1627,9 +1852,10 @@ __device__ __forceinline__ void num_global_row(const int *__restrict__ Arp, cons
         const long long ex = block_excl_scan<long long, kGlobalThreads>((long long)pc, L.tmp, tot);
         L.base[threadIdx.x] = (int)ex;
         __syncthreads();
-        for (int t = threadIdx.x; t < T; t += kGlobalThreads) {
-            const int j = gload(&keys[t]);
-            if (j == kEmpty || j < lo || j >= hi) continue;
+        for (int t = threadIdx.x; t < nt; t += kGlobalThreads) {
+            const int slot = touched[t];
+            const int j = gload(&keys[slot]);
+            if (j < lo || j >= hi) continue;
             const int jl = j - lo, wd = jl >> 5, owner = wd / WPT;
             int rank = L.base[owner];
             for (int q = owner * WPT; q < wd; ++q) rank += __popc(s_bm[q]);
@@ -1637,29 +1863,33 @@ __device__ __forceinline__ void num_global_row(const int *__restrict__ Arp, cons
             const long long pos = done + rank;
             if (pos < nc) {
                 store_c(&Ccol[rb + pos], j);
-                store_c(&Cval[rb + pos], gload_v(&vals[t]));
+                store_c(&Cval[rb + pos], (V)gload_v(&vals[slot]));
             }
         }
         done += tot;
         __syncthreads();
+        if (done >= nt) break;                    // every listed entry is out
     }
-    if (threadIdx.x == 0 && done != nc) atomicOr(err, kErrCount);
+    if (threadIdx.x == 0 && (done != nc || L.ntouched != nc)) atomicOr(err, kErrCount);
 }
 
-// Numeric phase of heavy rows in global mode: one block per row.
+// Numeric phase of heavy rows in global mode: one block per row (the row's
+// table and touched-slot list start at the same offset of the pool's key,
+// value and list arrays).
 template <typename V>
 __global__ __launch_bounds__(kGlobalThreads) void k_num_global(
     const int *__restrict__ Arp, const int *__restrict__ Acol, const V *__restrict__ Aval,
     const int *__restrict__ Brp, const int *__restrict__ Bcol, const V *__restrict__ Bval,
     const int *__restrict__ rows, int ncols, const long long *__restrict__ goff, long long gbase, int *gkeys,
-    V *gvals, const long long *__restrict__ Crp, int *__restrict__ Ccol, V *__restrict__ Cval, int *err)
+    double *gvals, int *gtouch, const long long *__restrict__ Crp, int *__restrict__ Ccol, V *__restrict__ Cval,
+    int *err)
 {
     extern __shared__ unsigned s_bm[];                     // [kGlobalRankBits / 32]
     __shared__ GlobalNumLds<V> L;
     const int row = rows[blockIdx.x];
     const long long at = goff[blockIdx.x] - gbase;
-    num_global_row<V>(Arp, Acol, Aval, Brp, Bcol, Bval, row, row, ncols, gkeys + at, gvals + at, L, s_bm, Crp, Ccol,
-                      Cval, err);
+    num_global_row<V>(Arp, Acol, Aval, Brp, Bcol, Bval, row, row, ncols, gkeys + at, gvals + at, gtouch + at, L, s_bm,
+                      Crp, Ccol, Cval, err);
 }
 
 }  // namespace smash

@@ -24,7 +24,8 @@ OK = 0
 STATUS = {0: "SMASH_OK", 1: "SMASH_ERR_INVALID_ARG", 2: "SMASH_ERR_INVALID_CSR", 3: "SMASH_ERR_INDEX_OVERFLOW",
           4: "SMASH_ERR_CAPACITY", 5: "SMASH_ERR_OUT_OF_MEMORY", 6: "SMASH_ERR_HIP", 7: "SMASH_ERR_NO_PLAN"}
 F32, F64 = 0, 1
-OPT_VALIDATE, OPT_LDS_ROW_MAX, OPT_HEAVY_MODE, OPT_TIMING, OPT_FUSED_SIZING, OPT_GLOBAL_POOL = range(6)
+OPT_VALIDATE, OPT_LDS_ROW_MAX, OPT_HEAVY_MODE, OPT_TIMING, OPT_FUSED_SIZING, OPT_GLOBAL_POOL, OPT_ROW_HASH = range(7)
+CAPACITY = 4
 
 
 class CsrDesc(ctypes.Structure):
@@ -37,7 +38,7 @@ class Stats(ctypes.Structure):
                                                "rows_heavy", "heavy_segments", "heavy_dense_chunks",
                                                "global_slots", "nnz_heavy", "nnz_dense", "fused_rows",
                                                "fused_overflow", "fused_capacity", "global_waves",
-                                               "global_pool", "fused_entries")]
+                                               "global_pool", "fused_entries", "workspace_bytes")]
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}
@@ -61,11 +62,16 @@ _lib.smash_status_string.argtypes = [ctypes.c_int]
 _lib.smash_status_string.restype = ctypes.c_char_p
 _lib.smash_set_option.argtypes = [_c, ctypes.c_int, ctypes.c_int64]
 _lib.smash_get_option.argtypes = [_c, ctypes.c_int, ctypes.POINTER(ctypes.c_int64)]
+_lib.smash_workspace_size.argtypes = [_c, ctypes.c_int, ctypes.POINTER(CsrDesc), ctypes.POINTER(CsrDesc),
+                                      ctypes.POINTER(ctypes.c_size_t), _c]
 _lib.smash_spgemm_symbolic.argtypes = [_c, ctypes.POINTER(CsrDesc), ctypes.POINTER(CsrDesc), _c,
-                                       ctypes.POINTER(ctypes.c_int64), _c]
-_lib.smash_spgemm_numeric.argtypes = [_c, ctypes.c_int, ctypes.POINTER(CsrDesc), ctypes.POINTER(CsrDesc), _c, _c, _c, _c]
+                                       ctypes.POINTER(ctypes.c_int64), _c, ctypes.c_size_t, _c]
+_lib.smash_spgemm_numeric.argtypes = [_c, ctypes.c_int, ctypes.POINTER(CsrDesc), ctypes.POINTER(CsrDesc), _c, _c, _c,
+                                      _c, ctypes.c_size_t, _c]
 _lib.smash_spgemm.argtypes = [_c, ctypes.c_int, ctypes.POINTER(CsrDesc), ctypes.POINTER(CsrDesc), ALLOC_FN, _c, _c,
-                              ctypes.POINTER(_c), ctypes.POINTER(_c), ctypes.POINTER(ctypes.c_int64), _c]
+                              ctypes.POINTER(_c), ctypes.POINTER(_c), ctypes.POINTER(ctypes.c_int64), _c,
+                              ctypes.c_size_t, _c]
+_lib.smash_sync.argtypes = [_c, _c]
 _lib.smash_get_stats.argtypes = [_c, ctypes.POINTER(Stats)]
 _lib.smash_kernel_count.argtypes = []
 _lib.smash_kernel_time.argtypes = [_c, ctypes.c_int, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_int64),
@@ -84,13 +90,14 @@ for _f in ("smash_features", "smash_mlp_predict", "smash_mlp_loss_grad", "smash_
            "smash_predictor_load"):
     getattr(_lib, _f).restype = ctypes.c_int
 for _f in ("smash_create", "smash_set_option", "smash_get_option", "smash_spgemm_symbolic", "smash_spgemm_numeric",
-           "smash_spgemm", "smash_get_stats", "smash_kernel_count", "smash_kernel_time", "smash_kernel_time_reset"):
+           "smash_spgemm", "smash_get_stats", "smash_kernel_count", "smash_kernel_time", "smash_kernel_time_reset",
+           "smash_workspace_size", "smash_sync"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
 class BatchConfig(ctypes.Structure):
     _fields_ = [("lds_row_max", ctypes.c_int32), ("table_shift", ctypes.c_int32), ("wide_groups", ctypes.c_int32),
-                ("blocks_per_cu", ctypes.c_int32)]
+                ("blocks_per_cu", ctypes.c_int32), ("row_hash", ctypes.c_int32)]
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}
@@ -179,6 +186,8 @@ class Context:
         self._h = h
         self.device = int(device)
         self._keep = []
+        self._ws = None            # workspace tensor grown on demand (uint8, device)
+        self._plan_ws = None       # the workspace of the last symbolic call
 
     def close(self):
         if getattr(self, "_h", None):
@@ -203,25 +212,80 @@ class Context:
         self._check(_lib.smash_get_option(self._h, int(opt), ctypes.byref(v)))
         return int(v.value)
 
-    def symbolic(self, A: DeviceCSR, B: DeviceCSR, C_row_ptr, stream=None) -> int:
+    # ------------------------------------------------------------ workspace
+    def workspace_size(self, A: DeviceCSR, B: DeviceCSR, stream=None) -> int:
+        """Bytes of workspace C = A * B needs (smash_workspace_size)."""
+        n = ctypes.c_size_t()
+        da, db = A.desc(), B.desc()
+        dt = _dtype_code(A.val) if A.val is not None else F32
+        self._check(_lib.smash_workspace_size(self._h, dt, ctypes.byref(da), ctypes.byref(db), ctypes.byref(n),
+                                              _stream_ptr(stream)))
+        return int(n.value)
+
+    def workspace(self, nbytes: int, device="cuda"):
+        """A torch uint8 device tensor of at least nbytes (the context's own,
+        grown on demand; a grown workspace replaces the old one)."""
+        import torch
+        nbytes = max(int(nbytes), 256)
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = None
+            self._ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        return self._ws
+
+    @staticmethod
+    def _ws_args(ws):
+        return (ws.data_ptr(), ws.numel()) if ws is not None and ws.numel() else (None, 0)
+
+    def _with_workspace(self, call, ws, device):
+        """Runs call(ws_ptr, ws_bytes); with ws None it uses the context's
+        workspace, grown to the size the library reports after CAPACITY."""
+        if ws is not None:
+            self._check(call(*self._ws_args(ws)))
+            return ws
+        cur = self._ws
+        for _ in range(3):
+            st = call(*self._ws_args(cur))
+            need = self.stats()["workspace_bytes"] if st == CAPACITY else 0
+            if st == CAPACITY and need > (cur.numel() if cur is not None else 0):
+                cur = self.workspace(need, device)
+                continue
+            self._check(st)
+            return cur
+        self._check(st)
+        return cur
+
+    def symbolic(self, A: DeviceCSR, B: DeviceCSR, C_row_ptr, stream=None, ws=None) -> int:
         nnz = ctypes.c_int64()
         da, db = A.desc(), B.desc()
-        self._check(_lib.smash_spgemm_symbolic(self._h, ctypes.byref(da), ctypes.byref(db), C_row_ptr.data_ptr(),
-                                               ctypes.byref(nnz), _stream_ptr(stream)))
+        self._plan_ws = self._with_workspace(
+            lambda wp, wb: _lib.smash_spgemm_symbolic(self._h, ctypes.byref(da), ctypes.byref(db),
+                                                      C_row_ptr.data_ptr(), ctypes.byref(nnz), wp, wb,
+                                                      _stream_ptr(stream)), ws, A.row_ptr.device)
         return int(nnz.value)
 
-    def numeric(self, A: DeviceCSR, B: DeviceCSR, C_row_ptr, C_col, C_val, stream=None):
+    def numeric(self, A: DeviceCSR, B: DeviceCSR, C_row_ptr, C_col, C_val, stream=None, ws=None, check=True):
+        """Numeric phase; with check (default) it then synchronises and
+        reports what the kernels found (smash_sync)."""
         da, db = A.desc(), B.desc()
+        wp, wb = self._ws_args(ws if ws is not None else self._plan_ws)
         self._check(_lib.smash_spgemm_numeric(self._h, _dtype_code(A.val), ctypes.byref(da), ctypes.byref(db),
                                               C_row_ptr.data_ptr(), C_col.data_ptr() if C_col.numel() else 0,
-                                              C_val.data_ptr() if C_val.numel() else 0, _stream_ptr(stream)))
+                                              C_val.data_ptr() if C_val.numel() else 0, wp, wb,
+                                              _stream_ptr(stream)))
+        if check:
+            self.sync(stream)
 
-    def spgemm_fused(self, A: DeviceCSR, B: DeviceCSR, stream=None, C_row_ptr=None) -> DeviceCSR:
+    def sync(self, stream=None):
+        """smash_sync: waits for the stream, raises what numeric calls found."""
+        self._check(_lib.smash_sync(self._h, _stream_ptr(stream)))
+
+    def spgemm_fused(self, A: DeviceCSR, B: DeviceCSR, stream=None, C_row_ptr=None, ws=None) -> DeviceCSR:
         """C = A * B through smash_spgemm_fused (needs an installed predictor)."""
-        return self.spgemm(A, B, stream, C_row_ptr, _fn=_lib.smash_spgemm_fused)
+        return self.spgemm(A, B, stream, C_row_ptr, ws=ws, _fn=_lib.smash_spgemm_fused)
 
-    def spgemm(self, A: DeviceCSR, B: DeviceCSR, stream=None, C_row_ptr=None, _fn=None) -> DeviceCSR:
-        """C = A * B through smash_spgemm; C's arrays come from torch."""
+    def spgemm(self, A: DeviceCSR, B: DeviceCSR, stream=None, C_row_ptr=None, ws=None, _fn=None) -> DeviceCSR:
+        """C = A * B through smash_spgemm; C's arrays and (with ws None) the
+        workspace come from torch."""
         import torch
         dev = A.row_ptr.device
         if C_row_ptr is None:
@@ -237,12 +301,20 @@ class Context:
         col_p, val_p, nnz = _c(), _c(), ctypes.c_int64()
         da, db = A.desc(), B.desc()
         fn = _fn or _lib.smash_spgemm
-        self._check(fn(self._h, _dtype_code(A.val), ctypes.byref(da), ctypes.byref(db), cb, None,
-                                      C_row_ptr.data_ptr(), ctypes.byref(col_p), ctypes.byref(val_p),
-                                      ctypes.byref(nnz), _stream_ptr(stream)))
+
+        def call(wp, wb):
+            held.clear()
+            return fn(self._h, _dtype_code(A.val), ctypes.byref(da), ctypes.byref(db), cb, None,
+                      C_row_ptr.data_ptr(), ctypes.byref(col_p), ctypes.byref(val_p), ctypes.byref(nnz), wp, wb,
+                      _stream_ptr(stream))
+
+        self._plan_ws = self._with_workspace(call, ws, dev)
         n = int(nnz.value)
-        col = held[0].view(torch.int32)[:n]
-        val = held[1].view(A.val.dtype)[:n]
+        # the output buffers are the last two allocations (a fused call first
+        # allocates its staging area)
+        col = held[-2].view(torch.int32)[:n]
+        val = held[-1].view(A.val.dtype)[:n]
+        self._keep = held[:-2]      # staging buffers stay alive until the next call
         return DeviceCSR(A.rows, B.cols, C_row_ptr, col, val)
 
     # ------------------------------------------------------------ predictor
@@ -346,9 +418,13 @@ class BatchPlan:
                                                  ctypes.byref(r0)))
         self.capacity, self.total_rows = int(cap.value), int(rows.value)
         self.row0 = np.array([r0[i] for i in range(self.count + 1)], dtype=np.int64)
-        self.C_row_ptr = self._held[0].view(torch.int64)[:self.total_rows + 1]
-        self.C_col = self._held[1].view(torch.int32)[:self.capacity]
-        self.C_val = self._held[2].view(dt)[:self.capacity]
+        crp, ccol, cval = _c(), _c(), _c()
+        ctx._check(_lib.smash_batch_plan_outputs(self._h, ctypes.byref(crp), ctypes.byref(ccol), ctypes.byref(cval),
+                                                 None, None, None))
+        by_ptr = {t.data_ptr(): t for t in self._held}
+        self.C_row_ptr = by_ptr[crp.value].view(torch.int64)[:self.total_rows + 1]
+        self.C_col = by_ptr[ccol.value].view(torch.int32)[:self.capacity]
+        self.C_val = by_ptr[cval.value].view(dt)[:self.capacity]
 
     def close(self):
         if getattr(self, "_h", None):

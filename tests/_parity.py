@@ -35,3 +35,29 @@ def check_rows(row_ptr, col, val, ref, dtype, where=""):
             f"{where}: single-term FP32 entries not bitwise"
     margin = float(np.max(err / np.where(ref["absmass"] > 0, ref["absmass"], 1.0))) if err.size else 0.0
     return margin
+
+
+def check_streaming(C, A, B, oracle_mod, dtype, where, chunk=1 << 27, log=print):
+    """Every entry of C (device tensors: row_ptr int64, col_idx, val) against
+    the oracle, in chunks of whole rows of about `chunk` entries: the
+    oracle computes the chunk's rows, the GPU's slice is copied back, and
+    check_rows compares them (row counts, columns, values).  Returns (the
+    largest |err| / absmass, entries compared)."""
+    rp = C.row_ptr.cpu().numpy()
+    assert rp[0] == 0, f"{where}: row_ptr[0] != 0"
+    m = A.rows
+    worst, done, r0 = 0.0, 0, 0
+    while r0 < m:
+        r1 = int(np.searchsorted(rp, rp[r0] + chunk, side="right")) - 1
+        r1 = min(max(r1, r0 + 1), m)
+        s, e = int(rp[r0]), int(rp[r1])
+        ref = oracle_mod.spgemm(A, B, rows=np.arange(r0, r1, dtype=np.int64))
+        col = C.col_idx[s:e].cpu().numpy()
+        val = C.val[s:e].cpu().numpy()
+        worst = max(worst, check_rows(rp[r0:r1 + 1], col, val, ref, dtype, f"{where} rows {r0}..{r1 - 1}"))
+        done += e - s
+        del ref, col, val
+        log(f"{where}: rows {r0}..{r1 - 1} ok ({done} entries so far, max err/absmass {worst:.2e})", flush=True)
+        r0 = r1
+    assert done == int(rp[m])
+    return worst, done

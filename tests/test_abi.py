@@ -28,7 +28,7 @@ def lib():
 def test_header_declares_boundary():
     fns = declared_functions()
     for required in ("smash_spgemm_symbolic", "smash_spgemm_numeric", "smash_spgemm", "smash_create",
-                     "smash_destroy", "smash_last_error"):
+                     "smash_destroy", "smash_last_error", "smash_workspace_size", "smash_sync"):
         assert required in fns
 
 
@@ -50,7 +50,9 @@ def test_null_arguments_rejected(lib):
     assert lib.smash_create(None, 0) == 1
     lib.smash_last_error.restype = ctypes.c_char_p
     assert lib.smash_last_error(None) == b"null context"
-    assert lib.smash_spgemm_symbolic(None, None, None, None, None, None) == 1
+    assert lib.smash_spgemm_symbolic(None, None, None, None, None, None, 0, None) == 1
+    assert lib.smash_workspace_size(None, 0, None, None, None, None) == 1
+    assert lib.smash_sync(None, None) == 1
 
 
 def test_binding_matches_header():
@@ -77,3 +79,8 @@ def test_binding_layouts_match_header():
         if k != "COUNT":
             assert getattr(smash, "OPT_" + k) == v, k
     assert opts["COUNT"] == len(opts) - 1
+
+
+def test_batch_config_layout_matches_header():
+    from paper_2105_14156_amd import smash
+    assert [n for n, _ in smash.BatchConfig._fields_] == _struct_fields("smash_batch_config")

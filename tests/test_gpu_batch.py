@@ -70,10 +70,11 @@ def test_batch_eager_and_graph(env, oracle_mod, dtype):
 
 
 @pytest.mark.parametrize("config", [
-    dict(lds_row_max=256, table_shift=2, wide_groups=1, blocks_per_cu=1),
-    dict(lds_row_max=512, table_shift=2, wide_groups=0, blocks_per_cu=32),
-    dict(lds_row_max=32, table_shift=1, wide_groups=1, blocks_per_cu=4),
-    dict(lds_row_max=1024, table_shift=1, wide_groups=1, blocks_per_cu=16),
+    dict(lds_row_max=256, table_shift=2, wide_groups=1, blocks_per_cu=1, row_hash=0),
+    dict(lds_row_max=512, table_shift=2, wide_groups=0, blocks_per_cu=32, row_hash=1),
+    dict(lds_row_max=32, table_shift=1, wide_groups=1, blocks_per_cu=4, row_hash=0),
+    dict(lds_row_max=1024, table_shift=1, wide_groups=1, blocks_per_cu=16, row_hash=1),
+    dict(lds_row_max=1024, table_shift=1, wide_groups=0, blocks_per_cu=8, row_hash=1),
 ])
 def test_batch_configs(env, oracle_mod, config):
     torch, smash, ctx = env

@@ -3,8 +3,9 @@
 Structure bit-exact, values within 1e-5 (FP32) / 1e-12 (FP64) of the sum of
 |a_ik b_kj| per entry, single-term entries bitwise (see tests/_parity.py).
 Workloads: RMAT scale 10 (edge factor 8) and scale 16 (edge factor 16) C = A.A,
-both heavy-row strategies, forced heavy rows, rectangular and structured
-edge cases.
+both heavy-row strategies, both row-table hashes, forced heavy rows,
+rectangular and structured edge cases, subnormal and cancelling sums on
+every accumulation path.
 """
 import numpy as np
 import pytest
@@ -313,4 +314,111 @@ def test_errors(sm, ctx, torch_mod):
     with pytest.raises(sm.SmashError):
         ctx.set_option(sm.OPT_GLOBAL_POOL, -1)
     with pytest.raises(sm.SmashError):
-        ctx.set_option(6, 0)
+        ctx.set_option(sm.OPT_ROW_HASH, 2)
+    with pytest.raises(sm.SmashError):
+        ctx.set_option(7, 0)
+
+
+def _subnormal_case(width, n, dtype=np.float64):
+    """One output row from two B rows over the same `width` columns: entry 7
+    sums to a negative subnormal (-1e-320 plus an exact zero), entry 9
+    cancels to +0.0, entry 11 adds the smallest subnormal twice."""
+    cols = np.arange(width, dtype=np.int32) * (n // width)
+    b0 = np.ones(width)
+    b1 = np.ones(width)
+    b0[7], b1[7] = -1e-320, 0.0
+    b0[9], b1[9] = 1.0, -1.0
+    b0[11], b1[11] = -5e-324, -5e-324
+    B = syn.CSR(2, n, np.array([0, width, 2 * width], np.int32), np.concatenate([cols, cols]),
+                np.concatenate([b0, b1]).astype(dtype))
+    A = syn.CSR(1, 2, np.array([0, 2], np.int32), np.array([0, 1], np.int32), np.array([1.0, 1.0], dtype))
+    return A, B
+
+
+@pytest.mark.parametrize("path", ["light", "light_ordered", "global", "segment"])
+def test_subnormal_and_cancelling_sums(sm, ctx, oracle_mod, path):
+    """FP64 sums that end subnormal or cancel keep their entries and values
+    on the light-row tables (both hashes), the global-memory tables (FP64
+    device atomics) and hashed heavy-row segments."""
+    if path.startswith("light"):
+        A, B = _subnormal_case(100, 1 << 16)
+        if path == "light_ordered":
+            ctx.set_option(sm.OPT_ROW_HASH, 1)
+    elif path == "global":
+        A, B = _subnormal_case(1500, 1 << 20)
+        ctx.set_option(sm.OPT_HEAVY_MODE, 1)
+    else:
+        A, B = _subnormal_case(1500, 1 << 20)          # 1500 columns over 128 chunks: hashed segments
+    rp, col, val = run(sm, ctx, A, B, np.float64)
+    st = ctx.stats()
+    if path.startswith("light"):
+        assert st["rows_lds"] == 1, st
+    elif path == "global":
+        assert st["global_slots"] > 0, st
+    else:
+        assert st["heavy_segments"] > 0 and st["heavy_dense_chunks"] == 0, st
+    ref = oracle_mod.spgemm(A, B)
+    assert val[7] == -1e-320 and val[9] == 0.0 and val[11] == -1e-323
+    check_rows(rp, col, val, ref, np.float64, f"subnormal {path}")
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_many_terms_one_column(sm, ctx, oracle_mod, mode):
+    """One output column collects 1.0 and 3000 terms of 2^-24 (FP32 inputs):
+    summed in FP32 in an order that adds 1.0 first, every small term would
+    round away (an error of 1.8e-4 of the column's absolute mass, above the
+    1e-5 tolerance); the FP64 accumulation of the LDS and global tables
+    keeps them.  The row also has 2000 other columns, so it is heavy."""
+    n_small = 3000
+    k = n_small + 1
+    rows_b = []
+    vals_b = []
+    for r in range(k):
+        c = [0] + ([1 + (r % 2000)] if r else list(range(1, 2001)))
+        rows_b.append(np.array(c, np.int32))
+        vals_b.append(np.array([1.0 if r == 0 else 2.0 ** -24] + [0.5] * (len(c) - 1)))
+    rp_b = np.zeros(k + 1, np.int32)
+    rp_b[1:] = np.cumsum([len(r) for r in rows_b])
+    B = syn.CSR(k, 1 << 20, rp_b, np.concatenate(rows_b), np.concatenate(vals_b).astype(np.float32))
+    A = syn.CSR(1, k, np.array([0, k], np.int32), np.arange(k, dtype=np.int32), np.ones(k, np.float32))
+    ctx.set_option(sm.OPT_HEAVY_MODE, mode)
+    rp, col, val = run(sm, ctx, A, B, np.float32)
+    assert ctx.stats()["rows_heavy"] == 1
+    ref = oracle_mod.spgemm(A, B)
+    assert ref["terms"][0] == k and col[0] == 0
+    check_rows(rp, col, val, ref, np.float32, f"many terms mode={mode}")
+    assert val[0] == np.float32(1.0 + n_small * 2.0 ** -24)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_order_preserving_row_hash(sm, ctx, oracle_mod, s16, dtype):
+    """The order-preserving row hash with the bounded insertion write-back
+    (SMASH_OPT_ROW_HASH = 1) gives the same C: RMAT scale 10 and 16, a
+    rectangular product, rows of every table size (LDS row limit lowered and
+    raised), identity and dense-row cases."""
+    ctx.set_option(sm.OPT_ROW_HASH, 1)
+    full_check(sm, ctx, syn.workload_small().A, None, dtype, oracle_mod, False, "s10 ordered")
+    full_check(sm, ctx, syn.workload_small().A, None, dtype, oracle_mod, True, "s10 ordered split")
+    full_check(sm, ctx, s16, None, dtype, oracle_mod, False, "s16 ordered")
+    A = syn.rmat(14, 8, 0x5EED0501, dtype)
+    full_check(sm, ctx, A, syn.uniform_k_per_row(A.cols, 4096, 16, 0xB, dtype), dtype, oracle_mod, False,
+               "rect ordered")
+    full_check(sm, ctx, syn.identity(2048), syn.rmat(11, 4, 3, np.float64), dtype, oracle_mod, False, "identity")
+    full_check(sm, ctx, syn.dense_rows(64, 64, [0, 5, 63], 10, np.float64),
+               syn.dense_rows(64, 900, range(64), 11, np.float64), dtype, oracle_mod, False, "dense rows ordered")
+    ctx.set_option(sm.OPT_LDS_ROW_MAX, 64)
+    full_check(sm, ctx, syn.rmat(12, 8, 5, dtype), None, dtype, oracle_mod, False, "small tables ordered")
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_global_touched_lists_across_windows(sm, ctx, oracle_mod, dtype):
+    """Global-mode heavy rows whose columns span three rank windows of 2^19
+    columns: the write-out walks each row's touched-slot list once per
+    window (every heavy row of RMAT scale 12 times 400 columns per row out
+    of 1.5M)."""
+    A = syn.rmat(12, 8, 0x44, dtype)
+    B = syn.uniform_k_per_row(A.cols, 1_500_000, 400, 0x45, dtype)
+    ctx.set_option(sm.OPT_HEAVY_MODE, 1)
+    full_check(sm, ctx, A, B, dtype, oracle_mod, False, "global, 3 windows")
+    st = ctx.stats()
+    assert st["rows_heavy"] > 100 and st["global_slots"] > 0
