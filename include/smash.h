@@ -221,6 +221,27 @@ smash_status smash_spgemm(smash_ctx ctx, smash_dtype dtype, const smash_csr *A, 
                           int32_t **C_col_idx, void **C_val, int64_t *C_nnz, void *ws, size_t ws_bytes,
                           hipStream_t stream);
 
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): smash_spgemm with neither a workspace
+ * nor an allocation callback.  The workspace is a 64 MiB device array of the
+ * library (SMASH_NOALLOC_SCRATCH_BYTES, one per GPU, held until the process
+ * ends); C goes to the caller's buffers: C_row_ptr (A.rows + 1 int64),
+ * C_col_idx and C_val (C_capacity entries each, C_val of dtype).  The call
+ * allocates no device memory (with SMASH_OPT_TIMING off: timing events
+ * aside) and synchronises the stream once, like smash_spgemm.  *C_nnz
+ * receives nnz(C), also when it exceeds C_capacity (then CAPACITY, and
+ * nothing is written to C_col_idx / C_val).  Errors: CAPACITY (C_capacity too
+ * small, or the product needs more workspace than the array holds:
+ * smash_get_stats().workspace_bytes then says how much), INVALID_ARG (also
+ * for SMASH_OPT_HEAVY_MODE = 1, which is not supported here), INVALID_CSR,
+ * HIP.  Every call on one GPU uses the same array: calls that overlap on one
+ * GPU (from several contexts or streams) race and must be serialised by the
+ * caller; each call initialises the parts of the array it reads. */
+#define SMASH_NOALLOC_SCRATCH_BYTES (64ull << 20)
+smash_status smash_spgemm_noalloc(smash_ctx ctx, smash_dtype dtype, const smash_csr *A, const smash_csr *B,
+                                  int64_t *C_row_ptr, int32_t *C_col_idx, void *C_val, int64_t C_capacity,
+                                  int64_t *C_nnz, hipStream_t stream);
+
 /* Waits for `stream` and reports what the numeric calls enqueued on ctx
  * since the last report found wrong on the device (CAPACITY: a C_row_ptr
  * inconsistent with the product); clears it.  Errors: CAPACITY, HIP. */

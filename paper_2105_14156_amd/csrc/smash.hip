@@ -29,11 +29,28 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
 
 using namespace smash;
+
+// Workspace of smash_spgemm_noalloc: a file-scope device array (each GPU the
+// library runs on holds its own copy until the process ends).  In host code
+// `scratch` names a host-side stand-in, not device memory: its device address
+// is resolved once per device with hipGetSymbolAddress (in smash_create, with
+// the device current) and only that address is ever passed to kernels.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+}  // namespace
 
 namespace {
 
@@ -152,6 +169,7 @@ struct smash_ctx_s {
     int64_t launches[K_COUNT] = {};
     double ms[K_COUNT] = {};
     int cus = 256;                 // compute units of the device
+    void *scratch = nullptr;       // device address of `scratch` on this context's device
 };
 
 namespace {
@@ -715,6 +733,23 @@ smash_status smash_create(smash_ctx *out, int device)
     }
     memset(c->h_hdr, 0, sizeof(DevHdr));
     *c->h_numerr = 0;
+    if (device < kMaxDevices) {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (!g_scratch_ptr[device]) {
+            void *ptr = nullptr;
+            if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+                (void)hipGetLastError();
+                (void)hipFree(c->d_hdr);
+                (void)hipFree(c->d_numerr);
+                (void)hipHostFree(c->h_hdr);
+                (void)hipHostFree(c->h_numerr);
+                delete c;
+                return SMASH_ERR_HIP;
+            }
+            g_scratch_ptr[device] = ptr;
+        }
+        c->scratch = g_scratch_ptr[device];
+    }
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
         c->cus = cus;
@@ -1164,6 +1199,33 @@ smash_status smash_spgemm(smash_ctx c, smash_dtype dtype, const smash_csr *A, co
     *C_val = val;
     *C_nnz = nnz;
     return smash_spgemm_numeric(c, dtype, A, B, C_row_ptr, (int32_t *)col, val, ws, ws_bytes, s);
+}
+
+smash_status smash_spgemm_noalloc(smash_ctx c, smash_dtype dtype, const smash_csr *A, const smash_csr *B,
+                                  int64_t *C_row_ptr, int32_t *C_col_idx, void *C_val, int64_t C_capacity,
+                                  int64_t *C_nnz, hipStream_t s)
+{
+    if (!c) return SMASH_ERR_INVALID_ARG;
+    c->err.clear();
+    if (!C_nnz || C_capacity < 0) return fail(c, SMASH_ERR_INVALID_ARG, "C_nnz is NULL or C_capacity < 0");
+    if (dtype != SMASH_F32 && dtype != SMASH_F64) return fail(c, SMASH_ERR_INVALID_ARG, "unknown dtype %d", (int)dtype);
+    if (c->opt[SMASH_OPT_HEAVY_MODE] != 0)
+        return fail(c, SMASH_ERR_INVALID_ARG, "the no-allocation entry point runs the LDS heavy-row mode only");
+    if (!c->scratch) return fail(c, SMASH_ERR_HIP, "no scratch array on device %d", c->device);
+    int64_t nnz = 0;
+    const smash_status st = symbolic_impl(c, A, B, C_row_ptr, &nnz, c->scratch, kScratchBytes, s, -1, nullptr,
+                                          nullptr);
+    if (st == SMASH_ERR_CAPACITY)
+        return fail(c, SMASH_ERR_CAPACITY, "the product needs %lld bytes of workspace; the no-allocation entry "
+                    "point has %zu", (long long)c->stats.workspace_bytes, kScratchBytes);
+    if (st != SMASH_OK) return st;
+    *C_nnz = nnz;
+    if (nnz > C_capacity) {
+        c->plan.valid = false;
+        return fail(c, SMASH_ERR_CAPACITY, "C has %lld entries; the output buffers hold %lld", (long long)nnz,
+                    (long long)C_capacity);
+    }
+    return numeric_checked(c, dtype, A, B, C_row_ptr, C_col_idx, C_val, c->scratch, s);
 }
 
 smash_status smash_sync(smash_ctx c, hipStream_t s)

@@ -72,6 +72,9 @@ _lib.smash_spgemm.argtypes = [_c, ctypes.c_int, ctypes.POINTER(CsrDesc), ctypes.
                               ctypes.POINTER(_c), ctypes.POINTER(_c), ctypes.POINTER(ctypes.c_int64), _c,
                               ctypes.c_size_t, _c]
 _lib.smash_sync.argtypes = [_c, _c]
+_lib.smash_spgemm_noalloc.argtypes = [_c, ctypes.c_int, ctypes.POINTER(CsrDesc), ctypes.POINTER(CsrDesc), _c, _c, _c,
+                                      ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), _c]
+NOALLOC_SCRATCH_BYTES = 64 << 20
 _lib.smash_get_stats.argtypes = [_c, ctypes.POINTER(Stats)]
 _lib.smash_kernel_count.argtypes = []
 _lib.smash_kernel_time.argtypes = [_c, ctypes.c_int, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_int64),
@@ -91,7 +94,7 @@ for _f in ("smash_features", "smash_mlp_predict", "smash_mlp_loss_grad", "smash_
     getattr(_lib, _f).restype = ctypes.c_int
 for _f in ("smash_create", "smash_set_option", "smash_get_option", "smash_spgemm_symbolic", "smash_spgemm_numeric",
            "smash_spgemm", "smash_get_stats", "smash_kernel_count", "smash_kernel_time", "smash_kernel_time_reset",
-           "smash_workspace_size", "smash_sync"):
+           "smash_workspace_size", "smash_sync", "smash_spgemm_noalloc"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -274,6 +277,21 @@ class Context:
                                               _stream_ptr(stream)))
         if check:
             self.sync(stream)
+
+    def spgemm_noalloc(self, A: DeviceCSR, B: DeviceCSR, C_row_ptr, C_col, C_val, stream=None) -> int:
+        """smash_spgemm_noalloc into caller buffers (capacity C_col.numel());
+        returns nnz(C).  On CAPACITY the raised SmashError carries .nnz."""
+        nnz = ctypes.c_int64(-1)
+        da, db = A.desc(), B.desc()
+        st = _lib.smash_spgemm_noalloc(self._h, _dtype_code(A.val), ctypes.byref(da), ctypes.byref(db),
+                                       C_row_ptr.data_ptr(), C_col.data_ptr() if C_col.numel() else 0,
+                                       C_val.data_ptr() if C_val.numel() else 0, min(C_col.numel(), C_val.numel()),
+                                       ctypes.byref(nnz), _stream_ptr(stream))
+        if st != OK:
+            err = SmashError(st, _lib.smash_last_error(self._h).decode())
+            err.nnz = int(nnz.value)
+            raise err
+        return int(nnz.value)
 
     def sync(self, stream=None):
         """smash_sync: waits for the stream, raises what numeric calls found."""
