@@ -135,16 +135,50 @@ __device__ __forceinline__ void group_sync()
     else __syncthreads();
 }
 
+// DPP controls of GFX9 (CDNA) used by the int scans below: shifts within
+// rows of 16 lanes, broadcasts of lanes 15 and 31 to the following rows,
+// and a whole-wave shift by one lane.
+constexpr int kDppRowShr = 0x110;
+constexpr int kDppBcast15 = 0x142;
+constexpr int kDppBcast31 = 0x143;
+constexpr int kDppWaveShr1 = 0x138;
+
+// Inclusive scan over the 64 lanes of a wave with operator `op` and its
+// identity `id`, in DPP moves (no LDS crossbar round trips): Hillis-Steele
+// within each row of 16 lanes, then row 0's total into row 1 and row 2's
+// into row 3, then rows 0-1's total into rows 2-3.
+template <typename Op>
+__device__ __forceinline__ int wave_scan_dpp(int v, int id, Op op)
+{
+    v = op(v, __builtin_amdgcn_update_dpp(id, v, kDppRowShr | 1, 0xf, 0xf, false));
+    v = op(v, __builtin_amdgcn_update_dpp(id, v, kDppRowShr | 2, 0xf, 0xf, false));
+    v = op(v, __builtin_amdgcn_update_dpp(id, v, kDppRowShr | 4, 0xf, 0xf, false));
+    v = op(v, __builtin_amdgcn_update_dpp(id, v, kDppRowShr | 8, 0xf, 0xf, false));
+    v = op(v, __builtin_amdgcn_update_dpp(id, v, kDppBcast15, 0xa, 0xf, false));
+    v = op(v, __builtin_amdgcn_update_dpp(id, v, kDppBcast31, 0xc, 0xf, false));
+    return v;
+}
+
+// The value of the lane below (lane 0 gets `id`).
+__device__ __forceinline__ int wave_shift_up1(int v, int id)
+{
+    return __builtin_amdgcn_update_dpp(id, v, kDppWaveShr1, 0xf, 0xf, false);
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_incl_scan(T v)
 {
-    const int lane = lane_id();
+    if constexpr (sizeof(T) == 4) {
+        return (T)wave_scan_dpp((int)v, 0, [](int a, int b) { return a + b; });
+    } else {
+        const int lane = lane_id();
 #pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        T t = __shfl_up(v, d, kWave);
-        if (lane >= d) v += t;
+        for (int d = 1; d < kWave; d <<= 1) {
+            T t = __shfl_up(v, d, kWave);
+            if (lane >= d) v += t;
+        }
+        return v;
     }
-    return v;
 }
 
 template <typename T>
@@ -396,19 +430,29 @@ __device__ __forceinline__ void group_products(int e0, int e1, int gt, EnumScrat
         // consecutive B entries where a range continues); with PIPELINE the
         // next round is located while this round's loads are in flight
         auto locate_flat = [&](int q0, int (&pos)[U], double (&av)[U]) {
+            // the U searches advance step by step together, so that their
+            // LDS reads are in flight at once
+            int src[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) src[u] = 0;
+#pragma unroll
+            for (int step = G / 2; step > 0; step >>= 1) {
+                int t[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) t[u] = S.sincl[src[u] + step - 1];
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (t[u] <= q0 + u * G + gt) src[u] += step;
+            }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int q = q0 + u * G + gt;
                 pos[u] = -1;
                 av[u] = 0.0;
                 if (q < stot) {
-                    int src = 0;
-#pragma unroll
-                    for (int step = G / 2; step > 0; step >>= 1)
-                        if (S.sincl[src + step - 1] <= q) src += step;
-                    const int excl = src ? S.sincl[src - 1] : 0;
-                    pos[u] = S.bs[src] + (q - excl);
-                    if constexpr (WITH_VAL) av[u] = (double)S.a[src];
+                    const int excl = src[u] ? S.sincl[src[u] - 1] : 0;
+                    pos[u] = S.bs[src[u]] + (q - excl);
+                    if constexpr (WITH_VAL) av[u] = (double)S.a[src[u]];
                 }
             }
         };
