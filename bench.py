@@ -25,6 +25,7 @@ if ROOT not in sys.path:
 import synthetic  # noqa: E402
 from paper_2105_14156_amd import metrics  # noqa: E402
 
+_NATIVE_ORACLE = None
 METRIC = "SpGEMM GFLOP/s (2·products/s) + HBM GB/s; learned/batched vs plain at exact C"
 HBM_PEAK_GBS = 8000.0
 
@@ -134,8 +135,12 @@ def log(msg):
 
 def cpu_baseline(A, B, target_s, threads=None):
     """The oracle timed on a seeded row sample of the same product (all host
-    threads up to 16, or `threads`), scaled to GFLOP/s of 2 x products."""
+    threads up to 16, or `threads`), scaled to GFLOP/s of 2 x products.  The
+    oracle is compiled for this host (gcc -O3 -march=native) first."""
     import oracle
+    global _NATIVE_ORACLE
+    if _NATIVE_ORACLE is None:
+        _NATIVE_ORACLE = oracle.use_native_build()
     ub = oracle.products_per_row(A, B)
     if threads is None:
         threads = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity")
@@ -159,7 +164,7 @@ def cpu_baseline(A, B, target_s, threads=None):
     return {"value": round(2.0 * prods / t / 1e9, 4), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
             "sample": f"{n_rows} seeded random rows of {A.rows} ({prods} of {total} products, "
                       f"{prods / total:.1%}), {t:.1f} s wall",
-            "cpu": cpu_model()}
+            "cpu": cpu_model(), "build": "gcc -O3 -march=native"}
 
 
 def cpu_model() -> str:

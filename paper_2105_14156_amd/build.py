@@ -8,9 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libsmash.so")
-SOURCES = [os.path.join(HERE, "csrc", "smash.hip")]
-DEPS = SOURCES + [os.path.join(HERE, "csrc", h) for h in ("smash_kernels.hpp", "smash_mlp.hpp", "smash_fused.hpp")] \
-    + [os.path.join(ROOT, "include", "smash.h")]
+SOURCES = [os.path.join(HERE, "csrc", "smash.hip")]     # includes every csrc/*.hpp and include/smash.h
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -35,13 +33,6 @@ def build(verbose: bool = False) -> str:
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     return LIB
-
-
-def stale() -> bool:
-    if not os.path.exists(LIB):
-        return True
-    t = os.path.getmtime(LIB)
-    return any(os.path.getmtime(d) > t for d in DEPS)
 
 
 if __name__ == "__main__":
