@@ -182,6 +182,47 @@ def products_of(A, B) -> int:
     return int(np.diff(B.row_ptr).astype(np.int64)[A.col_idx].sum()) if A.nnz else 0
 
 
+def run_fused_compare(key: str, npdt, steps: int, warmup: int):
+    """Plain two-phase against the fused pass (learned and exact upper-bound
+    capacities) on another workload, each in its own workspace-sized loop."""
+    import torch
+    from paper_2105_14156_amd import smash
+    name, make, _ = WORKLOADS[key]
+    w = make(npdt)
+    dA = smash.to_device(w.A)
+    dB = dA if w.B is w.A else smash.to_device(w.B)
+    ctx = smash.Context(0)
+    ctx.predictor_load()
+    ws = ctx.workspace(ctx.workspace_size(dA, dB))
+
+    def timed(fn):
+        C = None
+        for _ in range(max(1, warmup)):
+            C = None
+            C = fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            C = None
+            C = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps * 1e3, ctx.stats()
+
+    plain_ms, _ = timed(lambda: ctx.spgemm(dA, dB, ws=ws))
+    res = {"workload": name, "plain_ms_per_step": round(plain_ms, 4)}
+    for sizing, label in ((0, "learned"), (1, "upper_bound")):
+        ctx.set_option(smash.OPT_FUSED_SIZING, sizing)
+        f_ms, st = timed(lambda: ctx.spgemm_fused(dA, dB, ws=ws))
+        res[label] = {"ms_per_step": round(f_ms, 4), "fused_rows": st["fused_rows"],
+                      "overflow_rows": st["fused_overflow"], "rows_heavy": st["rows_heavy"]}
+    res["fused_speedup_vs_plain"] = round(plain_ms / res["learned"]["ms_per_step"], 4)
+    res["network_speedup_vs_upper_bound"] = round(res["upper_bound"]["ms_per_step"] / res["learned"]["ms_per_step"], 4)
+    ctx.close()
+    log(f"{name}: plain {plain_ms:.3f} ms, fused learned {res['learned']['ms_per_step']:.3f}, "
+        f"upper bound {res['upper_bound']['ms_per_step']:.3f}")
+    return res
+
+
 def run_batch(count: int, steps: int, warmup: int, plain_loops: int = 2):
     """The batched workload: `count` products in one captured graph (after
     autotuning the plan), against a loop of plain smash_spgemm calls over the
@@ -407,6 +448,7 @@ def main():
             ms_plain = ms_step
         else:
             ms_plain, _ = timed(lambda: ctx.spgemm(dA, dB, stream, ws=ws))
+        rect = run_fused_compare("rect", npdt, args.steps, args.warmup) if args.workload != "rect" else None
         b = run_batch(args.batch_count, args.steps, args.warmup)
         out["variants"] = {
             "plain_ms_per_step": round(ms_plain, 4),
@@ -415,6 +457,7 @@ def main():
             "network_speedup_vs_upper_bound": round(fused["upper_bound"]["ms_per_step"]
                                                     / fused["learned"]["ms_per_step"], 4),
             "predictor": predictor_report(ctx, smash, dA, dB, counts, fused),
+            "rect": rect,
             "batch": {"workload": f"batch{b['count']}_rmat_x_uniform8", "graph_ms": round(b["graph_ms"], 4),
                       "plain_loop_ms": round(b["plain_loop_ms"], 3),
                       "speedup_vs_plain_loop": round(b["plain_loop_ms"] / b["graph_ms"], 2),

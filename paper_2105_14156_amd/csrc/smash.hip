@@ -646,7 +646,8 @@ smash_status fused_stage(smash_ctx c, hipStream_t s, Plan &p, smash_alloc_fn all
     if (learned) {      // the features came with the analysis
         TRY(launch(c, K_MLP_PREDICT, s, [&] {
             k_mlp_predict<<<blocks_for(m, 256), 256, 0, s>>>(m, (int)p.n, p.feats, prm, prm + kParams,
-                                                             c->pred_delta, p.ub, p.maxb, nullptr, p.cap_pred);
+                                                             c->pred_delta, p.ub, p.maxb, nullptr, p.cap_pred,
+                                                             p.lds_row_max);
         }));
     }
     TRY(launch(c, K_FUSED_AUX, s, [&] {
@@ -1272,7 +1273,7 @@ smash_status smash_mlp_predict(smash_ctx c, int64_t m, const float *feats, const
     DeviceGuard g(c->device);
     TRY(launch(c, K_MLP_PREDICT, s, [&] {
         k_mlp_predict<<<blocks_for(m, 256), 256, 0, s>>>((int)m, 0, feats, params, ms, 0.f, nullptr, nullptr, yhat,
-                                                         nullptr);
+                                                         nullptr, -1);
     }));
     return SMASH_OK;
 }

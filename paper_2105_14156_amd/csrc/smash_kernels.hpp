@@ -686,7 +686,9 @@ __device__ __forceinline__ float row_feature(int t, int na, long long ub, double
 // Row analysis (step a1): products ub_i = sum_k nnz(B_k) over row i of A, the
 // output bound cap_i = min(ub_i, cols) and the row's symbolic bin.  One wave
 // per row, four rows per block.  With feats non-NULL it also writes the
-// learned predictor's six features and max_k nnz(B_k) (maxb_out).
+// learned predictor's six features and max_k nnz(B_k) (maxb_out) of the rows
+// whose bound exceeds the LDS row limit, the only rows the predictor is
+// asked about.
 __global__ __launch_bounds__(256) void k_analyze(int m, int ncols, int lds_row_max,
                                                  const int *__restrict__ Arp, const int *__restrict__ Acol,
                                                  const int *__restrict__ Brp, long long *__restrict__ ub_out,
@@ -712,7 +714,7 @@ __global__ __launch_bounds__(256) void k_analyze(int m, int ncols, int lds_row_m
         }
     }
     ub = wave_sum(ub);
-    if (feats) {
+    if (feats && (ub < ncols ? ub : ncols) > lds_row_max) {
         // the predictor's six features (the same arithmetic as k_features)
         sq = wave_sum(sq);
 #pragma unroll

@@ -100,20 +100,36 @@ __device__ __forceinline__ float mlp_eval(const float *s_w, const float x[kFeat]
 
 // Inference (one thread per row): predicted log2(1 + nnz) and, when cap is
 // given, the capacity clamp(ceil(2^(yhat + delta) - 1), max(maxb, 1),
-// min(ub, cols)) (0 for rows without products).
+// min(ub, cols)) (0 for rows without products).  With only_above >= 0 the
+// network is evaluated only for rows whose exact bound min(ub, cols)
+// exceeds it (the rows a prediction can move into the LDS tables); the
+// others get the bound itself, and a block without such rows loads no
+// weights.
 __global__ __launch_bounds__(256) void k_mlp_predict(int m, int ncols, const float *__restrict__ feats,
                                                      const float *__restrict__ theta, const float *__restrict__ ms,
                                                      float delta, const long long *__restrict__ ub,
                                                      const int *__restrict__ maxb, float *__restrict__ yhat_out,
-                                                     int *__restrict__ cap_out)
+                                                     int *__restrict__ cap_out, int only_above)
 {
     __shared__ float s_w[kParams];
     __shared__ float s_ms[2 * kFeat];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = i < m;
+    const long long ub_i = live && ub ? ub[i] : 0;
+    const long long bound = ub_i < ncols ? ub_i : ncols;
+    const bool cand = live && (only_above < 0 || bound > only_above);
+    if (!__syncthreads_or(cand)) {
+        if (live && cap_out) cap_out[i] = (int)bound;
+        return;
+    }
     load_params(s_w, theta);
     if (threadIdx.x < 2 * kFeat) s_ms[threadIdx.x] = ms[threadIdx.x];
     __syncthreads();
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m) return;
+    if (!live) return;
+    if (!cand) {
+        if (cap_out) cap_out[i] = (int)bound;
+        return;
+    }
     float x[kFeat];
 #pragma unroll
     for (int f = 0; f < kFeat; ++f) x[f] = (feats[(long long)i * kFeat + f] - s_ms[f]) / s_ms[kFeat + f];

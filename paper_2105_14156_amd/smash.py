@@ -379,7 +379,7 @@ class Context:
 
     def predictor_load(self, path: str = None):
         """Installs a predictor file (default: the weights shipped with the package)."""
-        path = path or os.path.join(HERE, "data", "predictor_v1.bin")
+        path = path or os.path.join(HERE, "data", "predictor_v2.bin")
         self._check(_lib.smash_predictor_load(self._h, os.fsencode(path)))
 
     def stats(self) -> dict:
