@@ -483,6 +483,187 @@ __device__ __forceinline__ void group_products(int e0, int e1, int gt, EnumScrat
     }
 }
 
+// --------------------------------------------- product enumeration by runs
+//
+// run_products enumerates the same products as group_products with fewer
+// instructions per product: locating a product's A entry (a search in LDS)
+// is shared by 64 products of a wave (a full piece of a long range) or by
+// the kRun consecutive products of one lane (a run of a short range), never
+// done once per product.  Every B range is split into full pieces of 64
+// products and a tail of fewer than 64; entries with full pieces form the
+// long list, entries with a tail the short list (an entry can be in both),
+// each compacted in LDS with the inclusive prefix of its piece (or run)
+// counts.  Long phase: each wave locates 64 of its pieces at once, one per
+// lane (a binary search over the long list, O(log n) reads per lane), keeps
+// their starts in registers and then takes U pieces per step: the start of
+// piece u is read across lanes (v_readlane) and lane l loads product
+// start + l, coalesced.  Short phase: thread gt takes runs q = gt, gt + G,
+// ... (RU per step), finds each run's entry by binary search over the short
+// list and loads its kRun consecutive products.  Pieces are dealt to the
+// waves U at a time in turn, so short rows still spread over the group.
+constexpr int kRun = 4;
+
+template <typename V, int GE, int G = GE>
+struct RunScratch {
+    int lincl[GE];  // long list: inclusive prefix of the full-piece counts
+    int lbs[GE];    //   B range start
+    V la[GE];       //   A value
+    int sincl[GE];  // short list: inclusive prefix of the tail-run counts
+    int sbs[GE];    //   start of the tail
+    int sbe[GE];    //   end of the B range
+    V sa[GE];       //   A value
+    int wsum[3 * (G / kWave)];
+};
+
+// Number of entries of the strictly increasing incl[0, n) that are <= x,
+// i.e. the first index whose prefix exceeds x (n is group-uniform).
+__device__ __forceinline__ int prefix_rank(const int *incl, int n, int x)
+{
+    int lo = 0;
+    for (int s = n > 0 ? 1 << (31 - __clz(n)) : 0; s > 0; s >>= 1)
+        if (lo + s <= n && incl[lo + s - 1] <= x) lo += s;
+    return lo;
+}
+
+__device__ __forceinline__ double readlane_d(double v, int lane)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// GE (a multiple of 64, at most G) is the number of A entries taken per step;
+// a group with more threads than entries per step keeps the LDS lists small
+// while all G threads share the products.
+template <typename V, bool WITH_VAL, int GE, int G, int U, int RU, int RUN, typename Get, typename Sink,
+          bool ARRAY_SINK = false>
+__device__ __forceinline__ void run_products(int e0, int e1, int gt, RunScratch<V, GE, G> &S,
+                                             const int *__restrict__ Bcol, const V *__restrict__ Bval, Get get,
+                                             Sink sink)
+{
+    constexpr int WG = G / kWave;
+    static_assert(kWave % U == 0, "U must divide the wave");
+    static_assert(GE % kWave == 0 && GE <= G, "entry step");
+    const int lane = lane_id(), wg = gt / kWave;
+    for (int base = e0; base < e1; base += GE) {
+        const int e = base + gt;
+        int bs = 0, bl = 0;
+        V a = V(0);
+        if (gt < GE && e < e1) get(e, bs, bl, a);
+        const int np = bl >> 6;                          // full pieces
+        const int tail = bl & (kWave - 1);
+        const int nr = (tail + RUN - 1) / RUN;           // runs of the tail
+        const int isl = np > 0, iss = tail > 0;
+        int ip = wave_incl_scan(np);
+        int ic = wave_incl_scan(isl | (iss << 16));
+        int ir = wave_incl_scan(nr);
+        int P, RT, NC;
+        if constexpr (WG > 1) {
+            if (lane == kWave - 1) {
+                S.wsum[wg] = ip;
+                S.wsum[WG + wg] = ic;
+                S.wsum[2 * WG + wg] = ir;
+            }
+            group_sync<WG>();
+            int ap = 0, ac = 0, ar = 0;
+            P = 0, NC = 0, RT = 0;
+            for (int w = 0; w < WG; ++w) {
+                const int tp = S.wsum[w], tc = S.wsum[WG + w], tr = S.wsum[2 * WG + w];
+                if (w < wg) { ap += tp; ac += tc; ar += tr; }
+                P += tp;
+                NC += tc;
+                RT += tr;
+            }
+            ip += ap;
+            ic += ac;
+            ir += ar;
+        } else {
+            P = __builtin_amdgcn_readlane(ip, kWave - 1);
+            NC = __builtin_amdgcn_readlane(ic, kWave - 1);
+            RT = __builtin_amdgcn_readlane(ir, kWave - 1);
+        }
+        const int NL = NC & 0xffff, NS = NC >> 16;
+        if (isl) {
+            const int li = (ic & 0xffff) - 1;
+            S.lincl[li] = ip;
+            S.lbs[li] = bs;
+            if constexpr (WITH_VAL) S.la[li] = a;
+        }
+        if (iss) {
+            const int si = (ic >> 16) - 1;
+            S.sincl[si] = ir;
+            S.sbs[si] = bs + (np << 6);
+            S.sbe[si] = bs + bl;
+            if constexpr (WITH_VAL) S.sa[si] = a;
+        }
+        group_sync<WG>();
+        // long phase: wave wg owns pieces (k * WG + wg) * U + u, k = 0, 1, ...
+        for (int k0 = 0; (k0 * WG + wg) * U < P; k0 += kWave / U) {
+            const int pc = ((k0 + lane / U) * WG + wg) * U + lane % U;
+            int st = -1;
+            double al = 0.0;
+            if (pc < P) {
+                const int li = prefix_rank(S.lincl, NL, pc);
+                const int ex = li ? S.lincl[li - 1] : 0;
+                st = S.lbs[li] + ((pc - ex) << 6);
+                if constexpr (WITH_VAL) al = (double)S.la[li];
+            }
+            for (int g = 0; g < kWave / U && ((k0 + g) * WG + wg) * U < P; ++g) {
+                int pos[U], j[U];
+                double av[U], bv[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int s = __builtin_amdgcn_readlane(st, g * U + u);
+                    pos[u] = s >= 0 ? s + lane : -1;
+                    if constexpr (WITH_VAL) av[u] = readlane_d(al, g * U + u);
+                    else av[u] = 0.0;
+                }
+                load_products<V, WITH_VAL, U>(Bcol, Bval, pos, j, bv);
+                emit_products<WITH_VAL, U, ARRAY_SINK>(sink, pos, j, av, bv);
+            }
+        }
+        // short phase: runs of kRun consecutive products of the tails
+        for (int q0 = 0; q0 < RT; q0 += G * RU) {
+            int src[RU];
+#pragma unroll
+            for (int r = 0; r < RU; ++r) src[r] = 0;
+            // the RU searches advance together (their LDS reads overlap)
+            for (int s = NS > 0 ? 1 << (31 - __clz(NS)) : 0; s > 0; s >>= 1) {
+                int t[RU];
+#pragma unroll
+                for (int r = 0; r < RU; ++r) t[r] = src[r] + s <= NS ? S.sincl[src[r] + s - 1] : 0x7fffffff;
+#pragma unroll
+                for (int r = 0; r < RU; ++r)
+                    if (t[r] <= q0 + r * G + gt) src[r] += s;
+            }
+            constexpr int N = RU * RUN;
+            int pos[N], j[N];
+            double av[N], bv[N];
+#pragma unroll
+            for (int r = 0; r < RU; ++r) {
+                const int q = q0 + r * G + gt;
+                int st = 0, en = 0;
+                double ar = 0.0;
+                if (q < RT) {
+                    const int ex = src[r] ? S.sincl[src[r] - 1] : 0;
+                    st = S.sbs[src[r]] + (q - ex) * RUN;
+                    en = S.sbe[src[r]];
+                    if constexpr (WITH_VAL) ar = (double)S.sa[src[r]];
+                }
+#pragma unroll
+                for (int i = 0; i < RUN; ++i) {
+                    pos[r * RUN + i] = st + i < en ? st + i : -1;
+                    av[r * RUN + i] = ar;
+                }
+            }
+            load_products<V, WITH_VAL, N>(Bcol, Bval, pos, j, bv);
+            emit_products<WITH_VAL, N, ARRAY_SINK>(sink, pos, j, av, bv);
+        }
+        group_sync<WG>();
+    }
+}
+
 // ------------------------------------------------------------ LDS hashing
 
 // Claims the slot of `key` in an LDS key table, probing from slot h; returns
@@ -1002,26 +1183,30 @@ __device__ __forceinline__ void order_row_entries(const int (&kr)[SPT], const do
     const int lane = lane_id(), wg = gt / kWave;
     group_sync<WPR>();
     if (ncols <= 64 * T) {
-        // bitmap over B's columns in the value area (2T words), prefix of its
-        // popcounts per group of 8 words in the key area; then every entry's
-        // rank, and the entries staged in rank order for coalesced stores
+        // bitmap over B's columns in the value area (2T words), the prefix
+        // of its popcounts per word (16-bit) in the key area; then every
+        // entry's rank from two reads, and the entries staged in rank order
+        // for coalesced stores.  Each thread takes 16 words per step.
         unsigned *bm = reinterpret_cast<unsigned *>(vals);
-        int *pref = keys;
-        const int W = (ncols + 31) >> 5;
-        const int NGR = (W + 7) >> 3;
-        for (int t = gt; t < NGR * 8; t += G) bm[t] = 0u;
+        unsigned *pw = reinterpret_cast<unsigned *>(keys);
+        const unsigned short *pref = reinterpret_cast<const unsigned short *>(keys);
+        const int W16 = (((ncols + 31) >> 5) + 15) & ~15;     // at most 2T
+        for (int t = gt; t < W16; t += G) bm[t] = 0u;
         group_sync<WPR>();
 #pragma unroll
         for (int s = 0; s < SPT; ++s)
             if (kr[s] != kEmpty) atomicOr(&bm[(kr[s] - lo) >> 5], 1u << ((kr[s] - lo) & 31));
         group_sync<WPR>();
         int run = 0;
-        for (int g0 = 0; g0 < NGR; g0 += G) {
-            const int gi = g0 + gt;
+        for (int g0 = 0; g0 < W16; g0 += 16 * G) {
+            const int w0 = g0 + gt * 16;
+            int c[16];
             int pc = 0;
-            if (gi < NGR)
 #pragma unroll
-                for (int q = 0; q < 8; ++q) pc += __popc(bm[gi * 8 + q]);
+            for (int q = 0; q < 16; ++q) {
+                c[q] = w0 < W16 ? __popc(bm[w0 + q]) : 0;
+                pc += c[q];
+            }
             const int inc = wave_incl_scan(pc);
             if (lane == kWave - 1) s_scan[wg] = inc;
             group_sync<WPR>();
@@ -1031,7 +1216,15 @@ __device__ __forceinline__ void order_row_entries(const int (&kr)[SPT], const do
                 if (w < wg) wb += t;
                 tot += t;
             }
-            if (gi < NGR) pref[gi] = run + wb + inc - pc;
+            if (w0 < W16) {
+                unsigned p = (unsigned)(run + wb + inc - pc);
+#pragma unroll
+                for (int q = 0; q < 16; q += 2) {
+                    const unsigned p1 = p + c[q];
+                    pw[(w0 >> 1) + (q >> 1)] = p | (p1 << 16);
+                    p = p1 + c[q + 1];
+                }
+            }
             run += tot;
             group_sync<WPR>();
         }
@@ -1041,9 +1234,7 @@ __device__ __forceinline__ void order_row_entries(const int (&kr)[SPT], const do
             rk[s] = -1;
             if (kr[s] != kEmpty) {
                 const int j = kr[s] - lo, w = j >> 5;
-                int r = pref[w >> 3];
-                for (int q = w & ~7; q < w; ++q) r += __popc(bm[q]);
-                rk[s] = r + __popc(bm[w] & ((1u << (j & 31)) - 1u));
+                rk[s] = (int)pref[w] + __popc(bm[w] & ((1u << (j & 31)) - 1u));
             }
         }
         group_sync<WPR>();
@@ -1385,7 +1576,7 @@ __global__ __launch_bounds__(kSymHeavyThreads) void k_sym_heavy(
     constexpr int WG = G / kWave;
     constexpr int WORDS = kSymWinChunks * kChunkWords;
     __shared__ unsigned bm[WORDS];
-    __shared__ EnumScratch<float, G> S;
+    __shared__ RunScratch<float, G> S;
     // window-major: blocks launched together share one column window of B
     const int w = blockIdx.x / hcap, h = blockIdx.x % hcap;
     if (h >= sh->count[kBinHeavy] || stopped(err)) return;
@@ -1398,7 +1589,7 @@ __global__ __launch_bounds__(kSymHeavyThreads) void k_sym_heavy(
     const int *__restrict__ split1 = Bsplit + c1;
     for (int t = gt; t < WORDS; t += G) bm[t] = 0u;
     __syncthreads();
-    group_products<float, false, G, 8>(
+    run_products<float, false, G, G, 4, 2, kRun>(
         Arp[row], Arp[row + 1], gt, S, Bcol, (const float *)nullptr,
         [&](int e, int &bs, int &bl, float &) {
             const int k = Acol[e];
