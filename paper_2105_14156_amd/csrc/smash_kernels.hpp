@@ -1838,16 +1838,17 @@ __global__ __launch_bounds__(THREADS) void k_num_seg(
 
 // Dense chunk of a heavy row: products whose columns lie in chunk c0 added
 // directly into an LDS array of doubles indexed by column; each wave then
-// ranks its own 1024 columns with ballots and writes its entries straight to
-// C in column order (consecutive lanes, consecutive addresses).  Occupancy
-// needs no bitmap: the array starts at -0.0 and every product is added as
-// p + 0.0, which is never -0.0, so a column was reached exactly when its sum
-// is no longer the bit pattern of -0.0 (a sum of terms that are not -0.0 is
-// never -0.0 under round-to-nearest, even when they cancel).  The kernel is
-// persistent: a grid that fills the GPU once takes the dense chunks from a
-// global queue (one atomic per chunk), so that long and short chunks balance
-// across CUs, and each wave puts -0.0 back as it ranks its columns, so the
-// array is ready for the next chunk without a separate clearing pass.
+// ranks its own 1024 columns with ballots, stages its entries in column
+// order in those same LDS slots and copies them to C with whole-line stores.
+// Occupancy needs no bitmap: the array starts at -0.0 and every product is
+// added as p + 0.0, which is never -0.0, so a column was reached exactly when
+// its sum is no longer the bit pattern of -0.0 (a sum of terms that are not
+// -0.0 is never -0.0 under round-to-nearest, even when they cancel).  The
+// kernel is persistent: a grid that fills the GPU once takes the dense chunks
+// from a global queue (one atomic per chunk), so that long and short chunks
+// balance across CUs, and each wave puts -0.0 back in its slots once its
+// entries are out, so the array is ready for the next chunk without a
+// separate clearing pass.
 constexpr int kDenseThreads = 512;
 constexpr long long kNegZeroBits = (long long)0x8000000000000000ULL;
 
@@ -1892,9 +1893,7 @@ __global__ __launch_bounds__(kDenseThreads) void k_num_dense(
     int wcount = 0;
 #pragma unroll
     for (int r = 0; r < ROUNDS; ++r) {
-        const int jl = wg * CPW + r * kWave + lane;
-        vr[r] = acc[jl];
-        acc[jl] = -0.0;                                 // cleared for the next chunk
+        vr[r] = acc[wg * CPW + r * kWave + lane];
         msk[r] = __ballot(__double_as_longlong(vr[r]) != kNegZeroBits);
         wcount += __popcll(msk[r]);
     }
@@ -1907,19 +1906,54 @@ __global__ __launch_bounds__(kDenseThreads) void k_num_dense(
         tot += t;
     }
     if (gt == 0 && tot != sg.count) atomicOr(err, kErrCount);
-    const long long out0 = sg.out;
+    // the wave's entries are C[out0 + run, out0 + run + wcount): staged in
+    // rank order in the wave's own 1024 accumulator slots (now in
+    // registers), columns first and then values, and stored with
+    // consecutive lanes on consecutive addresses (whole cache lines)
+    const long long out = sg.out + run;
+    const int n = wcount < sg.count - run ? wcount : (sg.count - run > 0 ? sg.count - run : 0);
     const unsigned long long below = (1ull << lane) - 1ull;
+    int lr = 0;
+    if constexpr (sizeof(V) == 4) {
+        // FP32: (column, value) pairs, one pass
+        int2 *st = reinterpret_cast<int2 *>(acc + wg * CPW);
 #pragma unroll
-    for (int r = 0; r < ROUNDS; ++r) {
-        if ((msk[r] >> lane) & 1ull) {
-            const int p = run + __popcll(msk[r] & below);
-            if (p < sg.count) {
-                store_c(&Ccol[out0 + p], lo + wg * CPW + r * kWave + lane);
-                store_c(&Cval[out0 + p], (V)vr[r]);
-            }
+        for (int r = 0; r < ROUNDS; ++r) {
+            if ((msk[r] >> lane) & 1ull)
+                st[lr + __popcll(msk[r] & below)] =
+                    make_int2(lo + wg * CPW + r * kWave + lane, __float_as_int((float)vr[r]));
+            lr += __popcll(msk[r]);
         }
-        run += __popcll(msk[r]);
+        wave_sync();
+        for (int k = lane; k < n; k += kWave) {
+            const int2 e = st[k];
+            store_c(&Ccol[out + k], e.x);
+            store_c(&Cval[out + k], (V)__int_as_float(e.y));
+        }
+    } else {
+        // FP64: columns, then values
+        int *st_col = reinterpret_cast<int *>(acc + wg * CPW);
+        V *st_val = reinterpret_cast<V *>(acc + wg * CPW);
+#pragma unroll
+        for (int r = 0; r < ROUNDS; ++r) {
+            if ((msk[r] >> lane) & 1ull) st_col[lr + __popcll(msk[r] & below)] = lo + wg * CPW + r * kWave + lane;
+            lr += __popcll(msk[r]);
+        }
+        wave_sync();
+        for (int k = lane; k < n; k += kWave) store_c(&Ccol[out + k], st_col[k]);
+        wave_sync();
+        lr = 0;
+#pragma unroll
+        for (int r = 0; r < ROUNDS; ++r) {
+            if ((msk[r] >> lane) & 1ull) st_val[lr + __popcll(msk[r] & below)] = (V)vr[r];
+            lr += __popcll(msk[r]);
+        }
+        wave_sync();
+        for (int k = lane; k < n; k += kWave) store_c(&Cval[out + k], st_val[k]);
     }
+    wave_sync();
+#pragma unroll
+    for (int r = 0; r < ROUNDS; ++r) acc[wg * CPW + r * kWave + lane] = -0.0;   // cleared for the next chunk
     __syncthreads();                                    // s_wt and s_next are reused
     }
 }
