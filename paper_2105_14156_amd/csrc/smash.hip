@@ -529,10 +529,10 @@ smash_status numeric_impl(smash_ctx c, hipStream_t s, const Plan &p, const V *Av
     const int H = p.hdr.sym.count[kBinHeavy];
     if (H == 0) return SMASH_OK;
     if (p.heavy_mode == 0) {
-        // segments of up to 128 and 700 entries (tables of 256 and 1024 slots):
-        // two waves each; up to 1024 entries (2048 slots): four
-        TRY(launch_seg_bin<V, 8, 128>(c, s, p, 0, Aval, Bval, crp, ccol, cval));
-        TRY(launch_seg_bin<V, 10, 128>(c, s, p, 1, Aval, Bval, crp, ccol, cval));
+        // segments of up to 128 entries (table of 256 slots): one wave; up to
+        // 700 (1024 slots) and up to 1024 entries (2048 slots): four waves
+        TRY(launch_seg_bin<V, 8, 64>(c, s, p, 0, Aval, Bval, crp, ccol, cval));
+        TRY(launch_seg_bin<V, 10, 256>(c, s, p, 1, Aval, Bval, crp, ccol, cval));
         TRY(launch_seg_bin<V, 11, 256>(c, s, p, 2, Aval, Bval, crp, ccol, cval));
         const int nd = p.hdr.seg.count[kSegDense];
         if (nd) {

@@ -3,9 +3,14 @@
     python -m paper_2105_14156_amd.profiling stats RUN_kernel_stats.csv --steps K --cmd "..." > summary.txt
     python -m paper_2105_14156_amd.profiling traffic --fetch F.csv --write W.csv \\
         --copy-fetch CF.csv --copy-write CW.csv --copy-bytes N --steps K --cmd "..." --json out.json > summary.txt
+    python -m paper_2105_14156_amd.profiling counters P1.csv P2.csv ... --kernels num_dense,num_seg \\
+        --steps K --cmd "..." > summary.txt
 
 ``stats`` condenses a ``--kernel-trace --stats`` table to one line per kernel
-(calls, total and average duration).  ``traffic`` turns two ``--pmc`` runs
+(calls, total and average duration).  ``counters`` sums the counters of
+several ``--pmc`` passes per kernel and step and derives the figures that
+say what bounds a kernel (instruction mix, wait share, LDS bank conflicts,
+L2 hit rate and read latency).  ``traffic`` turns two ``--pmc`` runs
 (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch) into HBM bytes per launch,
 each counter scaled by what it reads for a plain device copy of known size
 (the copy reads and writes ``--copy-bytes`` bytes per launch).  The JSON
@@ -110,6 +115,58 @@ def cmd_traffic(args):
                        "kernels": kernels}, f, indent=1)
 
 
+def read_counters(paths, kernels):
+    """{kernel: {counter: sum over dispatches}} over several --pmc passes."""
+    out = collections.defaultdict(lambda: collections.defaultdict(float))
+    for path in paths:
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                n = short_name(r["Kernel_Name"])
+                if kernels and n not in kernels:
+                    continue
+                out[n][r["Counter_Name"]] += float(r["Counter_Value"])
+    return out
+
+
+# derived figures: (label, numerator, denominator, scale)
+DERIVED = [
+    ("VALU instructions per LDS instruction", "SQ_INSTS_VALU", "SQ_INSTS_LDS", 1.0),
+    ("SALU instructions per VALU instruction", "SQ_INSTS_SALU", "SQ_INSTS_VALU", 1.0),
+    ("share of wave cycles waiting (SQ_WAIT_ANY / SQ_WAVE_CYCLES)", "SQ_WAIT_ANY", "SQ_WAVE_CYCLES", 1.0),
+    ("LDS bank-conflict cycles per LDS-active cycle", "SQ_LDS_BANK_CONFLICT", "SQ_LDS_IDX_ACTIVE", 1.0),
+    ("LDS atomics with return per LDS instruction", "SQ_LDS_ATOMIC_RETURN", "SQ_INSTS_LDS", 1.0),
+    ("L2 hit rate (TCC_HIT / TCC_REQ)", "TCC_HIT_sum", "TCC_REQ_sum", 1.0),
+    ("L2 read latency seen by L1, cycles per request", "TCP_TCC_READ_REQ_LATENCY_sum", "TCP_TCC_READ_REQ_sum", 1.0),
+    ("L2 misses that go to DRAM", "TCC_EA0_RDREQ_DRAM_sum", "TCC_EA0_RDREQ_sum", 1.0),
+]
+
+
+def cmd_counters(args):
+    kernels = [k for k in args.kernels.split(",") if k] if args.kernels else []
+    c = read_counters(args.csv, kernels)
+    print(f"# rocprofv3 counters per step, {args.title}")
+    print(f"# command (one run per counter group): {args.cmd}")
+    print(f"# sums over the dispatches of {args.steps} step(s), divided by the step count; one --pmc pass per")
+    print("# group, so counters of different groups come from different (identical) runs")
+    for n in (kernels or sorted(c)):
+        t = c.get(n)
+        if not t:
+            continue
+        print(f"== {n}")
+        for k in sorted(t):
+            print(f"   {k:32s} {t[k] / args.steps:16.5g}")
+        if "GRBM_GUI_ACTIVE" in t and "SQ_INSTS_VALU" in t:
+            # GRBM_GUI_ACTIVE counts cycles once per XCD; a wave64 VALU
+            # instruction holds one of the CU's four SIMDs for 4 cycles
+            cycles = t["GRBM_GUI_ACTIVE"] / args.xcds
+            busy = t["SQ_INSTS_VALU"] * 4.0 / (args.cus * 4.0 * cycles)
+            print(f"   {'kernel cycles (GRBM_GUI_ACTIVE / XCDs)':58s} {cycles / args.steps:12.5g}")
+            print(f"   {'VALU issue share (4 x VALU / (4 SIMDs x CUs x cycles))':58s} {busy:12.3f}")
+        for label, num, den, sc in DERIVED:
+            if num in t and den in t and t[den]:
+                print(f"   {label:58s} {t[num] / t[den] * sc:12.3f}")
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd_name", required=True)
@@ -126,9 +183,19 @@ def main(argv=None):
     b.add_argument("--cmd", default="")
     b.add_argument("--title", default="")
     b.add_argument("--json")
+    c = sub.add_parser("counters")
+    c.add_argument("csv", nargs="+")
+    c.add_argument("--kernels", default="")
+    c.add_argument("--steps", type=int, default=1)
+    c.add_argument("--cus", type=int, default=256)
+    c.add_argument("--xcds", type=int, default=8)
+    c.add_argument("--cmd", default="")
+    c.add_argument("--title", default="")
     args = ap.parse_args(argv)
     if args.cmd_name == "stats":
         cmd_stats(args)
+    elif args.cmd_name == "counters":
+        cmd_counters(args)
     else:
         cmd_traffic(args)
 
