@@ -1589,18 +1589,27 @@ __global__ __launch_bounds__(kSymHeavyThreads) void k_sym_heavy(
     const int *__restrict__ split1 = Bsplit + c1;
     for (int t = gt; t < WORDS; t += G) bm[t] = 0u;
     __syncthreads();
-    run_products<float, false, G, G, 4, 2, kRun>(
-        Arp[row], Arp[row + 1], gt, S, Bcol, (const float *)nullptr,
-        [&](int e, int &bs, int &bl, float &) {
-            const int k = Acol[e];
-            bs = split0[k * per];
-            bl = split1[k * per] - bs;
-        },
-        [&](int j) {
-            const int jl = j - lo;
-            const unsigned bit = 1u << (jl & 31);
-            if (!(bm[jl >> 5] & bit)) atomicOr(&bm[jl >> 5], bit);     // most repeats skip the atomic
-        });
+    auto get = [&](int e, int &bs, int &bl, float &) {
+        const int k = Acol[e];
+        bs = split0[k * per];
+        bl = split1[k * per] - bs;
+    };
+    // all words of the thread's products are read before any is tested, so
+    // the reads overlap; most repeated columns then skip the atomic (an OR
+    // after a stale read is merely redundant)
+    auto sink = [&](const auto &j, const auto &ok) {
+        constexpr int N = sizeof(j) / sizeof(j[0]);
+        unsigned w[N];
+#pragma unroll
+        for (int u = 0; u < N; ++u) w[u] = ok[u] ? bm[(j[u] - lo) >> 5] : ~0u;
+#pragma unroll
+        for (int u = 0; u < N; ++u) {
+            const unsigned bit = 1u << ((j[u] - lo) & 31);
+            if (!(w[u] & bit)) atomicOr(&bm[(j[u] - lo) >> 5], bit);
+        }
+    };
+    run_products<float, false, G, G, 4, 2, kRun, decltype(get), decltype(sink), true>(
+        Arp[row], Arp[row + 1], gt, S, Bcol, (const float *)nullptr, get, sink);
     __syncthreads();
     // per-chunk counts: one wave per chunk
     int local = 0;
