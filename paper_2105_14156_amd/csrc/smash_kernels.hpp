@@ -1608,7 +1608,7 @@ __global__ __launch_bounds__(kSymHeavyThreads) void k_sym_heavy(
             if (!(w[u] & bit)) atomicOr(&bm[(j[u] - lo) >> 5], bit);
         }
     };
-    run_products<float, false, G, G, 4, 2, kRun, decltype(get), decltype(sink), true>(
+    run_products<float, false, G, G, 8, 2, kRun, decltype(get), decltype(sink), true>(
         Arp[row], Arp[row + 1], gt, S, Bcol, (const float *)nullptr, get, sink);
     __syncthreads();
     // per-chunk counts: one wave per chunk
