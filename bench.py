@@ -52,6 +52,10 @@ def parse():
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the fused-pass and batched-launch comparison beside the main line")
     ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--batch-config", default="", metavar="L,S,W,B,H",
+                    help="batch: use this configuration (lds_row_max,table_shift,wide_groups,blocks_per_cu,row_hash) "
+                         "instead of autotuning")
+    ap.add_argument("--no-plain-loop", action="store_true", help="batch: skip the loop of plain calls")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (counter calibration)")
     return ap.parse_args()
@@ -223,7 +227,7 @@ def run_fused_compare(key: str, npdt, steps: int, warmup: int):
     return res
 
 
-def run_batch(count: int, steps: int, warmup: int, plain_loops: int = 2):
+def run_batch(count: int, steps: int, warmup: int, plain_loops: int = 2, config: str = ""):
     """The batched workload: `count` products in one captured graph (after
     autotuning the plan), against a loop of plain smash_spgemm calls over the
     same problems on the same stream.  Returns a dict of the measurements."""
@@ -239,8 +243,14 @@ def run_batch(count: int, steps: int, warmup: int, plain_loops: int = 2):
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         plan = smash.BatchPlan(ctx, dA, dB, stream=stream)
-        cfg, tune_ms = plan.autotune(reps=3, stream=stream)
-        log(f"autotuned {cfg} ({tune_ms:.3f} ms per batch)")
+        if config:
+            keys = ("lds_row_max", "table_shift", "wide_groups", "blocks_per_cu", "row_hash")
+            plan.configure(dict(zip(keys, (int(v) for v in config.split(",")))))
+            cfg, tune_ms = plan.config(), 0.0
+            log(f"configured {cfg}")
+        else:
+            cfg, tune_ms = plan.autotune(reps=3, stream=stream)
+            log(f"autotuned {cfg} ({tune_ms:.3f} ms per batch)")
         plan.capture(stream)
         for _ in range(warmup):
             plan.launch(stream)
@@ -253,15 +263,17 @@ def run_batch(count: int, steps: int, warmup: int, plain_loops: int = 2):
         plan.result(stream)
         graph_ms = e0.elapsed_time(e1) / steps
         # the same problems one plain call at a time
-        for A, B in zip(dA[:8], dB[:8]):
-            ctx.spgemm(A, B, stream)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(plain_loops):
-            for A, B in zip(dA, dB):
+        loop_ms = float("nan")
+        if plain_loops:
+            for A, B in zip(dA[:8], dB[:8]):
                 ctx.spgemm(A, B, stream)
-        torch.cuda.synchronize()
-        loop_ms = (time.perf_counter() - t0) / plain_loops * 1e3
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(plain_loops):
+                for A, B in zip(dA, dB):
+                    ctx.spgemm(A, B, stream)
+            torch.cuda.synchronize()
+            loop_ms = (time.perf_counter() - t0) / plain_loops * 1e3
     rows = sum(w.A.rows for w in probs)
     alg = sum(metrics.algorithmic_bytes(w.A.rows, w.B.rows, w.A.nnz, w.B.nnz, 0, 4) for w in probs) \
         + nnz_c * 8
@@ -273,7 +285,7 @@ def run_batch(count: int, steps: int, warmup: int, plain_loops: int = 2):
 
 
 def main_batch(args):
-    r = run_batch(args.batch_count, args.steps, args.warmup)
+    r = run_batch(args.batch_count, args.steps, args.warmup, 0 if args.no_plain_loop else 2, args.batch_config)
     gflops = metrics.gflops(r["products"], r["graph_ms"] * 1e-3)
     gbs = r["alg_bytes"] / (r["graph_ms"] * 1e-3) / 1e9
     out = {
@@ -287,8 +299,9 @@ def main_batch(args):
         "hbm_gbs_algorithmic": round(gbs, 2), "path_roofline_frac": round(gbs / HBM_PEAK_GBS, 4),
         "roofline": {"bound": "hbm", "kernel": "whole batch graph", "achieved": round(gbs, 2),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None},
-        "plain_loop_ms": round(r["plain_loop_ms"], 3),
-        "speedup_vs_plain_loop": round(r["plain_loop_ms"] / r["graph_ms"], 2),
+        "plain_loop_ms": round(r["plain_loop_ms"], 3) if r["plain_loop_ms"] == r["plain_loop_ms"] else None,
+        "speedup_vs_plain_loop": round(r["plain_loop_ms"] / r["graph_ms"], 2)
+        if r["plain_loop_ms"] == r["plain_loop_ms"] else None,
     }
     print(json.dumps(out), flush=True)
 

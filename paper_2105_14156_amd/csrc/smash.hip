@@ -909,8 +909,9 @@ smash_status workspace_query(smash_ctx c, const smash_csr *A, const smash_csr *B
     TRY(validate_csr(c, s, *A, kErrCsrA, perr(c), nullptr));
     TRY(validate_csr(c, s, *B, kErrCsrB, perr(c), nullptr));
     TRY(launch(c, K_WS_QUERY, s, [&] {
-        k_ws_query<<<blocks_for(q.m, 4), 256, 0, s>>>((int)q.m, (int)q.n, q.lds_row_max, A->row_ptr, A->col_idx,
-                                                      B->row_ptr, c->d_hdr);
+        const unsigned grid = (unsigned)std::min<long long>(blocks_for(std::max<long long>(q.m, 1), 4), 4096);
+        k_ws_query<<<grid, 256, 0, s>>>((int)q.m, (int)q.n, q.lds_row_max, A->row_ptr, A->col_idx, B->row_ptr,
+                                        c->d_hdr);
     }));
     TRY(read_hdr(c, s));
     TRY(device_errors(c, c->h_hdr->error));

@@ -365,8 +365,8 @@ __global__ __launch_bounds__(kWideThreads) void k_bsym_wide(const BatchDesc *__r
 // row's products with columns inside it are added into an LDS array of
 // doubles indexed by column (occupancy marked by the -0.0 start value, as in
 // the dense chunks of single products), and each wave ranks its share of the
-// window with ballots and writes its entries in column order (dynamic LDS:
-// the kWideWin doubles).  Each window enumerates only the B entries inside
+// window with ballots and stores its entries in column order through its own
+// slots (dynamic LDS: the kWideWin doubles).  Each window enumerates only the B entries inside
 // it: a row with at most kWideThreads A entries keeps, per thread, a cursor
 // into its B row that the windows advance (one search per window); longer
 // rows search both window bounds in every B row they visit.
@@ -389,7 +389,6 @@ __global__ __launch_bounds__(kWideThreads) void k_bnum_wide(const BatchDesc *__r
     const int cnt = bh->num.count[kBinHeavy];
     const int *rows = perm + bh->num.offset[kBinHeavy];
     const int gt = threadIdx.x, lane = lane_id(), wg = gt / kWave;
-    const unsigned long long below = (1ull << lane) - 1ull;
     // heavy rows from a queue (one atomic per row): long and short rows
     // balance across the persistent blocks
     for (;;) {
@@ -458,17 +457,8 @@ __global__ __launch_bounds__(kWideThreads) void k_bnum_wide(const BatchDesc *__r
                 if (w < wg) run += t;
                 tot += t;
             }
-#pragma unroll
-            for (int q = 0; q < ROUNDS; ++q) {
-                if ((msk[q] >> lane) & 1ull) {
-                    const int pos = run + __popcll(msk[q] & below);
-                    if (pos < nc) {
-                        store_c(&Ccol[rb + pos], lo + wg * CPW + q * kWave + lane);
-                        store_c(&Cval[rb + pos], (V)vr[q]);
-                    }
-                }
-                run += __popcll(msk[q]);
-            }
+            const int n = wcount < nc - run ? wcount : (nc - run > 0 ? nc - run : 0);
+            wave_store_ranked<V, ROUNDS>(vr, msk, acc + wg * CPW, lo + wg * CPW, rb + run, n, Ccol, Cval);
             done += tot;
             __syncthreads();
         }

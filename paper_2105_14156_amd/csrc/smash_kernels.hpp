@@ -929,19 +929,45 @@ __global__ __launch_bounds__(256) void k_ws_query(int m, int ncols, int lds_row_
                                                   const int *__restrict__ Acol, const int *__restrict__ Brp,
                                                   DevHdr *h)
 {
-    const int lane = lane_id();
-    const int row = blockIdx.x * 4 + threadIdx.x / kWave;
-    if (row >= m || stopped(&h->error)) return;
-    const int e0 = Arp[row], e1 = Arp[row + 1];
-    long long ub = 0;
-    for (int e = e0 + lane; e < e1; e += kWave) ub += Brp[Acol[e] + 1] - Brp[Acol[e]];
-    ub = wave_sum(ub);
-    const long long cap = ub < ncols ? ub : ncols;
-    if (lane == 0 && cap > lds_row_max) {
-        const unsigned long long t = 1ull << gtable_log2(cap);
-        atomicAdd(&h->q_heavy, 1);
-        atomicAdd(&h->q_gsum, t);
-        atomicMax(&h->q_gmax, t);
+    // one wave per row, grid-stride; the counts of the block's rows are
+    // summed in LDS and added with one atomic per block and counter
+    __shared__ unsigned long long s_sum[4], s_max[4];
+    __shared__ int s_cnt[4];
+    const int lane = lane_id(), w = threadIdx.x / kWave;
+    int cnt = 0;
+    unsigned long long gsum = 0, gmax = 0;
+    if (!stopped(&h->error)) {
+        for (int row = blockIdx.x * 4 + w; row < m; row += gridDim.x * 4) {
+            const int e0 = Arp[row], e1 = Arp[row + 1];
+            long long ub = 0;
+            for (int e = e0 + lane; e < e1; e += kWave) ub += Brp[Acol[e] + 1] - Brp[Acol[e]];
+            ub = wave_sum(ub);
+            const long long cap = ub < ncols ? ub : ncols;
+            if (cap > lds_row_max) {
+                const unsigned long long t = 1ull << gtable_log2(cap);
+                ++cnt;
+                gsum += t;
+                gmax = t > gmax ? t : gmax;
+            }
+        }
+    }
+    if (lane == 0) {
+        s_cnt[w] = cnt;
+        s_sum[w] = gsum;
+        s_max[w] = gmax;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int v = 1; v < 4; ++v) {
+            cnt += s_cnt[v];
+            gsum += s_sum[v];
+            gmax = s_max[v] > gmax ? s_max[v] : gmax;
+        }
+        if (cnt) {
+            atomicAdd(&h->q_heavy, cnt);
+            atomicAdd(&h->q_gsum, gsum);
+            atomicMax(&h->q_gmax, gmax);
+        }
     }
 }
 
@@ -1845,6 +1871,59 @@ __global__ __launch_bounds__(THREADS) void k_num_seg(
     }
 }
 
+// Stores the entries a wave has ranked in its ROUNDS x 64 slots of a dense
+// window: slot r * 64 + lane holds column col0 + r * 64 + lane, occupied
+// where bit `lane` of msk[r] is set, with value vr[r].  The first n of them,
+// in column order, go to C[out, out + n): staged in the wave's own LDS slots
+// (whose values are already in registers) and copied with consecutive lanes
+// on consecutive addresses, so stores cover whole cache lines.  FP32 stages
+// (column, value) pairs in one pass, FP64 columns and then values.  Every
+// lane of the wave calls it; the slots are left dirty.
+template <typename V, int ROUNDS>
+__device__ __forceinline__ void wave_store_ranked(const double (&vr)[ROUNDS], const unsigned long long (&msk)[ROUNDS],
+                                                  double *slots, int col0, long long out, int n,
+                                                  int *__restrict__ Ccol, V *__restrict__ Cval)
+{
+    const int lane = lane_id();
+    const unsigned long long below = (1ull << lane) - 1ull;
+    int lr = 0;
+    if constexpr (sizeof(V) == 4) {
+        int2 *st = reinterpret_cast<int2 *>(slots);
+#pragma unroll
+        for (int r = 0; r < ROUNDS; ++r) {
+            if ((msk[r] >> lane) & 1ull)
+                st[lr + __popcll(msk[r] & below)] = make_int2(col0 + r * kWave + lane, __float_as_int((float)vr[r]));
+            lr += __popcll(msk[r]);
+        }
+        wave_sync();
+        for (int k = lane; k < n; k += kWave) {
+            const int2 e = st[k];
+            store_c(&Ccol[out + k], e.x);
+            store_c(&Cval[out + k], (V)__int_as_float(e.y));
+        }
+    } else {
+        int *st_col = reinterpret_cast<int *>(slots);
+        V *st_val = reinterpret_cast<V *>(slots);
+#pragma unroll
+        for (int r = 0; r < ROUNDS; ++r) {
+            if ((msk[r] >> lane) & 1ull) st_col[lr + __popcll(msk[r] & below)] = col0 + r * kWave + lane;
+            lr += __popcll(msk[r]);
+        }
+        wave_sync();
+        for (int k = lane; k < n; k += kWave) store_c(&Ccol[out + k], st_col[k]);
+        wave_sync();
+        lr = 0;
+#pragma unroll
+        for (int r = 0; r < ROUNDS; ++r) {
+            if ((msk[r] >> lane) & 1ull) st_val[lr + __popcll(msk[r] & below)] = (V)vr[r];
+            lr += __popcll(msk[r]);
+        }
+        wave_sync();
+        for (int k = lane; k < n; k += kWave) store_c(&Cval[out + k], st_val[k]);
+    }
+    wave_sync();
+}
+
 // Dense chunk of a heavy row: products whose columns lie in chunk c0 added
 // directly into an LDS array of doubles indexed by column; each wave then
 // ranks its own 1024 columns with ballots, stages its entries in column
@@ -1915,52 +1994,8 @@ __global__ __launch_bounds__(kDenseThreads) void k_num_dense(
         tot += t;
     }
     if (gt == 0 && tot != sg.count) atomicOr(err, kErrCount);
-    // the wave's entries are C[out0 + run, out0 + run + wcount): staged in
-    // rank order in the wave's own 1024 accumulator slots (now in
-    // registers), columns first and then values, and stored with
-    // consecutive lanes on consecutive addresses (whole cache lines)
-    const long long out = sg.out + run;
     const int n = wcount < sg.count - run ? wcount : (sg.count - run > 0 ? sg.count - run : 0);
-    const unsigned long long below = (1ull << lane) - 1ull;
-    int lr = 0;
-    if constexpr (sizeof(V) == 4) {
-        // FP32: (column, value) pairs, one pass
-        int2 *st = reinterpret_cast<int2 *>(acc + wg * CPW);
-#pragma unroll
-        for (int r = 0; r < ROUNDS; ++r) {
-            if ((msk[r] >> lane) & 1ull)
-                st[lr + __popcll(msk[r] & below)] =
-                    make_int2(lo + wg * CPW + r * kWave + lane, __float_as_int((float)vr[r]));
-            lr += __popcll(msk[r]);
-        }
-        wave_sync();
-        for (int k = lane; k < n; k += kWave) {
-            const int2 e = st[k];
-            store_c(&Ccol[out + k], e.x);
-            store_c(&Cval[out + k], (V)__int_as_float(e.y));
-        }
-    } else {
-        // FP64: columns, then values
-        int *st_col = reinterpret_cast<int *>(acc + wg * CPW);
-        V *st_val = reinterpret_cast<V *>(acc + wg * CPW);
-#pragma unroll
-        for (int r = 0; r < ROUNDS; ++r) {
-            if ((msk[r] >> lane) & 1ull) st_col[lr + __popcll(msk[r] & below)] = lo + wg * CPW + r * kWave + lane;
-            lr += __popcll(msk[r]);
-        }
-        wave_sync();
-        for (int k = lane; k < n; k += kWave) store_c(&Ccol[out + k], st_col[k]);
-        wave_sync();
-        lr = 0;
-#pragma unroll
-        for (int r = 0; r < ROUNDS; ++r) {
-            if ((msk[r] >> lane) & 1ull) st_val[lr + __popcll(msk[r] & below)] = (V)vr[r];
-            lr += __popcll(msk[r]);
-        }
-        wave_sync();
-        for (int k = lane; k < n; k += kWave) store_c(&Cval[out + k], st_val[k]);
-    }
-    wave_sync();
+    wave_store_ranked<V, ROUNDS>(vr, msk, acc + wg * CPW, lo + wg * CPW, sg.out + run, n, Ccol, Cval);
 #pragma unroll
     for (int r = 0; r < ROUNDS; ++r) acc[wg * CPW + r * kWave + lane] = -0.0;   // cleared for the next chunk
     __syncthreads();                                    // s_wt and s_next are reused
