@@ -909,7 +909,8 @@ smash_status workspace_query(smash_ctx c, const smash_csr *A, const smash_csr *B
     TRY(validate_csr(c, s, *A, kErrCsrA, perr(c), nullptr));
     TRY(validate_csr(c, s, *B, kErrCsrB, perr(c), nullptr));
     TRY(launch(c, K_WS_QUERY, s, [&] {
-        const unsigned grid = (unsigned)std::min<long long>(blocks_for(std::max<long long>(q.m, 1), 4), 4096);
+        const unsigned grid =
+            (unsigned)std::min<long long>(blocks_for(std::max<long long>(q.m, 1), 256 / kRowLanes), 4096);
         k_ws_query<<<grid, 256, 0, s>>>((int)q.m, (int)q.n, q.lds_row_max, A->row_ptr, A->col_idx, B->row_ptr,
                                         c->d_hdr);
     }));
@@ -975,9 +976,9 @@ smash_status symbolic_impl(smash_ctx c, const smash_csr *A, const smash_csr *B, 
     const bool global = p.heavy_mode == 1;
     const bool learned = fuse && c->opt[SMASH_OPT_FUSED_SIZING] == 0;
     TRY(launch(c, K_ANALYZE, s, [&] {
-        k_analyze<<<blocks_for(m, 4), 256, 0, s>>>((int)m, (int)p.n, p.lds_row_max, A->row_ptr, A->col_idx, B->row_ptr,
-                                                   p.ub, p.cap, p.nnzc, p.sym_bin, learned ? p.feats : nullptr,
-                                                   learned ? p.maxb : nullptr, perr(c));
+        k_analyze<<<blocks_for(m, 256 / kRowLanes), 256, 0, s>>>(
+            (int)m, (int)p.n, p.lds_row_max, A->row_ptr, A->col_idx, B->row_ptr, p.ub, p.cap, p.nnzc, p.sym_bin,
+            learned ? p.feats : nullptr, learned ? p.maxb : nullptr, perr(c));
     }));
     if (fuse) TRY(fused_stage(c, s, p, alloc, user));
     TRY(bin_rows(c, s, p, p.sym_bin, p.ub, nullptr, &c->d_hdr->sym, p.sym_perm, global ? p.cap : nullptr,

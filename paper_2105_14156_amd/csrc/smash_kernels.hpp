@@ -865,11 +865,98 @@ __device__ __forceinline__ float row_feature(int t, int na, long long ub, double
 }
 
 // Row analysis (step a1): products ub_i = sum_k nnz(B_k) over row i of A, the
-// output bound cap_i = min(ub_i, cols) and the row's symbolic bin.  One wave
-// per row, four rows per block.  With feats non-NULL it also writes the
-// learned predictor's six features and max_k nnz(B_k) (maxb_out) of the rows
-// whose bound exceeds the LDS row limit, the only rows the predictor is
-// asked about.
+// output bound cap_i = min(ub_i, cols) and the row's symbolic bin.  A wave
+// takes eight rows: rows of at most 64 entries are summed by their own group
+// of eight lanes (most rows of A have a few dozen entries, so a whole wave
+// per row would leave most lanes idle), longer rows one after another by the
+// whole wave, four entries per lane in flight, so that a hub row does not
+// leave one group with a long serial chain.  With feats non-NULL it also
+// writes the learned predictor's six features and max_k nnz(B_k) (maxb_out)
+// of the rows whose bound exceeds the LDS row limit, the only rows the
+// predictor is asked about.
+constexpr int kRowLanes = 8;
+constexpr int kShortRow = 64;
+
+// Partial sums of one lane over entries e0 + first, e0 + first + step, ...
+struct RowPart {
+    long long ub = 0;
+    double sq = 0.0;
+    int mx = 0, mn = 0x7fffffff;
+};
+
+template <bool FEATS>
+__device__ __forceinline__ void row_part(const int *__restrict__ Acol, const int *__restrict__ Brp, int e, int e1,
+                                         int step, RowPart &r)
+{
+    for (; e + 3 * step < e1; e += 4 * step) {
+        int k[4], len[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) k[u] = Acol[e + u * step];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) len[u] = Brp[k[u] + 1] - Brp[k[u]];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            r.ub += len[u];
+            if constexpr (FEATS) {
+                r.sq += (double)len[u] * (double)len[u];
+                r.mx = len[u] > r.mx ? len[u] : r.mx;
+                r.mn = len[u] < r.mn ? len[u] : r.mn;
+            }
+        }
+    }
+    for (; e < e1; e += step) {
+        const int len = Brp[Acol[e] + 1] - Brp[Acol[e]];
+        r.ub += len;
+        if constexpr (FEATS) {
+            r.sq += (double)len * (double)len;
+            r.mx = len > r.mx ? len : r.mx;
+            r.mn = len < r.mn ? len : r.mn;
+        }
+    }
+}
+
+// Reduction of RowPart over lanes that differ in the bits of `width - 1`.
+template <bool FEATS>
+__device__ __forceinline__ void row_reduce(RowPart &r, int width)
+{
+    for (int d = width / 2; d > 0; d >>= 1) {
+        r.ub += __shfl_xor(r.ub, d, kWave);
+        if constexpr (FEATS) {
+            r.sq += __shfl_xor(r.sq, d, kWave);
+            const int a = __shfl_xor(r.mx, d, kWave), b = __shfl_xor(r.mn, d, kWave);
+            r.mx = a > r.mx ? a : r.mx;
+            r.mn = b < r.mn ? b : r.mn;
+        }
+    }
+}
+
+// Sums of the wave's eight rows [row0, row0 + 8) into the lanes of each
+// row's group (every lane of the wave calls it).
+template <bool FEATS>
+__device__ __forceinline__ RowPart wave_rows(int m, int row0, const int *__restrict__ Arp,
+                                             const int *__restrict__ Acol, const int *__restrict__ Brp, int &e0,
+                                             int &e1)
+{
+    const int lane = lane_id(), sl = lane & (kRowLanes - 1), row = row0 + lane / kRowLanes;
+    e0 = row < m ? Arp[row] : 0;
+    e1 = row < m ? Arp[row + 1] : 0;
+    const bool lng = e1 - e0 > kShortRow;
+    RowPart r;
+    if (!lng) row_part<FEATS>(Acol, Brp, e0 + sl, e1, kRowLanes, r);
+    row_reduce<FEATS>(r, kRowLanes);
+    unsigned long long todo = __ballot(lng && sl == 0);
+    while (todo) {
+        const int src = __ffsll((long long)todo) - 1;
+        todo &= todo - 1;
+        RowPart w;
+        row_part<FEATS>(Acol, Brp, __builtin_amdgcn_readlane(e0, src) + lane, __builtin_amdgcn_readlane(e1, src),
+                        kWave, w);
+        row_reduce<FEATS>(w, kWave);
+        if (lane / kRowLanes == src / kRowLanes) r = w;
+    }
+    return r;
+}
+
 __global__ __launch_bounds__(256) void k_analyze(int m, int ncols, int lds_row_max,
                                                  const int *__restrict__ Arp, const int *__restrict__ Acol,
                                                  const int *__restrict__ Brp, long long *__restrict__ ub_out,
@@ -877,38 +964,21 @@ __global__ __launch_bounds__(256) void k_analyze(int m, int ncols, int lds_row_m
                                                  unsigned char *__restrict__ bin_out, float *__restrict__ feats,
                                                  int *__restrict__ maxb_out, const int *err)
 {
-    const int lane = lane_id();
-    const int row = blockIdx.x * 4 + threadIdx.x / kWave;
-    if (row >= m || stopped(err)) return;
-    const int e0 = Arp[row], e1 = Arp[row + 1];
-    long long ub = 0;
-    double sq = 0.0;
-    int mx = 0, mn = 0x7fffffff;
-    for (int e = e0 + lane; e < e1; e += kWave) {
-        const int k = Acol[e];
-        const int len = Brp[k + 1] - Brp[k];
-        ub += len;
-        if (feats) {
-            sq += (double)len * (double)len;
-            mx = len > mx ? len : mx;
-            mn = len < mn ? len : mn;
-        }
-    }
-    ub = wave_sum(ub);
+    const int row0 = (blockIdx.x * 256 + (int)threadIdx.x) / kWave * kRowLanes;
+    if (row0 >= m || stopped(err)) return;               // whole waves
+    const int sl = lane_id() & (kRowLanes - 1), row = row0 + lane_id() / kRowLanes;
+    int e0, e1;
+    RowPart r = feats ? wave_rows<true>(m, row0, Arp, Acol, Brp, e0, e1)
+                      : wave_rows<false>(m, row0, Arp, Acol, Brp, e0, e1);
+    if (row >= m) return;
+    const long long ub = r.ub;
     if (feats && (ub < ncols ? ub : ncols) > lds_row_max) {
-        // the predictor's six features (the same arithmetic as k_features)
-        sq = wave_sum(sq);
-#pragma unroll
-        for (int d = kWave / 2; d > 0; d >>= 1) {
-            const int a = __shfl_xor(mx, d, kWave), b = __shfl_xor(mn, d, kWave);
-            mx = a > mx ? a : mx;
-            mn = b < mn ? b : mn;
-        }
-        // lanes 0..5 write one feature each
-        if (lane < 6) feats[(long long)row * 6 + lane] = row_feature(lane, e1 - e0, ub, sq, mx, mn, ncols);
-        if (lane == 0) maxb_out[row] = e1 > e0 ? mx : 0;
+        // the predictor's six features (the same arithmetic as k_features):
+        // lanes 0..5 of the row's group write one each
+        if (sl < 6) feats[(long long)row * 6 + sl] = row_feature(sl, e1 - e0, ub, r.sq, r.mx, r.mn, ncols);
+        if (sl == 0) maxb_out[row] = e1 > e0 ? r.mx : 0;
     }
-    if (lane == 0) {
+    if (sl == 0) {
         const int cap = (int)(ub < ncols ? ub : ncols);
         int b;
         if (ub == 0) b = kBinEmpty;
@@ -921,35 +991,41 @@ __global__ __launch_bounds__(256) void k_analyze(int m, int ncols, int lds_row_m
     }
 }
 
-// Workspace query: the number of heavy rows (output bound above the LDS row
-// limit) and the global hash table slots their symbolic pass would take
-// (sum and largest), accumulated into the header with one atomic per wave.
-// A wave per row, four rows per block, like k_analyze.
+// Workspace query (smash_workspace_size): the number of heavy rows and the
+// slots their global tables would take (total and largest), from the same
+// bounds as k_analyze (eight rows per wave, grid-stride over whole waves);
+// the counts of a block's rows are summed in LDS and added with one atomic
+// per block and counter.
 __global__ __launch_bounds__(256) void k_ws_query(int m, int ncols, int lds_row_max, const int *__restrict__ Arp,
                                                   const int *__restrict__ Acol, const int *__restrict__ Brp,
                                                   DevHdr *h)
 {
-    // one wave per row, grid-stride; the counts of the block's rows are
-    // summed in LDS and added with one atomic per block and counter
-    __shared__ unsigned long long s_sum[4], s_max[4];
-    __shared__ int s_cnt[4];
-    const int lane = lane_id(), w = threadIdx.x / kWave;
+    constexpr int RPB = 256 / kWave * kRowLanes;        // rows per block and step
+    __shared__ unsigned long long s_sum[256 / kWave], s_max[256 / kWave];
+    __shared__ int s_cnt[256 / kWave];
+    const int lane = lane_id(), w = threadIdx.x / kWave, sl = lane & (kRowLanes - 1);
     int cnt = 0;
     unsigned long long gsum = 0, gmax = 0;
     if (!stopped(&h->error)) {
-        for (int row = blockIdx.x * 4 + w; row < m; row += gridDim.x * 4) {
-            const int e0 = Arp[row], e1 = Arp[row + 1];
-            long long ub = 0;
-            for (int e = e0 + lane; e < e1; e += kWave) ub += Brp[Acol[e] + 1] - Brp[Acol[e]];
-            ub = wave_sum(ub);
-            const long long cap = ub < ncols ? ub : ncols;
-            if (cap > lds_row_max) {
+        for (int r0 = blockIdx.x * RPB + w * kRowLanes; r0 < m; r0 += gridDim.x * RPB) {
+            int e0, e1;
+            const RowPart r = wave_rows<false>(m, r0, Arp, Acol, Brp, e0, e1);
+            const int row = r0 + lane / kRowLanes;
+            const long long cap = r.ub < ncols ? r.ub : ncols;
+            if (row < m && sl == 0 && cap > lds_row_max) {
                 const unsigned long long t = 1ull << gtable_log2(cap);
                 ++cnt;
                 gsum += t;
                 gmax = t > gmax ? t : gmax;
             }
         }
+    }
+    // wave totals, then the block's
+    for (int d = kWave / 2; d > 0; d >>= 1) {
+        cnt += __shfl_xor(cnt, d, kWave);
+        gsum += __shfl_xor(gsum, d, kWave);
+        const unsigned long long o = __shfl_xor(gmax, d, kWave);
+        gmax = o > gmax ? o : gmax;
     }
     if (lane == 0) {
         s_cnt[w] = cnt;
@@ -958,7 +1034,7 @@ __global__ __launch_bounds__(256) void k_ws_query(int m, int ncols, int lds_row_
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int v = 1; v < 4; ++v) {
+        for (int v = 1; v < 256 / kWave; ++v) {
             cnt += s_cnt[v];
             gsum += s_sum[v];
             gmax = s_max[v] > gmax ? s_max[v] : gmax;
