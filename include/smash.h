@@ -97,7 +97,7 @@ typedef enum {
      * 32..1024, default 1024. */
     SMASH_OPT_LDS_ROW_MAX = 1,
     /* Heavy-row path: 0 = column segments merged in LDS, hashed or, for
-     * chunks denser than a quarter, accumulated by column (default);
+     * chunks with more than 1024 of their 8192 columns, accumulated by column (default);
      * 1 = one hash table per row in global memory (the paper's third
      * version, "Fragmenting Memory", moves the table to DRAM). */
     SMASH_OPT_HEAVY_MODE = 2,
