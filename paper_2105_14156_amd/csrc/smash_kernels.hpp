@@ -2009,11 +2009,13 @@ __device__ __forceinline__ void wave_store_ranked(const double (&vr)[ROUNDS], co
 // its sum is no longer the bit pattern of -0.0 (a sum of terms that are not
 // -0.0 is never -0.0 under round-to-nearest, even when they cancel).  The
 // kernel is persistent: a grid that fills the GPU once takes the dense chunks
-// from a global queue (one atomic per chunk), so that long and short chunks
-// balance across CUs, and each wave puts -0.0 back in its slots once its
+// from a global queue (one atomic per kDenseClaim chunks), so that long and
+// short chunks balance across CUs, and each wave puts -0.0 back in its slots once its
 // entries are out, so the array is ready for the next chunk without a
 // separate clearing pass.
 constexpr int kDenseThreads = 512;
+// dense chunks a block claims with one atomic on the queue
+constexpr int kDenseClaim = 4;
 constexpr long long kNegZeroBits = (long long)0x8000000000000000ULL;
 
 template <typename V>
@@ -2035,10 +2037,13 @@ __global__ __launch_bounds__(kDenseThreads) void k_num_dense(
     const int gt = threadIdx.x, lane = lane_id(), wg = gt / kWave;
     for (int t = gt; t < kChunkCols; t += kDenseThreads) acc[t] = -0.0;
     for (;;) {
-    if (gt == 0) s_next = atomicAdd(queue, 1);
+    if (gt == 0) s_next = atomicAdd(queue, kDenseClaim);
     __syncthreads();                                    // also: the previous chunk is fully written
-    if (s_next >= nseg) break;
-    const Seg sg = segs[s_next];
+    const int first = s_next;
+    if (first >= nseg) break;
+    const int last = first + kDenseClaim < nseg ? first + kDenseClaim : nseg;
+    for (int t = first; t < last; ++t) {
+    const Seg sg = segs[t];
     const int lo = sg.c0 * kChunkCols;
     const int *__restrict__ split0 = Bsplit + sg.c0;
     const int *__restrict__ split1 = split0 + 1;
@@ -2065,9 +2070,9 @@ __global__ __launch_bounds__(kDenseThreads) void k_num_dense(
     __syncthreads();
     int run = 0, tot = 0;
     for (int w = 0; w < NW; ++w) {
-        const int t = s_wt[w];
-        if (w < wg) run += t;
-        tot += t;
+        const int c = s_wt[w];
+        if (w < wg) run += c;
+        tot += c;
     }
     if (gt == 0 && tot != sg.count) atomicOr(err, kErrCount);
     const int n = wcount < sg.count - run ? wcount : (sg.count - run > 0 ? sg.count - run : 0);
@@ -2075,6 +2080,7 @@ __global__ __launch_bounds__(kDenseThreads) void k_num_dense(
 #pragma unroll
     for (int r = 0; r < ROUNDS; ++r) acc[wg * CPW + r * kWave + lane] = -0.0;   // cleared for the next chunk
     __syncthreads();                                    // s_wt and s_next are reused
+    }
     }
 }
 
