@@ -381,8 +381,10 @@ void carve_workspace(smash_ctx c, Plan &p, char *base, size_t ws_bytes)
         p.gvals = cv.take<double>(p.pool_cap);
         p.gtouch = cv.take<int>(p.pool_cap);
     } else {
+        // a heavy row needs more than lds_row_max output columns: with B no
+        // wider than that there are none, and no heavy-row kernel is launched
         const size_t per_row = (size_t)p.nchunks * (2 * sizeof(int) + sizeof(Seg));
-        p.hcap = std::min<long long>((long long)(rest / per_row), m);
+        p.hcap = p.n > p.lds_row_max ? std::min<long long>((long long)(rest / per_row), m) : 0;
         const size_t cells = (size_t)p.hcap * p.nchunks;
         p.wcnt = cv.take<int>(cells);
         p.woff = cv.take<int>(cells);
@@ -547,7 +549,8 @@ smash_status numeric_impl(smash_ctx c, hipStream_t s, const Plan &p, const V *Av
                 k_num_dense<V><<<grid, kDenseThreads, lds, s>>>(p.A.row_ptr, p.A.col_idx, Aval, p.B.col_idx, Bval,
                                                                p.bsplit, (long long)(p.nchunks + 1), hrows, segs, p.nchunks,
                                                                p.woff, (const long long *)crp, ccol, cval,
-                                                               c->d_numerr, nd, p.queue);
+                                                               c->d_numerr, nd, p.queue,
+                                                               nd >= kDenseClaimMinPerBlock * grid ? kDenseClaim : 1);
             }));
         }
         return SMASH_OK;
@@ -666,7 +669,7 @@ smash_status fused_stage(smash_ctx c, hipStream_t s, Plan &p, smash_alloc_fn all
     if (p.fused_dtype == SMASH_F32) TRY(run_fused_bins<float>(c, s, p));
     else TRY(run_fused_bins<double>(c, s, p));
     TRY(launch(c, K_FUSED_AUX, s, [&] {
-        k_fused_mark<<<blocks_for(m, 256), 256, 0, s>>>(m, p.fbin, p.fstatus, p.nnzc, p.sym_bin, &c->d_hdr->fused_ok,
+        k_fused_mark<<<std::min(blocks_for(m, 256), 1024u), 256, 0, s>>>(m, p.fbin, p.fstatus, p.nnzc, p.sym_bin, &c->d_hdr->fused_ok,
                                                         &c->d_hdr->fused_entries, perr(c));
     }));
     return SMASH_OK;
@@ -958,7 +961,7 @@ smash_status symbolic_impl(smash_ctx c, const smash_csr *A, const smash_csr *B, 
     HIP_TRY(c, hipMemsetAsync(c->d_hdr, 0, sizeof(DevHdr), s));
     if (c->opt[SMASH_OPT_VALIDATE]) {
         TRY(validate_csr(c, s, *A, kErrCsrA, perr(c), p.valid_bm));
-        TRY(validate_csr(c, s, *B, kErrCsrB, perr(c), p.valid_bm));
+        if (!same_csr(*A, *B)) TRY(validate_csr(c, s, *B, kErrCsrB, perr(c), p.valid_bm));   // A * A: once
     }
     if (m == 0) {
         HIP_TRY(c, hipMemsetAsync(C_row_ptr, 0, sizeof(int64_t), s));

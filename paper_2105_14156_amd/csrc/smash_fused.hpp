@@ -179,6 +179,9 @@ __global__ __launch_bounds__(256) void k_fused_mark(int m, const unsigned char *
                                                     const int *__restrict__ nnzc, unsigned char *__restrict__ sym_bin,
                                                     int *fused_ok, unsigned long long *fused_entries, const int *err)
 {
+    // grid-stride over the rows; the block's totals go out with one atomic
+    // per counter (a block per 256 rows would serialise thousands of
+    // atomics on the two counters)
     if (stopped(err)) return;
     __shared__ int s_ok;
     __shared__ unsigned long long s_ent;
@@ -187,14 +190,20 @@ __global__ __launch_bounds__(256) void k_fused_mark(int m, const unsigned char *
         s_ent = 0;
     }
     __syncthreads();
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool done = i < m && fbin[i] != kBinEmpty && status[i] == 1;
-    if (done) sym_bin[i] = kBinEmpty;
-    const unsigned long long b = __ballot(done);
-    const unsigned long long e = wave_sum((unsigned long long)(done ? nnzc[i] : 0));
-    if (lane_id() == 0 && b) {
-        atomicAdd(&s_ok, (int)__popcll(b));
-        atomicAdd(&s_ent, e);
+    int ok = 0;
+    unsigned long long ent = 0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
+        if (fbin[i] != kBinEmpty && status[i] == 1) {
+            sym_bin[i] = kBinEmpty;
+            ++ok;
+            ent += (unsigned long long)nnzc[i];
+        }
+    }
+    ok = wave_sum(ok);
+    ent = wave_sum(ent);
+    if (lane_id() == 0 && ok) {
+        atomicAdd(&s_ok, ok);
+        atomicAdd(&s_ent, ent);
     }
     __syncthreads();
     if (threadIdx.x == 0 && s_ok) {

@@ -2009,13 +2009,16 @@ __device__ __forceinline__ void wave_store_ranked(const double (&vr)[ROUNDS], co
 // its sum is no longer the bit pattern of -0.0 (a sum of terms that are not
 // -0.0 is never -0.0 under round-to-nearest, even when they cancel).  The
 // kernel is persistent: a grid that fills the GPU once takes the dense chunks
-// from a global queue (one atomic per kDenseClaim chunks), so that long and
+// from a global queue (one atomic per `claim` chunks), so that long and
 // short chunks balance across CUs, and each wave puts -0.0 back in its slots once its
 // entries are out, so the array is ready for the next chunk without a
 // separate clearing pass.
 constexpr int kDenseThreads = 512;
-// dense chunks a block claims with one atomic on the queue
+// dense chunks a block claims with one atomic on the queue when every block
+// has many to do (one atomic per chunk from every resident block serialises
+// on the counter); one at a time otherwise, for the balance of the tail
 constexpr int kDenseClaim = 4;
+constexpr int kDenseClaimMinPerBlock = 256;
 constexpr long long kNegZeroBits = (long long)0x8000000000000000ULL;
 
 template <typename V>
@@ -2024,7 +2027,7 @@ __global__ __launch_bounds__(kDenseThreads) void k_num_dense(
     const int *__restrict__ Bcol, const V *__restrict__ Bval, const int *__restrict__ Bsplit, long long per,
     const int *__restrict__ heavy_rows, const Seg *__restrict__ segs, int nchunks,
     const int *__restrict__ woff, const long long *__restrict__ Crp, int *__restrict__ Ccol,
-    V *__restrict__ Cval, int *err, int nseg, int *queue)
+    V *__restrict__ Cval, int *err, int nseg, int *queue, int claim)
 {
     constexpr int NW = kDenseThreads / kWave;
     constexpr int CPW = kChunkCols / NW;              // columns ranked by each wave
@@ -2037,11 +2040,11 @@ __global__ __launch_bounds__(kDenseThreads) void k_num_dense(
     const int gt = threadIdx.x, lane = lane_id(), wg = gt / kWave;
     for (int t = gt; t < kChunkCols; t += kDenseThreads) acc[t] = -0.0;
     for (;;) {
-    if (gt == 0) s_next = atomicAdd(queue, kDenseClaim);
+    if (gt == 0) s_next = atomicAdd(queue, claim);
     __syncthreads();                                    // also: the previous chunk is fully written
     const int first = s_next;
     if (first >= nseg) break;
-    const int last = first + kDenseClaim < nseg ? first + kDenseClaim : nseg;
+    const int last = first + claim < nseg ? first + claim : nseg;
     for (int t = first; t < last; ++t) {
     const Seg sg = segs[t];
     const int lo = sg.c0 * kChunkCols;
