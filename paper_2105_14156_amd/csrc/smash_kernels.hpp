@@ -1275,7 +1275,8 @@ __device__ __forceinline__ void group_bitonic(int *keys, V *vals, int n2, int gt
 // the group calls it.  The columns lie in [lo, lo + ncols).  With ncols at
 // most 64 T the order comes from ranks in an occupancy bitmap over that
 // range built in the table's own LDS; otherwise the entries are compacted
-// and sorted (bitonic).
+// and sorted (bitonic), or, for one wave and at most 64 entries, ranked by
+// counting the smaller columns across the wave's lanes.
 template <int T, int WPR, int SPT>
 __device__ __forceinline__ void order_row_entries(const int (&kr)[SPT], const double (&vr)[SPT], int *keys,
                                                   double *vals, int *s_scan, int total, int wbase, int incl, int cnt,
@@ -1354,6 +1355,26 @@ __device__ __forceinline__ void order_row_entries(const int (&kr)[SPT], const do
                 keys[pos] = kr[s];
                 vals[pos] = vr[s];
                 ++pos;
+            }
+        }
+        if constexpr (WPR == 1) {
+            if (total <= kWave) {
+                // one wave, at most 64 entries: lane l takes entry l, and its
+                // rank is the number of smaller columns, counted over the
+                // wave's lanes (no sorting network, no LDS round trips)
+                wave_sync();
+                const int lane = lane_id();
+                const int k = lane < total ? keys[lane] : 0x7fffffff;
+                const double v = lane < total ? vals[lane] : 0.0;
+                int r = 0;
+                for (int q = 0; q < total; ++q) r += __builtin_amdgcn_readlane(k, q) < k;
+                wave_sync();
+                if (lane < total) {
+                    keys[r] = k;
+                    vals[r] = v;
+                }
+                wave_sync();
+                return;
             }
         }
         const int n2 = total <= 1 ? 1 : (1 << ceil_log2(total));
