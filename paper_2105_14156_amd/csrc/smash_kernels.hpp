@@ -55,6 +55,7 @@ constexpr int kChunkCols = 8192;        // column granularity of heavy-row count
 constexpr int kChunkWords = kChunkCols / 32;
 constexpr int kSymWinChunks = 16;       // symbolic heavy window: 16 chunks, 16 KiB bitmap
 constexpr int kSegCap = 1024;           // entries of one hashed segment (table of 2048 slots)
+constexpr int kSegMerge = 600;          // chunks are merged into one segment up to this many entries
 constexpr int kSegMaxSpan = 8;          // chunks spanned by one hashed segment
 constexpr int kSegBins = 4;             // hashed segments with <=128, <=700, <=1024 entries; dense chunks
 constexpr int kSegDense = 3;
@@ -1768,8 +1769,10 @@ __global__ __launch_bounds__(256) void k_chunk_prefix(const BinHdr *sh, int nchu
 
 // Cuts every heavy row into segments (one thread per heavy row): a chunk
 // with more than kSegCap columns is a dense segment of its own; otherwise
-// consecutive chunks are merged while the count stays <= kSegCap and the
-// span <= kSegMaxSpan chunks.  Pass 0 counts segments per block and bin;
+// consecutive chunks are merged while the count stays <= kSegMerge and the
+// span <= kSegMaxSpan chunks (a single chunk of up to kSegCap entries is a
+// segment of its own: smaller merged segments keep more of them in the
+// 1024-slot tables, which fit more blocks per CU).  Pass 0 counts segments per block and bin;
 // pass 1 writes them at offset[bin] + block base + rank in block.
 __device__ __forceinline__ int seg_bin(int count, bool dense)
 {
@@ -1788,7 +1791,7 @@ __device__ __forceinline__ void plan_row_segments(const int *__restrict__ wc, in
         int sum = 0, last = c;
         while (c < nchunks && c - start < kSegMaxSpan) {
             const int n = wc[c];
-            if (n > kSegCap || sum + n > kSegCap) break;
+            if (n > kSegCap || (sum + n > kSegMerge && sum > 0)) break;
             sum += n;
             if (n) last = c;
             ++c;
