@@ -414,7 +414,9 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": committed_traffic(name, dname) if args.path == "plain" and args.dtype == "f32" else None,
                      "launches_per_step": launches_per_step, "avg_launch_ms": round(avg_ms, 4),
-                     "alg_bytes_per_launch": int(per_launch_bytes), "c_entry_share": round(share, 4)},
+                     "alg_bytes_per_launch": int(per_launch_bytes), "c_entry_share": round(share, 4),
+                     "alg_bytes_basis": "apportioned: the path's compulsory bytes (A, B, C once) times the "
+                                        "kernel's share of C's entries, per launch"},
         "kernel_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in kt.items() if v[0]},
         "stats": st,
         "ms_median": round(float(np.median(step_ms)), 4),
