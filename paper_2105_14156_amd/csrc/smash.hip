@@ -151,14 +151,20 @@ struct Pending {
 
 }  // namespace
 
+// The context's device header and the numeric error word after it, in one
+// allocation (and one pinned host mirror), so one copy reads both.
+constexpr size_t kNumErrOffset = (sizeof(DevHdr) + 15) & ~size_t(15);
+constexpr size_t kHdrBytes = kNumErrOffset + 16;
+
 struct smash_ctx_s {
     int device = 0;
     std::string err;
     int64_t opt[SMASH_OPT_COUNT] = {1, 1024, 0, 0, 0, 0, 0};
     DevHdr *h_hdr = nullptr;   // pinned host mirror
     DevHdr *d_hdr = nullptr;
-    int *d_numerr = nullptr;   // flags of numeric calls (kept until smash_sync or a symbolic call reads them)
-    int *h_numerr = nullptr;   // pinned host mirror
+    int *d_numerr = nullptr;   // flags of numeric calls (kept until smash_sync or a symbolic call reads them);
+                               // right after the header, so one copy reads both
+    int *h_numerr = nullptr;   // pinned host mirror, likewise after h_hdr
     Arena mlp_mem, pred_mem;
     bool has_predictor = false;
     float pred_delta = 0.f;
@@ -604,8 +610,7 @@ smash_status run_fused_bins(smash_ctx c, hipStream_t s, const Plan &p)
 // waits: the one synchronisation of a symbolic call.
 smash_status read_hdr(smash_ctx c, hipStream_t s)
 {
-    HIP_TRY(c, hipMemcpyAsync(c->h_hdr, c->d_hdr, sizeof(DevHdr), hipMemcpyDeviceToHost, s));
-    HIP_TRY(c, hipMemcpyAsync(c->h_numerr, c->d_numerr, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipMemcpyAsync(c->h_hdr, c->d_hdr, kNumErrOffset + sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipStreamSynchronize(s));
     collect_times(c);
     return SMASH_OK;
@@ -717,24 +722,19 @@ smash_status smash_create(smash_ctx *out, int device)
     if (!c) return SMASH_ERR_OUT_OF_MEMORY;
     c->device = device;
     DeviceGuard g(device);
-    if (!g.ok || hipHostMalloc((void **)&c->h_hdr, sizeof(DevHdr), hipHostMallocDefault) != hipSuccess) {
+    if (!g.ok || hipHostMalloc((void **)&c->h_hdr, kHdrBytes, hipHostMallocDefault) != hipSuccess) {
         delete c;
         return SMASH_ERR_HIP;
     }
-    if (hipHostMalloc((void **)&c->h_numerr, sizeof(int), hipHostMallocDefault) != hipSuccess) {
-        (void)hipHostFree(c->h_hdr);
-        delete c;
-        return SMASH_ERR_HIP;
-    }
-    if (hipMalloc((void **)&c->d_hdr, sizeof(DevHdr)) != hipSuccess ||
-        hipMalloc((void **)&c->d_numerr, sizeof(int)) != hipSuccess ||
-        hipMemset(c->d_numerr, 0, sizeof(int)) != hipSuccess) {
+    c->h_numerr = (int *)((char *)c->h_hdr + kNumErrOffset);
+    if (hipMalloc((void **)&c->d_hdr, kHdrBytes) != hipSuccess ||
+        hipMemset(c->d_hdr, 0, kHdrBytes) != hipSuccess) {
         if (c->d_hdr) (void)hipFree(c->d_hdr);
         (void)hipHostFree(c->h_hdr);
-        (void)hipHostFree(c->h_numerr);
         delete c;
         return SMASH_ERR_OUT_OF_MEMORY;
     }
+    c->d_numerr = (int *)((char *)c->d_hdr + kNumErrOffset);
     memset(c->h_hdr, 0, sizeof(DevHdr));
     *c->h_numerr = 0;
     if (device < kMaxDevices) {
@@ -744,9 +744,7 @@ smash_status smash_create(smash_ctx *out, int device)
             if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
                 (void)hipGetLastError();
                 (void)hipFree(c->d_hdr);
-                (void)hipFree(c->d_numerr);
                 (void)hipHostFree(c->h_hdr);
-                (void)hipHostFree(c->h_numerr);
                 delete c;
                 return SMASH_ERR_HIP;
             }
@@ -767,10 +765,8 @@ void smash_destroy(smash_ctx c)
     DeviceGuard g(c->device);
     for (Arena *a : {&c->mlp_mem, &c->pred_mem})
         if (a->ptr) (void)hipFree(a->ptr);
-    if (c->d_hdr) (void)hipFree(c->d_hdr);
-    if (c->d_numerr) (void)hipFree(c->d_numerr);
-    if (c->h_hdr) (void)hipHostFree(c->h_hdr);
-    if (c->h_numerr) (void)hipHostFree(c->h_numerr);
+    if (c->d_hdr) (void)hipFree(c->d_hdr);      // holds d_numerr too
+    if (c->h_hdr) (void)hipHostFree(c->h_hdr);  // holds h_numerr too
     for (auto &p : c->pending) {
         (void)hipEventDestroy(p.a);
         (void)hipEventDestroy(p.b);
