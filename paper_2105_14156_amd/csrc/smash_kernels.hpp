@@ -1499,11 +1499,11 @@ __device__ __forceinline__ void num_row(int e0, int e1, const int *__restrict__ 
             bl = Brp[k + 1] - bs;
             a = Aval[e];
         };
-        auto sink = [&](const int (&j)[4], const double (&p)[4], const bool (&ok)[4]) {
-            if constexpr (HASH == 1) lds_insert_add_ord_u<4>(keys, vals, LOGT, shift, j, p, ok, s_maxd, err);
-            else lds_insert_add_u<4>(keys, vals, LOGT, j, p, ok, err);
+        auto sink = [&](const int (&j)[2], const double (&p)[2], const bool (&ok)[2]) {
+            if constexpr (HASH == 1) lds_insert_add_ord_u<2>(keys, vals, LOGT, shift, j, p, ok, s_maxd, err);
+            else lds_insert_add_u<2>(keys, vals, LOGT, j, p, ok, err);
         };
-        group_products<V, true, G, 4, decltype(get), decltype(sink), true>(e0, e1, gt, en, Bcol, Bval, get, sink);
+        group_products<V, true, G, 2, decltype(get), decltype(sink), true>(e0, e1, gt, en, Bcol, Bval, get, sink);
     }
     group_sync<WPR>();
     if constexpr (HASH == 1) {
@@ -1935,10 +1935,12 @@ __global__ __launch_bounds__(THREADS) void k_num_seg(
         bl = split1[k * per] - bs;
         a = Aval[e];
     };
-    auto sink = [&](const int (&j)[2], const double (&p)[2], const bool (&ok)[2]) {
-        lds_insert_add_u<2>(keys, vals, LOGT, j, p, ok, err);
+    // one product per thread in flight: the segment kernels are bound by how
+    // many blocks fit a CU, and fewer registers per thread let more in
+    auto sink = [&](const int (&j)[1], const double (&p)[1], const bool (&ok)[1]) {
+        lds_insert_add_u<1>(keys, vals, LOGT, j, p, ok, err);
     };
-    group_products<V, true, THREADS, 2, decltype(get), decltype(sink), true>(sg.e0, sg.e1, gt, S, Bcol, Bval, get,
+    group_products<V, true, THREADS, 1, decltype(get), decltype(sink), true>(sg.e0, sg.e1, gt, S, Bcol, Bval, get,
                                                                             sink);
     __syncthreads();
     int kr[SPT];
