@@ -128,10 +128,10 @@ __global__ __launch_bounds__(kWave *WPR *RPW) void k_fused_rows(
             bl = Brp[k + 1] - bs;
             a = Aval[e];
         };
-        auto sink = [&](const int (&j)[4], const double (&p)[4], const bool (&ok)[4]) {
-            lds_bounded_insert_add_u<4>(keys, vals, LOGT, j, p, ok, cap, &s_ndist[g], &s_full[g]);
+        auto sink = [&](const int (&j)[2], const double (&p)[2], const bool (&ok)[2]) {
+            lds_bounded_insert_add_u<2>(keys, vals, LOGT, j, p, ok, cap, &s_ndist[g], &s_full[g]);
         };
-        group_products<V, true, G, 4, decltype(get), decltype(sink), true>(Arp[row], Arp[row + 1], gt, s_en[g], Bcol,
+        group_products<V, true, G, 2, decltype(get), decltype(sink), true>(Arp[row], Arp[row + 1], gt, s_en[g], Bcol,
                                                                             Bval, get, sink);
     }
     group_sync<WPR>();

@@ -1199,8 +1199,8 @@ __device__ __forceinline__ void sym_row(int e0, int e1, const int *__restrict__ 
             bs = Brp[k];
             bl = Brp[k + 1] - bs;
         };
-        auto sink = [&](const int (&j)[4], const bool (&ok)[4]) { mine += lds_insert_key_u<4>(keys, LOGT, j, ok, err); };
-        group_products<float, false, G, 4, decltype(get), decltype(sink), true>(e0, e1, gt, en, Bcol,
+        auto sink = [&](const int (&j)[2], const bool (&ok)[2]) { mine += lds_insert_key_u<2>(keys, LOGT, j, ok, err); };
+        group_products<float, false, G, 2, decltype(get), decltype(sink), true>(e0, e1, gt, en, Bcol,
                                                                                 (const float *)nullptr, get, sink);
     }
     mine = wave_sum(mine);
