@@ -339,7 +339,7 @@ __global__ __launch_bounds__(kWideThreads) void k_bsym_wide(const BatchDesc *__r
         for (int t = gt; t < nw; t += kWideThreads) s_bmw[t] = 0u;
         if (gt == 0) s_cnt = 0;
         __syncthreads();
-        group_products<float, false, kWideThreads, 4>(
+        group_products<float, false, kWideThreads, 2>(
             d.Arp[arow], d.Arp[arow + 1], gt, S, d.Bcol, (const float *)nullptr,
             [&](int e, int &bs, int &bl, float &) {
                 const int k = Acol[e];
@@ -419,7 +419,7 @@ __global__ __launch_bounds__(kWideThreads) void k_bnum_wide(const BatchDesc *__r
             const int nxt = single && gt < e1 - e0 ? lower_bound_col(d.Bcol, cur, bend, hi) : 0;
             for (int t = gt; t < kWideWin; t += kWideThreads) acc[t] = -0.0;
             __syncthreads();
-            group_products<V, true, kWideThreads, 4>(
+            group_products<V, true, kWideThreads, 2>(
                 e0, e1, gt, S, d.Bcol, (const V *)d.Bval,
                 [&](int e, int &bs, int &bl, V &a) {
                     if (single) {                          // e is this thread's entry
