@@ -33,8 +33,11 @@ __global__ __launch_bounds__(256) void k_fused_bins(int m, const long long *__re
 
 // Like lds_insert_add_u, but a row stops inserting once it holds more
 // distinct columns than its capacity (*ndist counts them, *abort is
-// raised): the table then stays at most about half full, so probes stay
-// short however wrong the prediction was.
+// raised): the table then stays at most about half full (plus one wave
+// step of keys), so probes stay short however wrong the prediction was.
+// The wave's new keys are counted with ballots and added to *ndist by one
+// lane (one LDS atomic per wave step instead of one per new key, all on
+// the same address).  Every lane of the wave calls it.
 template <int U>
 __device__ __forceinline__ void lds_bounded_insert_add_u(int *keys, double *vals, int logT, const int (&j)[U],
                                                          const double (&p)[U], const bool (&okin)[U], int cap,
@@ -48,22 +51,24 @@ __device__ __forceinline__ void lds_bounded_insert_add_u(int *keys, double *vals
     for (int u = 0; u < U; ++u) h[u] = slot_of(j[u], logT);
 #pragma unroll
     for (int u = 0; u < U; ++u) old[u] = okin[u] ? atomicCAS(&keys[h[u]], kEmpty, j[u]) : j[u];
+    bool fresh[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
+        fresh[u] = false;
         if (!okin[u]) continue;
         unsigned hh = h[u];
         int cur = old[u];
         for (unsigned probe = 0;; ++probe) {
             if (cur == kEmpty) {                    // claimed a new slot
                 atomicAdd(&vals[hh], p[u]);
-                if (atomicAdd(ndist, 1) >= cap) atomicExch(abort, 1);
+                fresh[u] = true;
                 break;
             }
             if (cur == j[u]) {
                 atomicAdd(&vals[hh], p[u]);
                 break;
             }
-            if (probe >= mask) {                    // unreachable while cap <= T / 2
+            if (probe >= mask) {                    // table full: only after a wrong prediction
                 atomicExch(abort, 1);
                 break;
             }
@@ -71,6 +76,10 @@ __device__ __forceinline__ void lds_bounded_insert_add_u(int *keys, double *vals
             cur = atomicCAS(&keys[hh], kEmpty, j[u]);
         }
     }
+    int added = 0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) added += __popcll(__ballot(fresh[u]));
+    if (lane_id() == 0 && added > 0 && atomicAdd(ndist, added) + added > cap) atomicExch(abort, 1);
 }
 
 // Fused rows: products merged in an LDS table of 2^LOGT slots; a row whose

@@ -1277,11 +1277,13 @@ __device__ __forceinline__ void group_bitonic(int *keys, V *vals, int n2, int gt
 // most 64 T the order comes from ranks in an occupancy bitmap over that
 // range built in the table's own LDS; otherwise the entries are compacted
 // and sorted (bitonic), or, for one wave and at most 64 entries, ranked by
-// counting the smaller columns across the wave's lanes.
+// counting the smaller columns across the wave's lanes.  Only that second
+// form reads total, cnt, incl and wbase.  Returns the number of entries:
+// the bitmap's count, or total.
 template <int T, int WPR, int SPT>
-__device__ __forceinline__ void order_row_entries(const int (&kr)[SPT], const double (&vr)[SPT], int *keys,
-                                                  double *vals, int *s_scan, int total, int wbase, int incl, int cnt,
-                                                  int ncols, int gt, int lo = 0)
+__device__ __forceinline__ int order_row_entries(const int (&kr)[SPT], const double (&vr)[SPT], int *keys,
+                                                 double *vals, int *s_scan, int total, int wbase, int incl, int cnt,
+                                                 int ncols, int gt, int lo = 0)
 {
     constexpr int G = WPR * kWave;
     const int lane = lane_id(), wg = gt / kWave;
@@ -1348,6 +1350,7 @@ __device__ __forceinline__ void order_row_entries(const int (&kr)[SPT], const do
                 keys[rk[s]] = kr[s];
                 vals[rk[s]] = vr[s];
             }
+        total = run;
     } else {
         int pos = wbase + incl - cnt;
 #pragma unroll
@@ -1375,7 +1378,7 @@ __device__ __forceinline__ void order_row_entries(const int (&kr)[SPT], const do
                     vals[r] = v;
                 }
                 wave_sync();
-                return;
+                return total;
             }
         }
         const int n2 = total <= 1 ? 1 : (1 << ceil_log2(total));
@@ -1384,6 +1387,7 @@ __device__ __forceinline__ void order_row_entries(const int (&kr)[SPT], const do
         group_bitonic<double, WPR>(keys, vals, n2, gt);
     }
     group_sync<WPR>();
+    return total;
 }
 
 // Write-back of an order-preserving table (the paper's Write-back Phase,
@@ -1952,19 +1956,23 @@ __global__ __launch_bounds__(THREADS) void k_num_seg(
         vr[s] = vals[gt * SPT + s];
         cnt += kr[s] != kEmpty;
     }
-    const int lane = lane_id(), wg = gt / kWave;
-    const int incl = wave_incl_scan(cnt);
-    if (lane == kWave - 1) s_scan[wg] = incl;
-    __syncthreads();
-    int wbase = 0, total = 0;
-    for (int w = 0; w < WPR; ++w) {
-        const int t = s_scan[w];
-        if (w < wg) wbase += t;
-        total += t;
+    int incl = 0, wbase = 0, total = 0;
+    if constexpr (64 * T < kSegMaxSpan * kChunkCols) {
+        // a segment can be too wide for the bitmap ranks, and the sort that
+        // takes it then needs each thread's place among the entries
+        const int lane = lane_id(), wg = gt / kWave;
+        incl = wave_incl_scan(cnt);
+        if (lane == kWave - 1) s_scan[wg] = incl;
+        __syncthreads();
+        for (int w = 0; w < WPR; ++w) {
+            const int t = s_scan[w];
+            if (w < wg) wbase += t;
+            total += t;
+        }
     }
+    total = order_row_entries<T, WPR, SPT>(kr, vr, keys, vals, s_scan, total, wbase, incl, cnt,
+                                           (sg.c1 - sg.c0) * kChunkCols, gt, lo);
     if (gt == 0 && total != sg.count) atomicOr(err, kErrCount);
-    order_row_entries<T, WPR, SPT>(kr, vr, keys, vals, s_scan, total, wbase, incl, cnt,
-                                   (sg.c1 - sg.c0) * kChunkCols, gt, lo);
     const long long out0 = sg.out;
     const int n = total < sg.count ? total : sg.count;
     for (int t = gt; t < n; t += THREADS) {
