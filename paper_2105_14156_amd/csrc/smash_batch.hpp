@@ -446,7 +446,7 @@ __global__ __launch_bounds__(kWideThreads) void k_bnum_wide(const BatchDesc *__r
             for (int q = 0; q < ROUNDS; ++q) {
                 const int jl = wg * CPW + q * kWave + lane;
                 vr[q] = acc[jl];
-                msk[q] = __ballot(__double_as_longlong(vr[q]) != kNegZeroBits);
+                msk[q] = wave_ballot(reached(vr[q]));
                 wcount += __popcll(msk[q]);
             }
             if (lane == 0) s_wt[wg] = wcount;

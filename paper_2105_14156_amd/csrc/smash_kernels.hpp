@@ -1981,9 +1981,26 @@ __global__ __launch_bounds__(THREADS) void k_num_seg(
     }
 }
 
+constexpr long long kNegZeroBits = (long long)0x8000000000000000ULL;
+
+// A slot of a dense window was reached by a product when its sum is no
+// longer the bit pattern of -0.0 (the window starts at -0.0 and every
+// product is added as p + 0.0).
+__device__ __forceinline__ bool reached(double v) { return __double_as_longlong(v) != kNegZeroBits; }
+
+// Mask of the lanes of the wave for which p holds (a compare straight into
+// a scalar register pair, with no 0/1 select in between).
+__device__ __forceinline__ unsigned long long wave_ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+// Number of lanes below this one whose bit is set in m.
+__device__ __forceinline__ int lanes_below(unsigned long long m)
+{
+    return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
 // Stores the entries a wave has ranked in its ROUNDS x 64 slots of a dense
-// window: slot r * 64 + lane holds column col0 + r * 64 + lane, occupied
-// where bit `lane` of msk[r] is set, with value vr[r].  The first n of them,
+// window: slot r * 64 + lane holds column col0 + r * 64 + lane and value
+// vr[r], occupied where reached(vr[r]); msk[r] = wave_ballot(reached(vr[r])).  The first n of them,
 // in column order, go to C[out, out + n): staged in the wave's own LDS slots
 // (whose values are already in registers) and copied with consecutive lanes
 // on consecutive addresses, so stores cover whole cache lines.  FP32 stages
@@ -1995,14 +2012,13 @@ __device__ __forceinline__ void wave_store_ranked(const double (&vr)[ROUNDS], co
                                                   int *__restrict__ Ccol, V *__restrict__ Cval)
 {
     const int lane = lane_id();
-    const unsigned long long below = (1ull << lane) - 1ull;
     int lr = 0;
     if constexpr (sizeof(V) == 4) {
         int2 *st = reinterpret_cast<int2 *>(slots);
 #pragma unroll
         for (int r = 0; r < ROUNDS; ++r) {
-            if ((msk[r] >> lane) & 1ull)
-                st[lr + __popcll(msk[r] & below)] = make_int2(col0 + r * kWave + lane, __float_as_int((float)vr[r]));
+            if (reached(vr[r]))
+                st[lr + lanes_below(msk[r])] = make_int2(col0 + r * kWave + lane, __float_as_int((float)vr[r]));
             lr += __popcll(msk[r]);
         }
         wave_sync();
@@ -2016,7 +2032,7 @@ __device__ __forceinline__ void wave_store_ranked(const double (&vr)[ROUNDS], co
         V *st_val = reinterpret_cast<V *>(slots);
 #pragma unroll
         for (int r = 0; r < ROUNDS; ++r) {
-            if ((msk[r] >> lane) & 1ull) st_col[lr + __popcll(msk[r] & below)] = col0 + r * kWave + lane;
+            if (reached(vr[r])) st_col[lr + lanes_below(msk[r])] = col0 + r * kWave + lane;
             lr += __popcll(msk[r]);
         }
         wave_sync();
@@ -2025,7 +2041,7 @@ __device__ __forceinline__ void wave_store_ranked(const double (&vr)[ROUNDS], co
         lr = 0;
 #pragma unroll
         for (int r = 0; r < ROUNDS; ++r) {
-            if ((msk[r] >> lane) & 1ull) st_val[lr + __popcll(msk[r] & below)] = (V)vr[r];
+            if (reached(vr[r])) st_val[lr + lanes_below(msk[r])] = (V)vr[r];
             lr += __popcll(msk[r]);
         }
         wave_sync();
@@ -2053,7 +2069,6 @@ constexpr int kDenseThreads = 512;
 // on the counter); one at a time otherwise, for the balance of the tail
 constexpr int kDenseClaim = 4;
 constexpr int kDenseClaimMinPerBlock = 256;
-constexpr long long kNegZeroBits = (long long)0x8000000000000000ULL;
 
 template <typename V>
 __global__ __launch_bounds__(kDenseThreads) void k_num_dense(
@@ -2100,7 +2115,7 @@ __global__ __launch_bounds__(kDenseThreads) void k_num_dense(
 #pragma unroll
     for (int r = 0; r < ROUNDS; ++r) {
         vr[r] = acc[wg * CPW + r * kWave + lane];
-        msk[r] = __ballot(__double_as_longlong(vr[r]) != kNegZeroBits);
+        msk[r] = wave_ballot(reached(vr[r]));
         wcount += __popcll(msk[r]);
     }
     if (lane == 0) s_wt[wg] = wcount;
