@@ -98,22 +98,46 @@ __device__ __forceinline__ float mlp_eval(const float *s_w, const float x[kFeat]
     return y;
 }
 
-// Inference (one thread per row): predicted log2(1 + nnz) and, when cap is
-// given, the capacity clamp(ceil(2^(yhat + delta) - 1), max(maxb, 1),
-// min(ub, cols)) (0 for rows without products).  With only_above >= 0 the
-// network is evaluated only for rows whose exact bound min(ub, cols)
-// exceeds it (the rows a prediction can move into the LDS tables); the
-// others get the bound itself, and a block without such rows loads no
-// weights.
+// Capacity of a row from the network's output y: clamp(ceil(2^(y + delta)
+// - 1), max(maxb, 1), min(ub, cols)), 0 for a row without products.
+__device__ __forceinline__ int predicted_capacity(float y, float delta, long long u, int maxb_i, int ncols)
+{
+    if (u <= 0) return 0;
+    const long long hi = u < ncols ? u : ncols;
+    const long long lo = maxb_i > 1 ? maxb_i : 1;
+    float p = exp2f(y + delta) - 1.f;
+    long long c = p < 1.f ? 1 : (p > 2.0e9f ? 2000000000LL : (long long)ceilf(p));
+    c = c < lo ? lo : c;
+    c = c > hi ? hi : c;
+    return (int)c;
+}
+
+// A wave whose candidate rows are at most this many evaluates them one at a
+// time, a hidden unit per lane, instead of a row per lane.
+constexpr int kMlpSparseRows = 8;
+
+// Inference: predicted log2(1 + nnz) and, when cap is given, the capacity
+// (predicted_capacity).  With only_above >= 0 the network is evaluated only
+// for rows whose exact bound min(ub, cols) exceeds it (the rows a
+// prediction can move into the LDS tables); the others get the bound
+// itself, and a block without such rows loads no weights.  A wave with many
+// candidate rows evaluates a row per lane; a wave with few (where the
+// candidates are rare, most lanes of a row-per-lane wave would idle through
+// the whole network) takes them one by one with lane j computing hidden
+// unit j of both layers, reading the other units' values with v_readlane.
+// Both forms add in the same order, so a row's result does not depend on
+// which form evaluated it.
 __global__ __launch_bounds__(256) void k_mlp_predict(int m, int ncols, const float *__restrict__ feats,
                                                      const float *__restrict__ theta, const float *__restrict__ ms,
                                                      float delta, const long long *__restrict__ ub,
                                                      const int *__restrict__ maxb, float *__restrict__ yhat_out,
                                                      int *__restrict__ cap_out, int only_above)
 {
+    static_assert(kHid == kWave, "one hidden unit per lane");
     __shared__ float s_w[kParams];
     __shared__ float s_ms[2 * kFeat];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & (kWave - 1);
     const bool live = i < m;
     const long long ub_i = live && ub ? ub[i] : 0;
     const long long bound = ub_i < ncols ? ub_i : ncols;
@@ -125,29 +149,52 @@ __global__ __launch_bounds__(256) void k_mlp_predict(int m, int ncols, const flo
     load_params(s_w, theta);
     if (threadIdx.x < 2 * kFeat) s_ms[threadIdx.x] = ms[threadIdx.x];
     __syncthreads();
-    if (!live) return;
-    if (!cand) {
-        if (cap_out) cap_out[i] = (int)bound;
+    if (live && !cand && cap_out) cap_out[i] = (int)bound;
+    const unsigned long long cm = __builtin_amdgcn_ballot_w64(cand);
+    if (__popcll(cm) > kMlpSparseRows) {
+        if (!cand) return;
+        float x[kFeat];
+#pragma unroll
+        for (int f = 0; f < kFeat; ++f) x[f] = (feats[(long long)i * kFeat + f] - s_ms[f]) / s_ms[kFeat + f];
+        const float y = mlp_eval(s_w, x, nullptr, nullptr, 0);
+        if (yhat_out) yhat_out[i] = y;
+        if (cap_out) cap_out[i] = predicted_capacity(y, delta, ub[i], maxb[i], ncols);
         return;
     }
-    float x[kFeat];
+    if (!cm) return;
+    // few candidates: lane j is hidden unit j; its rows of W1 and W2 are
+    // read once from the parameters in global memory (a row of W2 in LDS
+    // lies in one bank for every lane)
+    float w1[kFeat], w2[kHid];
 #pragma unroll
-    for (int f = 0; f < kFeat; ++f) x[f] = (feats[(long long)i * kFeat + f] - s_ms[f]) / s_ms[kFeat + f];
-    const float y = mlp_eval(s_w, x, nullptr, nullptr, 0);
-    if (yhat_out) yhat_out[i] = y;
-    if (cap_out) {
-        const long long u = ub[i];
-        int cap = 0;
-        if (u > 0) {
-            const long long hi = u < ncols ? u : ncols;
-            const long long lo = maxb[i] > 1 ? maxb[i] : 1;
-            float p = exp2f(y + delta) - 1.f;
-            long long c = p < 1.f ? 1 : (p > 2.0e9f ? 2000000000LL : (long long)ceilf(p));
-            c = c < lo ? lo : c;
-            c = c > hi ? hi : c;
-            cap = (int)c;
+    for (int f = 0; f < kFeat; ++f) w1[f] = theta[kOW1 + lane * kFeat + f];
+#pragma unroll
+    for (int q = 0; q < kHid; ++q) w2[q] = theta[kOW2 + lane * kHid + q];
+    const float b1 = s_w[kOB1 + lane], b2 = s_w[kOB2 + lane];
+    const int row0 = i - lane;
+    for (unsigned long long mm = cm; mm; mm &= mm - 1) {
+        const int l = __ffsll((long long)mm) - 1;
+        const int r = row0 + l;
+        float x[kFeat];
+#pragma unroll
+        for (int f = 0; f < kFeat; ++f) x[f] = (feats[(long long)r * kFeat + f] - s_ms[f]) / s_ms[kFeat + f];
+        float z = b1;
+#pragma unroll
+        for (int f = 0; f < kFeat; ++f) z = fmaf(w1[f], x[f], z);
+        const float h1 = z > 0.f ? z : 0.f;
+        float z2 = b2;
+#pragma unroll
+        for (int q = 0; q < kHid; ++q)
+            z2 = fmaf(w2[q], __int_as_float(__builtin_amdgcn_readlane(__float_as_int(h1), q)), z2);
+        const float h2 = z2 > 0.f ? z2 : 0.f;
+        float y = s_w[kOB3];
+#pragma unroll
+        for (int q = 0; q < kHid; ++q)
+            y = fmaf(s_w[kOW3 + q], __int_as_float(__builtin_amdgcn_readlane(__float_as_int(h2), q)), y);
+        if (lane == l) {
+            if (yhat_out) yhat_out[r] = y;
+            if (cap_out) cap_out[r] = predicted_capacity(y, delta, ub[r], maxb[r], ncols);
         }
-        cap_out[i] = cap;
     }
 }
 
